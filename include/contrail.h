@@ -1,0 +1,165 @@
+/*
+ * contrail.h -- C ABI of the MI355X (gfx950) finite-volume step of the
+ * non-equilibrium contrail-formation solver of Tegethoff & Wheeler,
+ * "Non-Equilibrium Phase Changes in Aircraft Exhaust" (arXiv 2504.20742).
+ *
+ * The method (Sec. 3.1, Eq. 22-26): dU/dt + div(F^c - F^v) = Q on a 2-D
+ * axisymmetric (x, r) structured mesh, U the 15-component conservation vector
+ * below, F^c a Roe-type flux with MUSCL / van Leer reconstruction, F^v central
+ * viscous + eddy fluxes, Q the per-cell non-equilibrium phase-change source
+ * (Sec. 2.2, Eq. 1-21), advanced by explicit Runge-Kutta with a globally
+ * controlled CFL number and the source evaluated explicitly in every cell at
+ * every stage (Sec. 3.2).
+ *
+ * Conventions for every call
+ *  - Arrays are caller-owned DEVICE pointers (hipMalloc'ed memory or torch CUDA
+ *    tensors), contiguous structure-of-arrays U[15][nr][nx] (x index fastest).
+ *    Element type: double for CP_FP64 contexts, float for CP_MIXED contexts.
+ *    The library never frees caller memory.
+ *  - Component order of U (per m^3):
+ *      0 rho        gas density (dry air + vapour)          Eq. 23
+ *      1 rho u      axial momentum                          Eq. 23
+ *      2 rho v      radial momentum                         Eq. 23
+ *      3 rho E      gas total energy                        Eq. 23
+ *      4 rho Y_v    vapour partial density                  Eq. 25
+ *      5..8         rho mu_k of the droplets, k = 0..3      Eq. 19, 26
+ *      9..12        rho mu_k of the ice crystals, k = 0..3  Eq. 19, 26
+ *      13           soot number density                     Sec. 2.2 (soot at the inflow)
+ *      14           activated soot number density           Sec. 2.2 (heterogeneous nucleation)
+ *  - Every call is ordered on the HIP stream given to cp_create and returns
+ *    without synchronising unless stated.  Status codes are returned, never
+ *    exceptions; cp_error_string gives the last message of a context.
+ *  - Device-side failures (non-finite values written by a stage) are latched in
+ *    a device flag and reported as CP_ENONFINITE by the next synchronising call
+ *    (cp_cfl_dt, cp_step_n, cp_diag).
+ *  - One context per host thread.  Contexts own their workspace (two stage
+ *    buffers, mesh metrics, reduction scalars).
+ */
+#ifndef CONTRAIL_H
+#define CONTRAIL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cp_ctx cp_ctx;
+
+enum cp_status {
+    CP_OK = 0,
+    CP_EINVAL = -1,        /* bad argument (null pointer, size, dt <= 0, ...)       */
+    CP_EHIP = -2,          /* a HIP runtime call failed                             */
+    CP_ENONFINITE = -3,    /* a stage produced a NaN / Inf                          */
+    CP_EDT = -4,           /* time step not positive / not finite                   */
+    CP_ESTATE = -5,        /* call not valid in the context's state                 */
+    CP_ENOMEM = -6,        /* device allocation failed                              */
+    CP_EUNSUPPORTED = -7   /* option not supported                                  */
+};
+
+enum cp_precision {
+    CP_FP64 = 0,           /* FP64 storage and arithmetic                           */
+    CP_MIXED = 1           /* FP32 storage, fluxes and RK update; source in FP64    */
+};
+
+enum cp_qmode {
+    CP_Q_EXACT = 0,        /* sub-cycled exact source (Sec. 2.2, Sec. 3.2)          */
+    CP_Q_SURROGATE = 1,    /* learned MLP source with exact fallback                */
+    CP_Q_OFF = 2           /* no phase change                                       */
+};
+
+enum cp_geom { CP_GEOM_AXI = 0, CP_GEOM_PLANAR = 1 };
+
+/* Boundary treatment per side (Sec. 4.1: inflow streams, far field).
+ *  INFLOW   (x = 0 only): Dirichlet core / bypass / ambient state by radius
+ *  COPY     zero-gradient extrapolation
+ *  WALL     mirror (axis at r = 0, or a slip wall): normal velocity odd
+ *  FARFIELD (r = L_r only): Dirichlet ambient state                             */
+enum cp_bc { CP_BC_INFLOW = 0, CP_BC_COPY = 1, CP_BC_WALL = 2, CP_BC_FARFIELD = 3 };
+
+typedef struct {
+    int nx, nr;            /* cells, both >= 2                                      */
+    double Lx, Lr;         /* domain [0, Lx] x [0, Lr] in metres                    */
+    double sx_ratio;       /* ratio of successive axial widths (1 = uniform)        */
+    double r_cluster;      /* radius the radial cells cluster about (<= 0: uniform) */
+    double beta_r;         /* sinh clustering strength                              */
+    int geom;              /* cp_geom                                               */
+    int bc_xlo, bc_xhi, bc_rlo, bc_rhi;   /* cp_bc per side                         */
+} cp_mesh;
+
+typedef struct {
+    double p_amb, T_amb, RH_ice, mach_amb;  /* ambient: pressure, T, ice RH, flight Ma */
+    double R_core, u_core, T_core, Y_core;  /* core jet (pressure-matched)          */
+    double R_fan, u_byp, T_byp, Y_byp;      /* bypass jet; Y_byp < 0: ambient Y     */
+    double n_soot, r_g_soot, sigma_g_soot;  /* core soot: number, lognormal r_g, s_g */
+    double cfl;                             /* CFL number of the global time step   */
+    double theta_deg;                       /* soot contact angle (Eq. 9)           */
+    double n_s;                             /* active-site density (Eq. 14) [1/m^2] */
+    double k_imm;                           /* immersion-freezing rate scale [1/s]  */
+    double kappa_m, s_delta, delta0_frac;   /* mixing-length eddy viscosity         */
+    int n_sub_max;                          /* cap on source sub-steps (>= 1)       */
+    int phase_change;                       /* 0: Q = 0                             */
+    int pad0, pad1;
+} cp_case;
+
+/* Create a context for one mesh + operating point.  precision: cp_precision.
+ * hip_stream: a hipStream_t (NULL = default stream).  On success *out owns the
+ * workspace; release with cp_destroy.  Errors: CP_EINVAL, CP_ENOMEM, CP_EHIP.    */
+int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_stream, cp_ctx **out);
+void cp_destroy(cp_ctx *ctx);
+
+/* Initial state (Sec. 4.1 streams): the inflow profile (core for r < R_core,
+ * bypass for r < R_fan, ambient beyond) extended uniformly in x, at rest radially.  */
+int cp_init(cp_ctx *ctx, void *U);
+
+/* Transport residual per unit volume (Eq. 22 without Q):
+ *   R = -(1/V) sum_faces (F^c - F^v) . A  +  (p - tau_thetatheta) dx dr / V  on rho v.  */
+int cp_residual(cp_ctx *ctx, const void *U, void *R);
+
+/* Phase-change source integrated over dt (Sec. 2.2 rates, evaluated explicitly per
+ * cell, Sec. 3.2): Q(U, dt) = (Phi_dt(U) - U) / dt, computed in FP64 for both
+ * precisions.  dt > 0, else CP_EDT.                                               */
+int cp_source(cp_ctx *ctx, const void *U, double dt, void *Q);
+
+/* One SSP-RK3 step of size dt, in place: L(U) = R(U) + Q(U, dt).                 */
+int cp_step(cp_ctx *ctx, void *U, double dt);
+
+/* Global CFL time step (Sec. 3.2 "globally controlled CFL number"):
+ *   dt = CFL min_cells 1 / ((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)).
+ * Synchronises the stream and writes *dt_host.                                   */
+int cp_cfl_dt(cp_ctx *ctx, const void *U, double *dt_host);
+
+/* n steps, each with its own CFL time step computed and kept on the device; the
+ * step sequence is a captured HIP graph replayed n times.  Synchronises; writes the
+ * simulated time to *t_host (may be NULL).                                        */
+int cp_step_n(cp_ctx *ctx, void *U, int n, double *t_host);
+
+/* Select how Q is evaluated (cp_qmode).  CP_Q_SURROGATE needs cp_sur_set first.   */
+int cp_set_qmode(cp_ctx *ctx, int qmode);
+
+/* Diagnostics (synchronises): out[0] total water mass per radian
+ * (vapour + 4pi/3 (rho_l M3 + rho_s N3), Eq. 25-26), out[1] max ln S_l (Eq. 1),
+ * out[2] total ice number, out[3] gas mass, out[4] cells with an active source,
+ * out[5] source sub-steps of the last cp_source call, out[6] surrogate cells of the
+ * last stage, out[7] fallback cells of the last stage.                           */
+int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
+
+/* Tile shape of the stage kernel: (tx, ty) from the built set, or (0, 0) to run the
+ * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built.     */
+int cp_set_tile(cp_ctx *ctx, int tx, int ty);
+int cp_get_tile(const cp_ctx *ctx, int *tx, int *ty);
+
+/* Measurement entry point: launch the fused stage kernel `reps` times as the middle
+ * SSP-RK3 stage (reads the stage buffer and U, writes the other stage buffer; U is
+ * not modified) between two HIP events on the context stream; synchronises and
+ * writes the mean duration of one launch in milliseconds.  Uses the current tile
+ * (autotuned first if unset).                                                      */
+int cp_time_stage(cp_ctx *ctx, void *U, int reps, double *ms_per_launch);
+
+/* Mesh faces (host copies): xf[nx+1], rf[nr+1].                                   */
+int cp_mesh_faces(const cp_ctx *ctx, double *xf, double *rf);
+
+const char *cp_error_string(const cp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CONTRAIL_H */

@@ -57,6 +57,7 @@ static const double YOUNG_ALPHA = 11.0;          /* Sec. 2.2 growth kinetics    
 static const double N_MIN = 1.0;                 /* number floor [1/m^3]         */
 static const double SUB_SAFETY = 0.2;            /* sub-step / depletion time     */
 static const double PV_FLOOR = 1.0e-3;           /* Pa, floor of p_v in ln S     */
+static const double R_MIN = 1.0e-10;             /* m: smaller r20 = evaporated   */
 static const double PI = 3.14159265358979323846;
 
 /* --------------------------------------------------------- public structs -- */
@@ -303,7 +304,16 @@ typedef struct {
     double mdot_f;         /* liquid -> ice mass rate                              */
     double Gl, Gs;         /* growth rates at r20                                  */
     double Jhom, Jhet, rcrit, lnSl, lnSi;
+    int stale_l, stale_s;  /* number left without mass: evaporated population      */
 } rates_t;
+
+/* A population with particles (mu0 > N_MIN) is valid while its mean radii
+ * r20 = sqrt(mu2/mu0) and r30 = (mu3/mu0)^(1/3) are at least a molecular radius;
+ * below that it has evaporated (its number has no mass left).                  */
+static int population_valid(const double *m)
+{
+    return m[0] > N_MIN && m[2] > m[0] * R_MIN * R_MIN && m[3] > m[0] * R_MIN * R_MIN * R_MIN;
+}
 
 /* One evaluation of the phase-change rates at state U; h is the sub-step length,
  * which bounds the activation rate so that at most the unactivated soot activates. */
@@ -352,8 +362,10 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
         Jl = Jhom + act;
     }
 
-    const int liquid = (M[0] > N_MIN && M[2] > 0.0);
-    const int ice = (N[0] > N_MIN && N[2] > 0.0);
+    const int liquid = population_valid(M);
+    const int ice = population_valid(N);
+    r->stale_l = (M[0] > N_MIN && !liquid);
+    r->stale_s = (N[0] > N_MIN && !ice);
 
     /* Eq. 16, 21: droplet growth at r20 with the Kelvin factor (1 - r_crit/r) */
     if (liquid) {
@@ -378,7 +390,7 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     }
 
     /* Eq. 12-15: freezing of droplets; moments above mu3 from a lognormal closure */
-    if (T < T_REF && liquid && M[3] > 0.0) {
+    if (T < T_REF && liquid) {
         double l2 = log(M[2] / M[0]), l3 = log(M[3] / M[0]);
         double s2 = 2.0 / 3.0 * l3 - l2;
         if (s2 < 0.0) s2 = 0.0;
@@ -473,7 +485,7 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         double dM[4], dN[4], act = r.act, mdf = r.mdot_f;
         for (int k = 0; k < 4; ++k) { dM[k] = r.dM[k]; dN[k] = r.dN[k]; }
         int evap_l = 0, evap_s = 0;
-        if (r.Gl < 0.0 && U[8] + h * dM[3] <= 0.0) {
+        if (r.stale_l || (r.Gl < 0.0 && U[8] + h * dM[3] <= 0.0)) {
             /* all droplets evaporate within the sub-step: no freezing, soot deactivates */
             evap_l = 1;
             for (int k = 0; k < 4; ++k) {
@@ -483,31 +495,37 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
             mdf = 0.0;
             act = -U[14] / h;
         }
-        if (r.Gs < 0.0 && U[12] + h * dN[3] <= 0.0) {
+        if (r.stale_s || (r.Gs < 0.0 && U[12] + h * dN[3] <= 0.0)) {
             evap_s = 1;
             for (int k = 0; k < 4; ++k) dN[k] = -U[9 + k] / h;
         }
         exchange_terms(U, dM, dN, act, mdf, S);
+        /* positivity scaling; an evaporating population reaches zero at theta = 1 by
+         * construction and is left out of the minimum */
         double theta = 1.0;
-        for (int c = 4; c <= 12; ++c)
+        for (int c = 4; c <= 12; ++c) {
+            if ((evap_l && c >= 5 && c <= 8) || (evap_s && c >= 9)) continue;
             if (S[c] < 0.0) {
                 double t = U[c] / (-h * S[c]);
                 if (t < theta) theta = t;
             }
+        }
         for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];
         if (theta == 1.0) {
             if (evap_l) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
             if (evap_s) { U[9] = U[10] = U[11] = U[12] = 0.0; }
         }
-        /* Hoelder bounds on mu1 given (mu0, mu2, mu3) */
+        /* Hoelder bounds on mu1 given (mu0, mu2, mu3): mu2^2/mu3 <= mu1 <= sqrt(mu0 mu2).
+         * When the interval is empty (an unrealisable (mu0, mu2, mu3) triple) mu1 takes
+         * the upper bound, so the clamp is continuous where the interval degenerates
+         * (monodisperse populations, e.g. freshly nucleated or frozen ones). */
         for (int set = 0; set < 2; ++set) {
             double *m = U + (set ? 9 : 5);
-            if (m[0] > N_MIN && m[2] > 0.0 && m[3] > 0.0) {
+            if (population_valid(m)) {
                 double lo = m[2] * m[2] / m[3], hi = sqrt(m[0] * m[2]);
-                if (lo <= hi) {
-                    if (m[1] < lo) m[1] = lo;
-                    if (m[1] > hi) m[1] = hi;
-                }
+                if (lo > hi) lo = hi;
+                if (m[1] < lo) m[1] = lo;
+                if (m[1] > hi) m[1] = hi;
             }
         }
     }

@@ -1,0 +1,238 @@
+"""ctypes binding of ``libcontrail.so`` (the C ABI of include/contrail.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  Arrays are torch CUDA tensors (or raw device pointers) shaped
+``(15, nr, nx)``; float64 for CP_FP64 contexts, float32 for CP_MIXED contexts.
+Loading fails loudly when the library has not been built -- there is no
+fallback path.
+"""
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcontrail.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "contrail.h")
+
+CP_OK, CP_EINVAL, CP_EHIP, CP_ENONFINITE, CP_EDT, CP_ESTATE, CP_ENOMEM, CP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+CP_FP64, CP_MIXED = 0, 1
+CP_Q_EXACT, CP_Q_SURROGATE, CP_Q_OFF = 0, 1, 2
+NV = 15
+
+_lib = None
+
+
+class ContrailError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("contrail error %d: %s" % (code, msg))
+        self.code = code
+
+
+class CpMesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("nr", ctypes.c_int),
+                ("Lx", ctypes.c_double), ("Lr", ctypes.c_double),
+                ("sx_ratio", ctypes.c_double), ("r_cluster", ctypes.c_double),
+                ("beta_r", ctypes.c_double), ("geom", ctypes.c_int),
+                ("bc_xlo", ctypes.c_int), ("bc_xhi", ctypes.c_int),
+                ("bc_rlo", ctypes.c_int), ("bc_rhi", ctypes.c_int)]
+
+
+_CASE_D = ["p_amb", "T_amb", "RH_ice", "mach_amb", "R_core", "u_core", "T_core", "Y_core",
+           "R_fan", "u_byp", "T_byp", "Y_byp", "n_soot", "r_g_soot", "sigma_g_soot", "cfl",
+           "theta_deg", "n_s", "k_imm", "kappa_m", "s_delta", "delta0_frac"]
+
+
+class CpCase(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in _CASE_D] + [
+        ("n_sub_max", ctypes.c_int), ("phase_change", ctypes.c_int),
+        ("pad0", ctypes.c_int), ("pad1", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_DP = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "cp_create": (_I, [ctypes.POINTER(CpMesh), ctypes.POINTER(CpCase), _I, _P, ctypes.POINTER(_P)]),
+    "cp_destroy": (None, [_P]),
+    "cp_init": (_I, [_P, _P]),
+    "cp_residual": (_I, [_P, _P, _P]),
+    "cp_source": (_I, [_P, _P, _D, _P]),
+    "cp_step": (_I, [_P, _P, _D]),
+    "cp_cfl_dt": (_I, [_P, _P, _DP]),
+    "cp_step_n": (_I, [_P, _P, _I, _DP]),
+    "cp_set_qmode": (_I, [_P, _I]),
+    "cp_diag": (_I, [_P, _P, _DP]),
+    "cp_set_tile": (_I, [_P, _I, _I]),
+    "cp_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "cp_mesh_faces": (_I, [_P, _DP, _DP]),
+    "cp_time_stage": (_I, [_P, _P, _I, _DP]),
+    "cp_error_string": (ctypes.c_char_p, [_P]),
+}
+
+
+def header_functions():
+    """Names of the functions declared in include/contrail.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def load():
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcontrail.so is not built (run paper_2504_20742_amd/build.py or "
+                           "__graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def make_mesh(m):
+    return CpMesh(**{k: m[k] for k, _ in CpMesh._fields_})
+
+
+def make_case(c):
+    d = {k: float(c[k]) for k in _CASE_D}
+    d.update(n_sub_max=int(c["n_sub_max"]), phase_change=int(c["phase_change"]), pad0=0, pad1=0)
+    return CpCase(**d)
+
+
+def _current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Solver:
+    """One mesh + operating point on the GPU (a cp_ctx)."""
+
+    def __init__(self, mesh, case, precision=CP_FP64, stream=None):
+        self.L = load()
+        self.mesh, self.case = dict(mesh), dict(case)
+        self.nx, self.nr = int(mesh["nx"]), int(mesh["nr"])
+        self.precision = precision
+        self._m, self._c = make_mesh(mesh), make_case(case)
+        h = _P()
+        s = _current_stream() if stream is None else stream
+        rc = self.L.cp_create(ctypes.byref(self._m), ctypes.byref(self._c), int(precision), s, ctypes.byref(h))
+        if rc != CP_OK:
+            raise ContrailError(rc, "cp_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != CP_OK:
+            raise ContrailError(rc, self.L.cp_error_string(self.h).decode())
+        return rc
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == CP_FP64 else torch.float32
+
+    def empty(self):
+        import torch
+        return torch.empty((NV, self.nr, self.nx), dtype=self.dtype, device="cuda")
+
+    def _check(self, U):
+        import torch
+        if isinstance(U, torch.Tensor):
+            if U.dtype != self.dtype or not U.is_cuda or not U.is_contiguous() or U.numel() != NV * self.nx * self.nr:
+                raise ValueError("U must be a contiguous CUDA %s tensor of %d elements" % (self.dtype, NV * self.nx * self.nr))
+
+    def init(self, U=None):
+        U = self.empty() if U is None else U
+        self._check(U)
+        self._chk(self.L.cp_init(self.h, _ptr(U)))
+        return U
+
+    def residual(self, U, R=None):
+        R = self.empty() if R is None else R
+        self._check(U)
+        self._check(R)
+        self._chk(self.L.cp_residual(self.h, _ptr(U), _ptr(R)))
+        return R
+
+    def source(self, U, dt, Q=None):
+        Q = self.empty() if Q is None else Q
+        self._check(U)
+        self._check(Q)
+        self._chk(self.L.cp_source(self.h, _ptr(U), float(dt), _ptr(Q)))
+        return Q
+
+    def step(self, U, dt):
+        self._check(U)
+        self._chk(self.L.cp_step(self.h, _ptr(U), float(dt)))
+        return U
+
+    def cfl_dt(self, U):
+        self._check(U)
+        d = ctypes.c_double()
+        self._chk(self.L.cp_cfl_dt(self.h, _ptr(U), ctypes.byref(d)))
+        return d.value
+
+    def step_n(self, U, n):
+        self._check(U)
+        t = ctypes.c_double()
+        self._chk(self.L.cp_step_n(self.h, _ptr(U), int(n), ctypes.byref(t)))
+        return t.value
+
+    def set_qmode(self, q):
+        self._chk(self.L.cp_set_qmode(self.h, int(q)))
+
+    def diag(self, U):
+        self._check(U)
+        out = (ctypes.c_double * 8)()
+        self._chk(self.L.cp_diag(self.h, _ptr(U), out))
+        keys = ["water", "max_lnS_l", "ice_number", "gas_mass", "active_cells", "nsub_total",
+                "surrogate_cells", "fallback_cells"]
+        return dict(zip(keys, list(out)))
+
+    def set_tile(self, tx, ty):
+        self._chk(self.L.cp_set_tile(self.h, int(tx), int(ty)))
+
+    def get_tile(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._chk(self.L.cp_get_tile(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def time_stage(self, U, reps=20):
+        """Mean duration (ms) of one launch of the fused stage kernel."""
+        self._check(U)
+        ms = ctypes.c_double()
+        self._chk(self.L.cp_time_stage(self.h, _ptr(U), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def faces(self):
+        import numpy as np
+        xf = np.zeros(self.nx + 1)
+        rf = np.zeros(self.nr + 1)
+        self._chk(self.L.cp_mesh_faces(self.h, xf.ctypes.data_as(_DP), rf.ctypes.data_as(_DP)))
+        return xf, rf

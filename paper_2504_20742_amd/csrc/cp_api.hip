@@ -1,0 +1,678 @@
+// cp_api.hip -- host runtime and C ABI of the contrail finite-volume step.
+//
+// Owns the per-case state: mesh metrics (Sec. 4.1 axisymmetric mesh, tensor
+// product of a geometrically stretched axial and a sinh-clustered radial
+// distribution), inflow / far-field states, stage buffers, the device-resident
+// time step, the captured step graph and the tile-shape autotuner.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/contrail.h"
+#include "cp_internal.hpp"
+
+using namespace cp;
+
+enum { M_XC, M_RC, M_INV_DXF, M_INV_DRF, M_INV_D2X, M_INV_D2R, M_LM2, M_INV_DX, M_RFA, M_INVV_R, M_INV_RC,
+       M_INV_RF, M_COUNT };
+
+struct cp_ctx {
+    int precision = CP_FP64;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    cp_mesh mesh{};
+    cp_case cs{};
+    int nx = 0, nr = 0;
+    long plane = 0;
+    std::vector<double> xf, rf, xc, rc, dx, dr;     // host mesh
+    std::vector<void *> allocs;                     // device memory owned by the context
+    double *inflow = nullptr, *ambient = nullptr, *vol = nullptr;
+    double *xc_d = nullptr, *rc_d = nullptr, *inv_dx_d = nullptr, *inv_dr_d = nullptr;
+    void *met[M_COUNT] = {};                        // metric arrays in the storage precision
+    void *Ua = nullptr, *Ub = nullptr;
+    double *dt_d = nullptr, *t_d = nullptr, *diag_d = nullptr, *Qsur = nullptr;
+    unsigned long long *acc_d = nullptr, *nsub_d = nullptr;
+    int *flag_d = nullptr;
+    int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
+    SourceParams sp{};
+    int qmode = CP_Q_EXACT;
+    int tx = 0, ty = 0;                             // 0: autotune on first use
+    hipGraphExec_t graph = nullptr;
+    void *graph_U = nullptr;
+    double Y_amb = 0, u_amb = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(cp_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(c, x)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess) return fail((c), CP_EHIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T> T *dalloc(cp_ctx *c, size_t n)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return (T *)p;
+}
+
+// ---------------------------------------------------------------- gas model (host side)
+constexpr double hRa = 287.0, hCpa = 1004.5, hRv = 461.52, hCpv = 1846.08, hTref = 273.15, hLv0 = 2.5008e6;
+double h_R(double Y) { return (1.0 - Y) * hRa + Y * hRv; }
+double h_cp(double Y) { return (1.0 - Y) * hCpa + Y * hCpv; }
+double h_cv(double Y) { return h_cp(Y) - h_R(Y); }
+double h_ln_psat_ice(double T)
+{
+    return -6024.5282 / T + 24.7219 + 1.0613868e-2 * T - 1.3198825e-5 * T * T - 0.49382577 * log(T) + log(100.0);
+}
+
+// Conserved state of a jet or of the free stream: pressure-matched, no radial
+// velocity, no condensate; soot number n_soot.
+void stream_cons(double p, double T, double u, double Y, double nsoot, double *U)
+{
+    const double rho = p / (h_R(Y) * T);
+    const double e = h_cv(Y) * T - (1.0 - Y) * hCpa * hTref + Y * (hLv0 - hCpv * hTref);
+    for (int v = 0; v < NVAR; ++v) U[v] = 0.0;
+    U[0] = rho;
+    U[1] = rho * u;
+    U[3] = rho * (e + 0.5 * u * u);
+    U[4] = rho * Y;
+    U[13] = nsoot;
+}
+
+void build_mesh(cp_ctx *c)
+{
+    const cp_mesh &m = c->mesh;
+    const int nx = m.nx, nr = m.nr;
+    c->xf.assign(nx + 1, 0.0);
+    c->rf.assign(nr + 1, 0.0);
+    for (int i = 0; i <= nx; ++i)
+        c->xf[i] = m.sx_ratio == 1.0 ? m.Lx * i / nx
+                                     : m.Lx * (pow(m.sx_ratio, i) - 1.0) / (pow(m.sx_ratio, nx) - 1.0);
+    c->xf[nx] = m.Lx;
+    if (m.r_cluster > 0.0) {
+        // interior-point clustering: r = D (1 + sinh(b (eta - A)) / sinh(b A))
+        const double b = m.beta_r, D = m.r_cluster, H = m.Lr;
+        const double A = 0.5 / b * log((1.0 + (exp(b) - 1.0) * D / H) / (1.0 + (exp(-b) - 1.0) * D / H));
+        for (int j = 0; j <= nr; ++j) {
+            const double eta = (double)j / nr;
+            c->rf[j] = D * (1.0 + sinh(b * (eta - A)) / sinh(b * A));
+        }
+    } else {
+        for (int j = 0; j <= nr; ++j) c->rf[j] = m.Lr * j / nr;
+    }
+    c->rf[0] = 0.0;
+    c->rf[nr] = m.Lr;
+    c->xc.assign(nx + 4, 0.0);
+    c->rc.assign(nr + 4, 0.0);
+    c->dx.assign(nx, 0.0);
+    c->dr.assign(nr, 0.0);
+    for (int i = 0; i < nx; ++i) {
+        c->dx[i] = c->xf[i + 1] - c->xf[i];
+        c->xc[i + 2] = 0.5 * (c->xf[i] + c->xf[i + 1]);
+    }
+    for (int j = 0; j < nr; ++j) {
+        c->dr[j] = c->rf[j + 1] - c->rf[j];
+        c->rc[j + 2] = 0.5 * (c->rf[j] + c->rf[j + 1]);
+    }
+    for (int g = 0; g < 2; ++g) {   // ghost centres mirrored about the boundary faces
+        c->xc[1 - g] = 2.0 * c->xf[0] - c->xc[2 + g];
+        c->xc[nx + 2 + g] = 2.0 * c->xf[nx] - c->xc[nx + 1 - g];
+        c->rc[1 - g] = 2.0 * c->rf[0] - c->rc[2 + g];
+        c->rc[nr + 2 + g] = 2.0 * c->rf[nr] - c->rc[nr + 1 - g];
+    }
+}
+
+template <class T> int upload_as(cp_ctx *c, const std::vector<double> &h, void **slot)
+{
+    std::vector<T> t(h.begin(), h.end());
+    T *d = dalloc<T>(c, t.size());
+    if (!d) return fail(c, CP_ENOMEM, "metric allocation");
+    HIPCHK(c, hipMemcpy(d, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+    *slot = d;
+    return CP_OK;
+}
+
+template <class R> int upload_metrics(cp_ctx *c)
+{
+    const int nx = c->nx, nr = c->nr;
+    const bool axi = c->mesh.geom == CP_GEOM_AXI;
+    auto XC = [&](int i) { return c->xc[i + 2]; };
+    auto RC = [&](int j) { return c->rc[j + 2]; };
+    std::vector<double> inv_dxf(nx + 1), inv_drf(nr + 1), inv_d2x(nx + 2), inv_d2r(nr + 2), lm2(nx + 2),
+        inv_dx(nx), rfa(nr + 1), invV_r(nr), inv_rc(nr + 2), inv_rf(nr + 1);
+    for (int i = 0; i <= nx; ++i) inv_dxf[i] = 1.0 / (XC(i) - XC(i - 1));
+    for (int j = 0; j <= nr; ++j) inv_drf[j] = 1.0 / (RC(j) - RC(j - 1));
+    const double delta0 = c->cs.delta0_frac * c->cs.R_core;
+    for (int i = -1; i <= nx; ++i) {
+        inv_d2x[i + 1] = 1.0 / (XC(i + 1) - XC(i - 1));
+        const double lm = c->cs.kappa_m * (delta0 + c->cs.s_delta * XC(i));
+        lm2[i + 1] = lm * lm;
+    }
+    for (int j = -1; j <= nr; ++j) {
+        inv_d2r[j + 1] = 1.0 / (RC(j + 1) - RC(j - 1));
+        inv_rc[j + 1] = axi ? 1.0 / RC(j) : 0.0;
+    }
+    for (int i = 0; i < nx; ++i) inv_dx[i] = 1.0 / c->dx[i];
+    for (int j = 0; j <= nr; ++j) {
+        rfa[j] = axi ? c->rf[j] : 1.0;
+        inv_rf[j] = (axi && c->rf[j] > 0.0) ? 1.0 / c->rf[j] : 0.0;
+    }
+    for (int j = 0; j < nr; ++j) invV_r[j] = axi ? 1.0 / (RC(j) * c->dr[j]) : 1.0 / c->dr[j];
+    const std::vector<double> *src[M_COUNT] = {&c->xc, &c->rc, &inv_dxf, &inv_drf, &inv_d2x, &inv_d2r, &lm2,
+                                               &inv_dx, &rfa, &invV_r, &inv_rc, &inv_rf};
+    for (int k = 0; k < M_COUNT; ++k) {
+        int r = upload_as<R>(c, *src[k], &c->met[k]);
+        if (r) return r;
+    }
+    // double copies for the CFL reduction and the diagnostics
+    void *p;
+    int r;
+    if ((r = upload_as<double>(c, c->xc, &p))) return r;
+    c->xc_d = (double *)p;
+    if ((r = upload_as<double>(c, c->rc, &p))) return r;
+    c->rc_d = (double *)p;
+    std::vector<double> idx(nx), idr(nr), vol((size_t)nx * nr);
+    for (int i = 0; i < nx; ++i) idx[i] = 1.0 / c->dx[i];
+    for (int j = 0; j < nr; ++j) idr[j] = 1.0 / c->dr[j];
+    for (int j = 0; j < nr; ++j)
+        for (int i = 0; i < nx; ++i) vol[(size_t)j * nx + i] = (axi ? RC(j) : 1.0) * c->dr[j] * c->dx[i];
+    if ((r = upload_as<double>(c, idx, &p))) return r;
+    c->inv_dx_d = (double *)p;
+    if ((r = upload_as<double>(c, idr, &p))) return r;
+    c->inv_dr_d = (double *)p;
+    if ((r = upload_as<double>(c, vol, &p))) return r;
+    c->vol = (double *)p;
+    return CP_OK;
+}
+
+template <class R> Metrics<R> metrics(const cp_ctx *c)
+{
+    Metrics<R> m;
+    m.xc = (const R *)c->met[M_XC];
+    m.rc = (const R *)c->met[M_RC];
+    m.inv_dxf = (const R *)c->met[M_INV_DXF];
+    m.inv_drf = (const R *)c->met[M_INV_DRF];
+    m.inv_d2x = (const R *)c->met[M_INV_D2X];
+    m.inv_d2r = (const R *)c->met[M_INV_D2R];
+    m.lm2 = (const R *)c->met[M_LM2];
+    m.inv_dx = (const R *)c->met[M_INV_DX];
+    m.rfa = (const R *)c->met[M_RFA];
+    m.invV_r = (const R *)c->met[M_INVV_R];
+    m.inv_rc = (const R *)c->met[M_INV_RC];
+    m.inv_rf = (const R *)c->met[M_INV_RF];
+    return m;
+}
+
+BcInfo bcinfo(const cp_ctx *c)
+{
+    BcInfo b;
+    b.nx = c->nx;
+    b.nr = c->nr;
+    b.geom = c->mesh.geom;
+    b.bc_xlo = c->mesh.bc_xlo;
+    b.bc_xhi = c->mesh.bc_xhi;
+    b.bc_rlo = c->mesh.bc_rlo;
+    b.bc_rhi = c->mesh.bc_rhi;
+    b.inflow = c->inflow;
+    b.ambient = c->ambient;
+    return b;
+}
+
+template <class R>
+StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage, double dt,
+                        const double *dt_dev)
+{
+    StageArgs<R> a;
+    a.Uin = (const R *)Uin;
+    a.Un = (const R *)Un;
+    a.Uout = (R *)Uout;
+    a.dt_dev = dt_dev;
+    a.dt = dt;
+    a.plane = c->plane;
+    a.stage = stage;
+    a.qmode = c->qmode;
+    a.bc = bcinfo(c);
+    a.m = metrics<R>(c);
+    a.sp = c->sp;
+    a.sp.enabled = (c->cs.phase_change != 0 && c->qmode != CP_Q_OFF) ? 1 : 0;
+    a.flag = c->flag_d;
+    a.active_count = c->act_count + (stage < 0 ? 0 : stage);
+    a.active_list = c->act_list;
+    return a;
+}
+
+template <class R>
+SourceFixArgs<R> fix_args(const cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev)
+{
+    SourceFixArgs<R> a;
+    a.Uin = (const R *)Uin;
+    a.Uout = (R *)Uout;
+    a.dt_dev = dt_dev;
+    a.dt = dt;
+    a.plane = c->plane;
+    a.stage = stage;
+    a.count = c->act_count + stage;
+    a.list = c->act_list;
+    a.next_count = c->act_count + (stage + 1) % 3;
+    a.sp = c->sp;
+    a.sp.enabled = 1;
+    a.flag = c->flag_d;
+    a.nsub = c->nsub_d;
+    return a;
+}
+
+int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage, double dt, const double *dt_dev,
+              hipStream_t s)
+{
+    hipError_t e;
+    if (c->precision == CP_FP64)
+        e = launch_stage<double>(stage_args<double>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, s);
+    else
+        e = launch_stage<float>(stage_args<float>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
+    const bool src = stage >= 0 && c->cs.phase_change != 0 && c->qmode != CP_Q_OFF;
+    if (!src) return CP_OK;
+    if (c->precision == CP_FP64)
+        e = launch_source_fix<double>(fix_args<double>(c, Uin, Uout, stage, dt, dt_dev), c->plane, s);
+    else
+        e = launch_source_fix<float>(fix_args<float>(c, Uin, Uout, stage, dt, dt_dev), c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("source launch: ") + hipGetErrorString(e));
+    return CP_OK;
+}
+
+int cfl_any(cp_ctx *c, const void *U, hipStream_t s)
+{
+    hipError_t e;
+    auto fill = [&](auto *tag) {
+        using R = std::remove_pointer_t<decltype(tag)>;
+        CflArgs<R> a;
+        a.U = (const R *)U;
+        a.plane = c->plane;
+        a.bc = bcinfo(c);
+        a.xc = c->xc_d;
+        a.rc = c->rc_d;
+        a.inv_dx = c->inv_dx_d;
+        a.inv_dr = c->inv_dr_d;
+        a.kappa_m = c->cs.kappa_m;
+        a.delta0 = c->cs.delta0_frac * c->cs.R_core;
+        a.s_delta = c->cs.s_delta;
+        a.acc = c->acc_d;
+        return launch_cfl<R>(a, s);
+    };
+    e = c->precision == CP_FP64 ? fill((double *)nullptr) : fill((float *)nullptr);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("cfl launch: ") + hipGetErrorString(e));
+    return CP_OK;
+}
+
+int check_flag(cp_ctx *c)
+{
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, c->flag_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag & 1) return fail(c, CP_ENONFINITE, "a stage wrote a non-finite value");
+    return CP_OK;
+}
+
+// Pick the fastest tile shape for this mesh and precision: time the transport
+// residual (reads U, writes a private buffer) for every built shape.  All shapes give bit-identical
+// results, so the choice only affects speed.
+int autotune(cp_ctx *c, const void *U)
+{
+    if (c->tx) return CP_OK;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = 1e30f;
+    int btx = 32, bty = 8;
+    for (auto &sh : tile_list()) {
+        c->tx = sh.first;
+        c->ty = sh.second;
+        int r = stage_any(c, U, U, c->Ua, -1, 0.0, nullptr, c->stream);
+        if (r) return r;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < 3; ++k) {
+            r = stage_any(c, U, U, c->Ua, -1, 0.0, nullptr, c->stream);
+            if (r) return r;
+        }
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            btx = sh.first;
+            bty = sh.second;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tx = btx;
+    c->ty = bty;
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->flag_d, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    return CP_OK;
+}
+
+int enqueue_step(cp_ctx *c, void *U, double dt, const double *dt_dev, hipStream_t s)
+{
+    int r;
+    if ((r = stage_any(c, U, U, c->Ua, 0, dt, dt_dev, s))) return r;
+    if ((r = stage_any(c, c->Ua, U, c->Ub, 1, dt, dt_dev, s))) return r;
+    return stage_any(c, c->Ub, U, U, 2, dt, dt_dev, s);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_stream, cp_ctx **out)
+{
+    if (!mesh || !cs || !out) return CP_EINVAL;
+    *out = nullptr;
+    if (mesh->nx < 2 || mesh->nr < 2 || !(mesh->Lx > 0) || !(mesh->Lr > 0)) return CP_EINVAL;
+    if (precision != CP_FP64 && precision != CP_MIXED) return CP_EINVAL;
+    if (mesh->geom != CP_GEOM_AXI && mesh->geom != CP_GEOM_PLANAR) return CP_EINVAL;
+    if (mesh->bc_rhi == CP_BC_INFLOW || mesh->bc_xhi == CP_BC_INFLOW || mesh->bc_rlo != CP_BC_WALL) return CP_EINVAL;
+    if (!(mesh->sx_ratio > 0) || cs->n_sub_max < 1 || !(cs->cfl > 0)) return CP_EINVAL;
+    cp_ctx *c = new cp_ctx();
+    c->precision = precision;
+    c->stream = (hipStream_t)hip_stream;
+    c->mesh = *mesh;
+    c->cs = *cs;
+    c->nx = mesh->nx;
+    c->nr = mesh->nr;
+    c->plane = (long)mesh->nx * mesh->nr;
+    build_mesh(c);
+
+    // ambient and inflow states (Sec. 4.1 streams)
+    const double pv = cs->RH_ice * exp(h_ln_psat_ice(cs->T_amb));
+    const double rho_v = pv / (hRv * cs->T_amb), rho_a = (cs->p_amb - pv) / (hRa * cs->T_amb);
+    c->Y_amb = rho_v / (rho_a + rho_v);
+    const double cpA = h_cp(c->Y_amb), RA = h_R(c->Y_amb);
+    c->u_amb = cs->mach_amb * sqrt(cpA / (cpA - RA) * RA * cs->T_amb);
+    std::vector<double> amb(NVAR), inflow((size_t)NVAR * c->nr);
+    stream_cons(cs->p_amb, cs->T_amb, c->u_amb, c->Y_amb, 0.0, amb.data());
+    const double Yb = cs->Y_byp < 0.0 ? c->Y_amb : cs->Y_byp;
+    for (int j = 0; j < c->nr; ++j) {
+        const double r = c->rc[j + 2];
+        double *U = inflow.data() + (size_t)NVAR * j;
+        if (r < cs->R_core) stream_cons(cs->p_amb, cs->T_core, cs->u_core, cs->Y_core, cs->n_soot, U);
+        else if (r < cs->R_fan) stream_cons(cs->p_amb, cs->T_byp, cs->u_byp, Yb, 0.0, U);
+        else for (int v = 0; v < NVAR; ++v) U[v] = amb[v];
+    }
+
+    // phase-change constants evaluated once on the host
+    const double ct = cos(cs->theta_deg * M_PI / 180.0);
+    c->sp.f_theta = 0.25 * (2.0 + ct) * (1.0 - ct) * (1.0 - ct);
+    const double lsg = log(cs->sigma_g_soot);
+    c->sp.het_freeze = cs->k_imm * cs->n_s * (4.0 * M_PI * cs->r_g_soot * cs->r_g_soot * exp(2.0 * lsg * lsg));
+    const double NA = 6.02214076e23, Mw = 0.018015268;
+    c->sp.cnt_const = 1.0 * sqrt(2.0 * NA * NA * NA / (M_PI * Mw * Mw * Mw)) / 1000.0;
+    for (int k = 0; k < 4; ++k) c->sp.ice_ratio[k] = pow(1000.0 / 917.0, k / 3.0);
+    c->sp.n_sub_max = cs->n_sub_max;
+    c->sp.enabled = cs->phase_change ? 1 : 0;
+
+    int r = CP_OK;
+    auto bail = [&](int code) {
+        std::string msg = c->err;
+        cp_destroy(c);
+        return code;
+    };
+    if (!c->stream) {
+        // graph capture needs a non-null stream; the context still launches on the
+        // caller's stream
+    }
+    if (hipStreamCreate(&c->cap_stream) != hipSuccess) return bail(CP_EHIP);
+    const size_t esz = precision == CP_FP64 ? sizeof(double) : sizeof(float);
+    c->inflow = dalloc<double>(c, inflow.size());
+    c->ambient = dalloc<double>(c, NVAR);
+    c->Ua = dalloc<char>(c, esz * NVAR * c->plane);
+    c->Ub = dalloc<char>(c, esz * NVAR * c->plane);
+    c->dt_d = dalloc<double>(c, 1);
+    c->t_d = dalloc<double>(c, 1);
+    c->diag_d = dalloc<double>(c, 8);
+    c->acc_d = dalloc<unsigned long long>(c, 1);
+    c->nsub_d = dalloc<unsigned long long>(c, 1);
+    c->flag_d = dalloc<int>(c, 1);
+    c->act_count = dalloc<int>(c, 4);
+    c->act_list = dalloc<int>(c, c->plane);
+    if (!c->act_count || !c->act_list ||!c->inflow || !c->ambient || !c->Ua || !c->Ub || !c->dt_d || !c->t_d || !c->diag_d || !c->acc_d ||
+        !c->nsub_d || !c->flag_d)
+        return bail(CP_ENOMEM);
+    if (hipMemcpy(c->inflow, inflow.data(), inflow.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->ambient, amb.data(), NVAR * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(CP_EHIP);
+    r = precision == CP_FP64 ? upload_metrics<double>(c) : upload_metrics<float>(c);
+    if (r) return bail(r);
+    if (hipMemset(c->flag_d, 0, sizeof(int)) != hipSuccess || hipMemset(c->t_d, 0, sizeof(double)) != hipSuccess ||
+        hipMemset(c->nsub_d, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->act_count, 0, 4 * sizeof(int)) != hipSuccess)
+        return bail(CP_EHIP);
+    if (launch_acc_reset(c->acc_d, c->stream) != hipSuccess) return bail(CP_EHIP);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(CP_EHIP);
+    *out = c;
+    return CP_OK;
+}
+
+void cp_destroy(cp_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    for (void *p : c->allocs)
+        if (p) hipFree(p);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int cp_init(cp_ctx *c, void *U)
+{
+    if (!c || !U) return fail(c, CP_EINVAL, "null argument");
+    hipError_t e = c->precision == CP_FP64 ? launch_init<double>((double *)U, c->inflow, c->nx, c->nr, c->stream)
+                                           : launch_init<float>((float *)U, c->inflow, c->nx, c->nr, c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    return CP_OK;
+}
+
+int cp_residual(cp_ctx *c, const void *U, void *R)
+{
+    if (!c || !U || !R) return fail(c, CP_EINVAL, "null argument");
+    if (U == R) return fail(c, CP_EINVAL, "U and R must not alias");
+    if (!c->tx) {
+        c->tx = 32;
+        c->ty = 8;
+    }
+    return stage_any(c, U, U, R, -1, 0.0, nullptr, c->stream);
+}
+
+int cp_source(cp_ctx *c, const void *U, double dt, void *Q)
+{
+    if (!c || !U || !Q) return fail(c, CP_EINVAL, "null argument");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, CP_EDT, "dt must be positive and finite");
+    SourceParams sp = c->sp;
+    sp.enabled = (c->cs.phase_change != 0 && c->qmode != CP_Q_OFF) ? 1 : 0;
+    HIPCHK(c, hipMemsetAsync(c->nsub_d, 0, sizeof(unsigned long long), c->stream));
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_source<double>((const double *)U, (double *)Q, c->plane, c->plane, dt, sp, c->nsub_d,
+                                               c->stream)
+                       : launch_source<float>((const float *)U, (float *)Q, c->plane, c->plane, dt, sp, c->nsub_d,
+                                              c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    return CP_OK;
+}
+
+int cp_step(cp_ctx *c, void *U, double dt)
+{
+    if (!c || !U) return fail(c, CP_EINVAL, "null argument");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, CP_EDT, "dt must be positive and finite");
+    int r = autotune(c, U);
+    if (r) return r;
+    return enqueue_step(c, U, dt, nullptr, c->stream);
+}
+
+int cp_cfl_dt(cp_ctx *c, const void *U, double *dt_host)
+{
+    if (!c || !U || !dt_host) return fail(c, CP_EINVAL, "null argument");
+    int r = cfl_any(c, U, c->stream);
+    if (r) return r;
+    hipError_t e = launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, nullptr, c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    HIPCHK(c, hipMemcpyAsync(dt_host, c->dt_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if ((r = check_flag(c))) return r;
+    if (!(*dt_host > 0.0) || !isfinite(*dt_host)) return fail(c, CP_EDT, "CFL time step not positive");
+    return CP_OK;
+}
+
+int cp_step_n(cp_ctx *c, void *U, int n, double *t_host)
+{
+    if (!c || !U || n < 0) return fail(c, CP_EINVAL, "bad argument");
+    int r = autotune(c, U);
+    if (r) return r;
+    if (!c->graph || c->graph_U != U) {
+        if (c->graph) {
+            hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        hipGraph_t g;
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        r = cfl_any(c, U, c->cap_stream);
+        if (!r && launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) != hipSuccess)
+            r = fail(c, CP_EHIP, "finalize launch");
+        if (!r) r = enqueue_step(c, U, 0.0, c->dt_d, c->cap_stream);
+        hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+        if (r) return r;
+        if (ec != hipSuccess) return fail(c, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
+        HIPCHK(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+        hipGraphDestroy(g);
+        c->graph_U = U;
+    }
+    HIPCHK(c, hipMemsetAsync(c->t_d, 0, sizeof(double), c->stream));
+    for (int k = 0; k < n; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    double t = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&t, c->t_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if ((r = check_flag(c))) return r;
+    if (t_host) *t_host = t;
+    return CP_OK;
+}
+
+int cp_set_qmode(cp_ctx *c, int qmode)
+{
+    if (!c) return CP_EINVAL;
+    if (qmode == CP_Q_SURROGATE) return fail(c, CP_EUNSUPPORTED, "surrogate source not loaded");
+    if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF) return fail(c, CP_EINVAL, "bad qmode");
+    c->qmode = qmode;
+    if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return CP_OK;
+}
+
+int cp_diag(cp_ctx *c, const void *U, double out[8])
+{
+    if (!c || !U || !out) return fail(c, CP_EINVAL, "null argument");
+    HIPCHK(c, hipMemsetAsync(c->diag_d, 0, 8 * sizeof(double), c->stream));
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_diag<double>((const double *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->stream)
+                       : launch_diag<float>((const float *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    double h[8];
+    unsigned long long ns = 0;
+    HIPCHK(c, hipMemcpyAsync(h, c->diag_d, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&ns, c->nsub_d, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
+    int r = check_flag(c);
+    if (r) return r;
+    unsigned long long key;
+    memcpy(&key, &h[1], 8);
+    unsigned long long bits = (key & 0x8000000000000000ull) ? (key & 0x7FFFFFFFFFFFFFFFull) : ~key;
+    memcpy(&h[1], &bits, 8);
+    for (int k = 0; k < 5; ++k) out[k] = h[k];
+    out[5] = (double)ns;
+    out[6] = 0.0;
+    out[7] = 0.0;
+    return CP_OK;
+}
+
+int cp_set_tile(cp_ctx *c, int tx, int ty)
+{
+    if (!c) return CP_EINVAL;
+    if (tx == 0 && ty == 0) {
+        c->tx = c->ty = 0;
+    } else if (!tile_supported(tx, ty)) {
+        return fail(c, CP_EUNSUPPORTED, "tile shape not built");
+    } else {
+        c->tx = tx;
+        c->ty = ty;
+    }
+    if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return CP_OK;
+}
+
+int cp_get_tile(const cp_ctx *c, int *tx, int *ty)
+{
+    if (!c || !tx || !ty) return CP_EINVAL;
+    *tx = c->tx;
+    *ty = c->ty;
+    return CP_OK;
+}
+
+int cp_time_stage(cp_ctx *c, void *U, int reps, double *ms)
+{
+    if (!c || !U || !ms || reps < 1) return fail(c, CP_EINVAL, "bad argument");
+    int r = autotune(c, U);
+    if (r) return r;
+    // the middle stage reads a valid state: copy U into the first stage buffer
+    const size_t bytes = (size_t)NVAR * c->plane * (c->precision == CP_FP64 ? 8 : 4);
+    HIPCHK(c, hipMemcpyAsync(c->Ua, U, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const double dt = 1e-12;
+    StageArgs<double> ad = stage_args<double>(c, c->Ua, U, c->Ub, 1, dt, nullptr);
+    StageArgs<float> af = stage_args<float>(c, c->Ua, U, c->Ub, 1, dt, nullptr);
+    ad.sp.enabled = af.sp.enabled = 0;   // keep the active list untouched
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k) {
+        hipError_t e = c->precision == CP_FP64 ? launch_stage<double>(ad, c->tx, c->ty, c->stream)
+                                               : launch_stage<float>(af, c->tx, c->ty, c->stream);
+        if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    }
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return check_flag(c);
+}
+
+int cp_mesh_faces(const cp_ctx *c, double *xf, double *rf)
+{
+    if (!c || !xf || !rf) return CP_EINVAL;
+    memcpy(xf, c->xf.data(), sizeof(double) * (c->nx + 1));
+    memcpy(rf, c->rf.data(), sizeof(double) * (c->nr + 1));
+    return CP_OK;
+}
+
+const char *cp_error_string(const cp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

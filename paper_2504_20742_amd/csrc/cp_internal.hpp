@@ -1,0 +1,91 @@
+// cp_internal.hpp -- library-internal types shared by the kernels and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "cp_physics.hpp"
+
+namespace cp {
+
+// Mesh metrics as 1-D device arrays (tensor-product mesh).  Ghost-bearing arrays
+// are offset so that index i (or j) = -2 .. n+1 maps to element i+2.
+template <class R> struct Metrics {
+    const R *xc, *rc;          // n+4 centres (mirrored ghosts)
+    const R *inv_dxf;          // nx+1: 1/(xc[i] - xc[i-1]) for the face i-1/2, i = 0..nx
+    const R *inv_drf;          // nr+1
+    const R *inv_d2x;          // nx+2: 1/(xc[i+1] - xc[i-1]) for i = -1..nx   (index i+1)
+    const R *inv_d2r;          // nr+2
+    const R *lm2;              // nx+2: mixing length squared at xc[i], i = -1..nx
+    const R *inv_dx;           // nx
+    const R *rfa;              // nr+1: r-face area per unit axial length (r_f, or 1 planar)
+    const R *invV_r;           // nr: 1 / (r_c dr)  (1/dr planar)
+    const R *inv_rc;           // nr+2: 1 / r_c for j = -1..nr (0 planar)  (index j+1)
+    const R *inv_rf;           // nr+1: 1 / r_f (0 at the axis and for planar)
+};
+
+struct BcInfo {
+    int nx, nr, geom, bc_xlo, bc_xhi, bc_rlo, bc_rhi;
+    const double *inflow;      // nr x 15
+    const double *ambient;     // 15
+};
+
+template <class R> struct StageArgs {
+    const R *Uin;              // stencil input U^(s-1)
+    const R *Un;               // U^n for the RK combination (stages 2, 3)
+    R *Uout;
+    const double *dt_dev;      // device time step (graph path) or null
+    double dt;
+    long plane;
+    int stage;                 // 0, 1, 2: SSP-RK3 stage; -1: write R/V only
+    int qmode;
+    BcInfo bc;
+    Metrics<R> m;
+    SourceParams sp;
+    int *flag;                 // bit 0: non-finite output
+    int *active_count;         // cells appended to active_list by this stage
+    int *active_list;          // cells whose phase-change source may be non-zero
+};
+
+template <class R> struct SourceFixArgs {
+    const R *Uin;              // stage input U^(s-1): the source is evaluated here
+    R *Uout;                   // stage output, updated in place
+    const double *dt_dev;
+    double dt;
+    long plane;
+    int stage;
+    const int *count, *list;   // active cells of this stage
+    int *next_count;           // counter of the next stage, cleared here (or null)
+    SourceParams sp;
+    int *flag;
+    unsigned long long *nsub;  // running total of sub-steps (or null)
+};
+
+template <class R> struct CflArgs {
+    const R *U;
+    long plane;
+    BcInfo bc;
+    const double *xc, *rc;     // double centres (offset 2)
+    const double *inv_dx, *inv_dr;
+    double kappa_m, delta0, s_delta;
+    unsigned long long *acc;   // running min of the per-cell limit (bits of a positive double)
+};
+
+struct Ctx;   // host context (cp_api.hip)
+
+// launchers (cp_kernels.hip)
+template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s);
+template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
+template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s);
+hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
+hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s);
+template <class R> hipError_t launch_source(const R *U, R *Q, long n, long plane, double dt, const SourceParams &sp,
+                                            unsigned long long *nsub, hipStream_t s);
+template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, hipStream_t s);
+template <class R> hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol,
+                                          double *out, hipStream_t s);
+bool tile_supported(int tx, int ty);
+const std::vector<std::pair<int, int>> &tile_list();
+
+}  // namespace cp

@@ -1,0 +1,623 @@
+// cp_kernels.hip -- HIP kernels of the contrail finite-volume step for gfx950.
+//
+// k_stage: one fused SSP-RK3 stage per launch.  A block owns a TX x TY tile of
+// cells; the tile plus a 2-cell halo is staged in LDS as gas primitives (the
+// MUSCL stencil of Sec. 3.2 is 2 cells wide), so every primitive, viscosity and
+// eddy viscosity is computed once per tile cell.  The eleven per-mass scalars
+// (vapour excluded) are then streamed through one LDS slot each, upwinded with
+// the Roe mass flux.  The RK combination is fused into the epilogue, so a stage
+// reads U^(s-1) (+ U^n) and writes U^(s) once: a coalesced structure-of-arrays
+// stream.  Cells where the phase-change source (Sec. 2.2) can act are appended to
+// a compacted list; k_source_fix integrates the stiff source for those cells
+// only, which keeps the register footprint of the stencil kernel small.
+#include "cp_internal.hpp"
+
+namespace cp {
+
+constexpr int kAmbient = INT32_MIN;
+
+// Source location of cell (i, j), i in [-2, nx+1], j in [-2, nr+1]:
+//   code >= 0          interior element j*nx + i
+//   code == kAmbient   far-field ambient state
+//   code <  0          inflow state of row (-1 - code)
+// fu / fv: negate the axial / radial momentum (mirror boundaries).
+struct CellSrc {
+    int code;
+    bool fu, fv;
+};
+
+__device__ __forceinline__ CellSrc map_cell(int i, int j, const BcInfo &b)
+{
+    CellSrc s{0, false, false};
+    while (j < 0 || j >= b.nr) {
+        if (j < 0) {
+            j = -1 - j;
+            s.fv = !s.fv;
+        } else if (b.bc_rhi == 3) {
+            s.code = kAmbient;
+            return s;
+        } else if (b.bc_rhi == 2) {
+            j = 2 * b.nr - 1 - j;
+            s.fv = !s.fv;
+        } else {
+            j = b.nr - 1;
+        }
+    }
+    while (i < 0 || i >= b.nx) {
+        if (i < 0) {
+            if (b.bc_xlo == 0) {
+                s.code = -1 - j;
+                return s;
+            }
+            if (b.bc_xlo == 2) {
+                i = -1 - i;
+                s.fu = !s.fu;
+            } else {
+                i = 0;
+            }
+        } else if (b.bc_xhi == 2) {
+            i = 2 * b.nx - 1 - i;
+            s.fu = !s.fu;
+        } else {
+            i = b.nx - 1;
+        }
+    }
+    s.code = j * b.nx + i;
+    return s;
+}
+
+template <class R>
+__device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int code, int v)
+{
+    if (code >= 0) return U[v * plane + code];
+    if (code == kAmbient) return (R)b.ambient[v];
+    return (R)b.inflow[(-1 - code) * NVAR + v];
+}
+
+// ------------------------------------------------------------------ stage
+template <class R, int TX, int TY> struct Tile {
+    static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
+    R rho[N], u[N], v[N], p[N], T[N], Y[N], mu[N], D[N], mut[N], phi[N];
+    int code[N];
+};
+
+// Gas part of the flux through the face between LDS cells a and a+s (s = normal
+// stride, ts = tangential stride).  F = (F^c - F^v) on rho, rho u, rho v, rho E,
+// rho Y in global components; Fm = Roe mass flux; kd = eddy diffusivity / dn for the
+// passive scalars.
+template <class R, class TileT>
+__device__ __forceinline__ void gas_face(const TileT &t, int a, int s, int ts, bool xdir, R inv_dn, R inv_d2t,
+                                         R inv_r, R *F, R &Fm, R &kd)
+{
+    const int b = a + s;
+    const int c0 = a - s, c3 = b + s;
+    const R *un_ = xdir ? t.u : t.v;
+    const R *ut_ = xdir ? t.v : t.u;
+    R qL[5], qR[5];
+    {
+        const int ix[4] = {c0, a, b, c3};
+        R q[5][4];
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            q[0][k] = t.rho[ix[k]];
+            q[1][k] = un_[ix[k]];
+            q[2][k] = ut_[ix[k]];
+            q[3][k] = t.p[ix[k]];
+            q[4][k] = t.Y[ix[k]];
+        }
+        #pragma unroll
+        for (int w = 0; w < 5; ++w) {
+            R d0 = q[w][1] - q[w][0], d1 = q[w][2] - q[w][1], d2 = q[w][3] - q[w][2];
+            qL[w] = q[w][1] + R(0.5) * van_leer(d0, d1);
+            qR[w] = q[w][2] - R(0.5) * van_leer(d1, d2);
+        }
+    }
+    R Fc[4];
+    roe_flux(qL, qR, Fc);
+    Fm = Fc[0];
+    const R FY = Fm * (Fm >= R(0) ? qL[4] : qR[4]);
+
+    // central viscous + eddy flux
+    const R mu = R(0.5) * (t.mu[a] + t.mu[b]);
+    const R mut = R(0.5) * (t.mut[a] + t.mut[b]);
+    const R rho = R(0.5) * (t.rho[a] + t.rho[b]);
+    const R cpf = R(0.5) * (gas_cp(t.Y[a]) + gas_cp(t.Y[b]));
+    const R Df = R(0.5) * (t.D[a] + t.D[b]);
+    const R dhf = R(kLv0) + R(kCpv - kCpa) * (R(0.5) * (t.T[a] + t.T[b]) - R(kTref));
+    const R uf = R(0.5) * (t.u[a] + t.u[b]), vf = R(0.5) * (t.v[a] + t.v[b]);
+    const R un_n = (un_[b] - un_[a]) * inv_dn;
+    const R ut_n = (ut_[b] - ut_[a]) * inv_dn;
+    const R dT_n = (t.T[b] - t.T[a]) * inv_dn;
+    const R dY_n = (t.Y[b] - t.Y[a]) * inv_dn;
+    const R dut_t = R(0.5) * ((ut_[a + ts] - ut_[a - ts]) + (ut_[b + ts] - ut_[b - ts])) * inv_d2t;
+    const R dun_t = R(0.5) * ((un_[a + ts] - un_[a - ts]) + (un_[b + ts] - un_[b - ts])) * inv_d2t;
+    const R div = un_n + dut_t + vf * inv_r;
+    const R mue = mu + mut;
+    const R tnn = mue * (R(2) * un_n - R(2.0 / 3.0) * div);
+    const R tnt = mue * (ut_n + dun_t);
+    const R diffY = rho * Df + mut * R(1.0 / kSct);
+    const R Jv = -diffY * dY_n;
+    const R qn = -(cpf * mu * R(1.0 / kPr) + cpf * mut * R(1.0 / kPrT)) * dT_n + dhf * Jv;
+    F[0] = Fm;
+    if (xdir) {
+        F[1] = Fc[1] - tnn;
+        F[2] = Fc[2] - tnt;
+        F[3] = Fc[3] - (uf * tnn + vf * tnt - qn);
+    } else {
+        F[1] = Fc[2] - tnt;
+        F[2] = Fc[1] - tnn;
+        F[3] = Fc[3] - (uf * tnt + vf * tnn - qn);
+    }
+    F[4] = FY + Jv;
+    kd = mut * R(1.0 / kSct) * inv_dn;
+}
+
+// Flux divergence per unit volume from face fluxes, evaluated without contraction
+// so that equal opposite faces cancel exactly (free-stream / closed-box symmetry).
+template <class R> __device__ __forceinline__ R assemble_x(R fe, R fw, R idx)
+{
+#pragma clang fp contract(off)
+    return -(fe - fw) * idx;
+}
+
+template <class R> __device__ __forceinline__ R assemble_r(R rx, R fn, R an, R fs, R as, R ivr)
+{
+#pragma clang fp contract(off)
+    return rx - (fn * an - fs * as) * ivr;
+}
+
+// Passive scalar flux through a face: upwind MUSCL value times the mass flux
+// minus eddy diffusion.
+template <class R>
+__device__ __forceinline__ R scalar_face(const R *phi, int a, int s, R Fm, R kd)
+{
+    const R q0 = phi[a - s], q1 = phi[a], q2 = phi[a + s], q3 = phi[a + 2 * s];
+    const R d0 = q1 - q0, d1 = q2 - q1, d2 = q3 - q2;
+    const R up = Fm >= R(0) ? q1 + R(0.5) * van_leer(d0, d1) : q2 - R(0.5) * van_leer(d1, d2);
+    return Fm * up - kd * d1;
+}
+
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
+{
+    using TileT = Tile<R, TX, TY>;
+    constexpr int EX = TileT::EX, NE = TileT::N, NT = TX * TY;
+    __shared__ TileT t;
+    const BcInfo &bc = a.bc;
+    const Metrics<R> &m = a.m;
+    const int nx = bc.nx, nr = bc.nr;
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+
+    // phase 1: gas primitives, viscosity, vapour diffusivity of tile + halo
+    for (int e = tid; e < NE; e += NT) {
+        const int ex = e % EX, ey = e / EX;
+        const int i = min(i0 + ex - 2, nx + 1), j = min(j0 + ey - 2, nr + 1);
+        const CellSrc cs = map_cell(i, j, bc);
+        const R U0 = fetch(a.Uin, a.plane, bc, cs.code, 0);
+        R U1 = fetch(a.Uin, a.plane, bc, cs.code, 1);
+        R U2 = fetch(a.Uin, a.plane, bc, cs.code, 2);
+        const R U3 = fetch(a.Uin, a.plane, bc, cs.code, 3);
+        const R U4 = fetch(a.Uin, a.plane, bc, cs.code, 4);
+        if (cs.fu) U1 = -U1;
+        if (cs.fv) U2 = -U2;
+        const R ir = R(1) / U0;
+        const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
+        const R eint = U3 * ir - R(0.5) * (u * u + v * v);
+        const R T = gas_T(eint, Y);
+        const R p = U0 * gas_R(Y) * T;
+        t.code[e] = cs.code;
+        t.rho[e] = U0;
+        t.u[e] = u;
+        t.v[e] = v;
+        t.Y[e] = Y;
+        t.T[e] = T;
+        t.p[e] = p;
+        t.mu[e] = sutherland(T);
+        t.D[e] = R(kD0) * exp(R(kDexp) * log(T * R(1.0 / kTref))) * (R(kP0) / p);
+    }
+    __syncthreads();
+    // phase 2: eddy viscosity mu_t = rho l^2 |du/dr + dv/dx| on tile + 1 ring
+    for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
+        const int ex = e % (TX + 2) + 1, ey = e / (TX + 2) + 1;
+        const int l = ey * EX + ex;
+        const int i = min(i0 + ex - 2, nx), j = min(j0 + ey - 2, nr);
+        const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
+        const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
+        t.mut[l] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
+    }
+    __syncthreads();
+
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool valid = i < nx && j < nr;
+    const int l = (ty + 2) * EX + tx + 2;
+    const bool axi = bc.geom == 0;
+
+    R res[NVAR];
+    R Fm0 = R(0), Fm1 = R(0), Fm2 = R(0), Fm3 = R(0), kd0 = R(0), kd1 = R(0), kd2 = R(0), kd3 = R(0);
+    if (valid) {
+        R Fw[5], Fs[5] = {R(0), R(0), R(0), R(0), R(0)};
+        const R idx = m.inv_dx[i], ivr = m.invV_r[j], as = m.rfa[j], an = m.rfa[j + 1];
+        // faces one at a time (west, east, south, north) to bound register use; the
+        // divergence is formed from face differences as -(Fe-Fw)/dx - (Fn An - Fs As)/V
+        // without contraction, so identical faces cancel exactly
+        #pragma unroll 1
+        for (int f = 0; f < 4; ++f) {
+            if (f == 2 && axi && j == 0) continue;   // the axis face has zero area
+            const bool xd = f < 2;
+            const int la = f == 0 ? l - 1 : (f == 2 ? l - EX : l);
+            const R inv_dn = f == 0 ? m.inv_dxf[i] : f == 1 ? m.inv_dxf[i + 1] : f == 2 ? m.inv_drf[j] : m.inv_drf[j + 1];
+            const R inv_d2t = xd ? m.inv_d2r[j + 1] : m.inv_d2x[i + 1];
+            const R inv_r = xd ? m.inv_rc[j + 1] : (f == 2 ? m.inv_rf[j] : m.inv_rf[j + 1]);
+            R F[5], fm, kdv;
+            gas_face<R>(t, la, xd ? 1 : EX, xd ? EX : 1, xd, inv_dn, inv_d2t, inv_r, F, fm, kdv);
+            if (f == 0) {
+                Fm0 = fm; kd0 = kdv;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) Fw[k] = F[k];
+            } else if (f == 1) {
+                Fm1 = fm; kd1 = kdv;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) res[k] = assemble_x(F[k], Fw[k], idx);
+            } else if (f == 2) {
+                Fm2 = fm; kd2 = kdv;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) Fs[k] = F[k];
+            } else {
+                Fm3 = fm; kd3 = kdv;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], F[k], an, Fs[k], as, ivr);
+            }
+        }
+        if (axi) {   // (p - tau_thetatheta) / r_c on radial momentum
+            const R ir = m.inv_rc[j + 1];
+            const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
+            const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
+            const R vr = t.v[l] * ir;
+            const R mue = t.mu[l] + t.mut[l];
+            const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
+            res[2] += (t.p[l] - ttt) * ir;
+        }
+    }
+    // phase 3: passive scalars, one LDS slot each
+    for (int s = 5; s < NVAR; ++s) {
+        __syncthreads();
+        for (int e = tid; e < NE; e += NT) t.phi[e] = fetch(a.Uin, a.plane, bc, t.code[e], s) / t.rho[e];
+        __syncthreads();
+        if (valid) {
+            const R fw = scalar_face(t.phi, l - 1, 1, Fm0, kd0);
+            const R fe = scalar_face(t.phi, l, 1, Fm1, kd1);
+            const R fs = (axi && j == 0) ? R(0) : scalar_face(t.phi, l - EX, EX, Fm2, kd2);
+            const R fn = scalar_face(t.phi, l, EX, Fm3, kd3);
+            res[s] = assemble_r(assemble_x(fe, fw, m.inv_dx[i]), fn, m.rfa[j + 1], fs, m.rfa[j], m.invV_r[j]);
+        }
+    }
+    if (!valid) return;
+
+    // phase 4: SSP-RK3 combination with the transport residual.  Cells whose
+    // phase-change source can be non-zero are appended to the active list; the
+    // source kernel adds b dt Q(U^(s-1), dt) to them (the stage is linear in L).
+    const long c = (long)j * nx + i;
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    bool bad = false;
+    if (a.stage < 0) {
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            a.Uout[v * a.plane + c] = res[v];
+            bad |= !isfinite(res[v]);
+        }
+    } else {
+        const R rdt = (R)dt;
+        if (a.sp.enabled) {
+            double Ug[NVAR];
+            #pragma unroll
+            for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)a.Uin[v * a.plane + c] : 0.0;
+            CellThermo th;
+            cell_thermo(Ug, th);
+            if (!source_inactive(Ug, th.T)) {
+                const int slot = atomicAdd(a.active_count, 1);
+                if (slot < a.plane) a.active_list[slot] = (int)c;
+            }
+        }
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            const R ui = a.Uin[v * a.plane + c];
+            const R L = res[v];
+            R out;
+            if (a.stage == 0) {
+                out = ui + rdt * L;
+            } else {
+                const R un = a.Un[v * a.plane + c];
+                out = a.stage == 1 ? R(0.75) * un + R(0.25) * (ui + rdt * L)
+                                   : R(1.0 / 3.0) * un + R(2.0 / 3.0) * (ui + rdt * L);
+            }
+            a.Uout[v * a.plane + c] = out;
+            bad |= !isfinite(out);
+        }
+    }
+    if (bad) atomicOr(a.flag, 1);
+}
+
+// Phase-change source of the listed cells: U^(s) += b dt Q(U^(s-1), dt), b the
+// weight of L in the stage (1, 1/4, 2/3).  Q is evaluated in FP64.  Clears the
+// list counter of the next stage.
+template <class R>
+__global__ void __launch_bounds__(256) k_source_fix(SourceFixArgs<R> a)
+{
+    const int n = (int)min((long)*a.count, a.plane);
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    const double b = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
+    int ns = 0;
+    bool bad = false;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const long c = a.list[k];
+        double Ud[NVAR], Q[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
+        ns += source_integrate(Ud, dt, a.sp, Q);
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            R out = a.Uout[v * a.plane + c] + (R)(b * dt * Q[v]);
+            a.Uout[v * a.plane + c] = out;
+            bad |= !isfinite(out);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
+    if (bad) atomicOr(a.flag, 1);
+    for (int o = 32; o > 0; o >>= 1) ns += __shfl_xor(ns, o, 64);
+    if ((threadIdx.x & 63) == 0 && ns && a.nsub) atomicAdd(a.nsub, (unsigned long long)ns);
+}
+
+// ------------------------------------------------------------------ CFL
+// Per-cell limit 1/((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)), written
+// without contraction so that the FP64 result is reproducible operation by
+// operation; the block minimum is merged with an unsigned 64-bit atomic min (the
+// bit patterns of positive doubles order like the values).
+struct PrimD {
+    double rho, u, v, T, Y;
+};
+
+template <class R>
+__device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &bc, int i, int j)
+{
+#pragma clang fp contract(off)
+    const CellSrc cs = map_cell(i, j, bc);
+    PrimD w;
+    const double U0 = (double)fetch(U, plane, bc, cs.code, 0);
+    double U1 = (double)fetch(U, plane, bc, cs.code, 1);
+    double U2 = (double)fetch(U, plane, bc, cs.code, 2);
+    const double U3 = (double)fetch(U, plane, bc, cs.code, 3);
+    const double U4 = (double)fetch(U, plane, bc, cs.code, 4);
+    if (cs.fu) U1 = -U1;
+    if (cs.fv) U2 = -U2;
+    w.rho = U0;
+    w.u = U1 / U0;
+    w.v = U2 / U0;
+    w.Y = U4 / U0;
+    const double e = U3 / U0 - 0.5 * (w.u * w.u + w.v * w.v);
+    const double cv = (1.0 - w.Y) * kCva + w.Y * kCvv;
+    w.T = (e + (1.0 - w.Y) * kCpa * kTref - w.Y * (kLv0 - kCpv * kTref)) / cv;
+    return w;
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_cfl(CflArgs<R> a)
+{
+#pragma clang fp contract(off)
+    const BcInfo &bc = a.bc;
+    const int n = bc.nx * bc.nr;
+    double best = __builtin_huge_val();
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const int i = c % bc.nx, j = c / bc.nx;
+        const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
+        const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
+        const double vE = cfl_prim(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim(a.U, a.plane, bc, i - 1, j).v;
+        const double dudr = (uN - uS) / (a.rc[j + 3] - a.rc[j + 1]);
+        const double dvdx = (vE - vW) / (a.xc[i + 3] - a.xc[i + 1]);
+        const double lm = a.kappa_m * (a.delta0 + a.s_delta * a.xc[i + 2]);
+        const double mut = w.rho * lm * lm * fabs(dudr + dvdx);
+        const double Rm = (1.0 - w.Y) * kRa + w.Y * kRv;
+        const double cpm = (1.0 - w.Y) * kCpa + w.Y * kCpv;
+        const double cvm = (1.0 - w.Y) * kCva + w.Y * kCvv;
+        const double gam = cpm / cvm;
+        const double snd = sqrt(gam * Rm * w.T);
+        const double t = w.T / kTref;
+        const double mu = kMu0 * t * sqrt(t) * (kTref + kSuth) / (w.T + kSuth);
+        double fac = gam / kPr;
+        if (fac < 4.0 / 3.0) fac = 4.0 / 3.0;
+        const double nu = (mu + mut) / w.rho * fac;
+        const double idx = a.inv_dx[i], idr = a.inv_dr[j];
+        const double rate = (fabs(w.u) + snd) * idx + (fabs(w.v) + snd) * idr + 2.0 * nu * (idx * idx + idr * idr);
+        const double d = 1.0 / rate;
+        if (d < best) best = d;
+    }
+    // wavefront min (64 lanes) then block min through LDS
+    for (int o = 32; o > 0; o >>= 1) best = fmin(best, __shfl_xor(best, o, 64));
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = part[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmin(b, part[k]);
+        if (b > 0.0) atomicMin(a.acc, (unsigned long long)__double_as_longlong(b));
+        else atomicMin(a.acc, 0ull);   // non-positive limit: dt collapses to 0 (reported as CP_EDT)
+    }
+}
+
+__global__ void k_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t)
+{
+#pragma clang fp contract(off)
+    const double m = __longlong_as_double((long long)*acc);
+    const double d = cfl * m;
+    *dt = d;
+    if (t) *t = *t + d;
+    *acc = 0x7FF0000000000000ull;   // +inf for the next reduction
+}
+
+__global__ void k_acc_reset(unsigned long long *acc) { *acc = 0x7FF0000000000000ull; }
+
+// ------------------------------------------------------------------ source
+template <class R>
+__global__ void __launch_bounds__(256) k_source(const R *U, R *Q, long n, long plane, double dt, SourceParams sp,
+                                                unsigned long long *nsub)
+{
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int ns = 0;
+    if (c < n) {
+        double Ud[NVAR], Qd[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
+        ns = source_integrate(Ud, dt, sp, Qd);
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Q[v * plane + c] = (R)Qd[v];
+    }
+    for (int o = 32; o > 0; o >>= 1) ns += __shfl_xor(ns, o, 64);
+    if ((threadIdx.x & 63) == 0 && ns) atomicAdd(nsub, (unsigned long long)ns);
+}
+
+// ------------------------------------------------------------------ init
+template <class R>
+__global__ void __launch_bounds__(256) k_init(R *U, const double *inflow, int nx, int nr)
+{
+    const long n = (long)nx * nr;
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int j = (int)(c / nx);
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) U[v * n + c] = (R)inflow[j * NVAR + v];
+}
+
+// ------------------------------------------------------------------ diagnostics
+template <class R>
+__global__ void __launch_bounds__(256) k_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out)
+{
+    const long n = (long)nx * nr;
+    double w = 0.0, ice = 0.0, gas = 0.0, act = 0.0, lnS = -__builtin_huge_val();
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
+        double Ud[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
+        const double V = vol[c];
+        w += V * (Ud[4] + kFourThirdsPi * (kRhoL * Ud[8] + kRhoS * Ud[12]));
+        ice += V * Ud[9];
+        gas += V * Ud[0];
+        CellThermo th;
+        cell_thermo(Ud, th);
+        double pv = fmax(Ud[4] * kRv * th.T, kPvFloor);
+        lnS = fmax(lnS, log(pv) - ln_psat(kSonW, th.T));
+        act += source_inactive(Ud, th.T) ? 0.0 : 1.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        w += __shfl_xor(w, o, 64);
+        ice += __shfl_xor(ice, o, 64);
+        gas += __shfl_xor(gas, o, 64);
+        act += __shfl_xor(act, o, 64);
+        lnS = fmax(lnS, __shfl_xor(lnS, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(out + 0, w);
+        atomicAdd(out + 2, ice);
+        atomicAdd(out + 3, gas);
+        atomicAdd(out + 4, act);
+        // max of ln S through an order-preserving integer map of the double
+        long long b = __double_as_longlong(lnS);
+        unsigned long long key = b >= 0 ? ((unsigned long long)b | 0x8000000000000000ull) : ~(unsigned long long)b;
+        atomicMax((unsigned long long *)(out + 1), key);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static const std::vector<std::pair<int, int>> kTiles = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}};
+
+const std::vector<std::pair<int, int>> &tile_list() { return kTiles; }
+
+bool tile_supported(int tx, int ty)
+{
+    for (auto &p : kTiles)
+        if (p.first == tx && p.second == ty) return true;
+    return false;
+}
+
+template <class R, int TX, int TY>
+static hipError_t stage_launch(const StageArgs<R> &a, hipStream_t s)
+{
+    dim3 grid((a.bc.nx + TX - 1) / TX, (a.bc.nr + TY - 1) / TY);
+    hipLaunchKernelGGL((k_stage<R, TX, TY>), grid, dim3(TX * TY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s)
+{
+    if (tx == 32 && ty == 8) return stage_launch<R, 32, 8>(a, s);
+    if (tx == 16 && ty == 16) return stage_launch<R, 16, 16>(a, s);
+    if (tx == 64 && ty == 4) return stage_launch<R, 64, 4>(a, s);
+    if (tx == 32 && ty == 4) return stage_launch<R, 32, 4>(a, s);
+    if (tx == 16 && ty == 8) return stage_launch<R, 16, 8>(a, s);
+    return hipErrorInvalidValue;
+}
+
+template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
+{
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
+    hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s)
+{
+    const long n = (long)a.bc.nx * a.bc.nr;
+    int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_cfl<R>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cfl_finalize, dim3(1), dim3(1), 0, s, acc, cfl, dt, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_acc_reset, dim3(1), dim3(1), 0, s, acc);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_source(const R *U, R *Q, long n, long plane, double dt, const SourceParams &sp,
+                         unsigned long long *nsub, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_source<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, Q, n, plane, dt, sp, nsub);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, hipStream_t s)
+{
+    const long n = (long)nx * nr;
+    hipLaunchKernelGGL((k_init<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, inflow, nx, nr);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out, hipStream_t s)
+{
+    const long n = (long)nx * nr;
+    int blocks = (int)std::min<long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL((k_diag<R>), dim3(blocks), dim3(256), 0, s, U, plane, nx, nr, vol, out);
+    return hipGetLastError();
+}
+
+#define CP_INSTANTIATE(R)                                                                                   \
+    template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, hipStream_t);                        \
+    template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
+    template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \
+    template hipError_t launch_source<R>(const R *, R *, long, long, double, const SourceParams &,           \
+                                         unsigned long long *, hipStream_t);                                  \
+    template hipError_t launch_init<R>(R *, const double *, int, int, hipStream_t);                           \
+    template hipError_t launch_diag<R>(const R *, long, int, int, const double *, double *, hipStream_t);
+
+CP_INSTANTIATE(double)
+CP_INSTANTIATE(float)
+
+}  // namespace cp

@@ -1,0 +1,400 @@
+// cp_physics.hpp -- device functions of the contrail finite-volume step (gfx950).
+//
+// Gas model, phase-change rates and the sub-cycled source of Tegethoff & Wheeler
+// (arXiv 2504.20742), Sec. 2.2 (Eq. 1-21) and Sec. 3.1 (Eq. 22-26); Roe flux,
+// MUSCL / van Leer and central viscous fluxes of Sec. 3.2.  Flux helpers are
+// templated on the arithmetic type (double for the FP64 path, float for the mixed
+// path); the phase-change source is always evaluated in double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cp {
+
+constexpr int NVAR = 15;
+
+// -------------------------------------------------------------- constants
+// Calorically perfect carrier: dry-air pseudo-component (78/21/1 % N2/O2/Ar of the
+// paper's free stream, diatomic) + water vapour (triatomic); reference 273.15 K.
+constexpr double kTref = 273.15;
+constexpr double kRa = 287.0, kCpa = 1004.5;
+constexpr double kRv = 461.52, kCpv = 1846.08;
+constexpr double kCva = kCpa - kRa, kCvv = kCpv - kRv;
+constexpr double kGv = 4.0 / 3.0;
+constexpr double kCl = 4218.0, kCi = 2106.0;
+constexpr double kLv0 = 2.5008e6, kLs0 = 2.8345e6;
+constexpr double kRhoL = 1000.0, kRhoS = 917.0;
+constexpr double kKb = 1.380649e-23;
+constexpr double kPr = 0.71, kPrT = 0.9, kPrV = 1.0, kSct = 0.7;
+constexpr double kMu0 = 1.716e-5, kSuth = 110.4;
+constexpr double kD0 = 2.11e-5, kDexp = 1.94, kP0 = 101325.0;
+constexpr double kQc = 1.0, kYoungA = 11.0;
+constexpr double kNmin = 1.0, kSubSafety = 0.2, kPvFloor = 1.0e-3;
+constexpr double kRmin2 = 1.0e-20, kRmin3 = 1.0e-30;   // (1e-10 m)^2, (1e-10 m)^3
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kFourThirdsPi = 4.0 / 3.0 * kPi;
+constexpr double kLn100 = 4.605170185988092;   // ln(100): hPa -> Pa
+
+// Sonntag coefficients, ln p [hPa] = a/T + b + c T + d T^2 + e ln T (Sec. 2.1)
+struct Sonntag { double a, b, c, d, e; };
+constexpr Sonntag kSonW = {-6096.9385, 16.635794, -2.711193e-2, 1.673952e-5, 2.433502};
+constexpr Sonntag kSonI = {-6024.5282, 24.7219, 1.0613868e-2, -1.3198825e-5, -0.49382577};
+
+// Case constants the host derives once (transcendentals evaluated on the host).
+struct SourceParams {
+    double f_theta;        // Eq. 9 at the contact angle
+    double het_freeze;     // k_imm * n_s * 4 pi r_g^2 exp(2 ln^2 s_g)  (Eq. 14)
+    double cnt_const;      // q_c sqrt(2 N_A^3 / (pi M^3)) / rho_l        (Eq. 4)
+    double ice_ratio[4];   // (rho_l / rho_s)^(k/3)
+    int n_sub_max;
+    int enabled;
+};
+
+// -------------------------------------------------------------- gas model
+template <class R> __device__ __forceinline__ R gas_R(R Y) { return (R(1) - Y) * R(kRa) + Y * R(kRv); }
+template <class R> __device__ __forceinline__ R gas_cp(R Y) { return (R(1) - Y) * R(kCpa) + Y * R(kCpv); }
+template <class R> __device__ __forceinline__ R gas_cv(R Y) { return (R(1) - Y) * R(kCva) + Y * R(kCvv); }
+// h = cp(Y) T + h0(Y), with h_air = cp_a (T - Tref) and h_vap = L0 + cp_v (T - Tref)
+template <class R> __device__ __forceinline__ R gas_h0(R Y)
+{
+    return -(R(1) - Y) * R(kCpa * kTref) + Y * R(kLv0 - kCpv * kTref);
+}
+
+// Temperature from specific internal energy e and vapour fraction Y (Eq. 23).
+template <class R> __device__ __forceinline__ R gas_T(R e, R Y)
+{
+    return (e + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref)) / gas_cv(Y);
+}
+
+template <class R> __device__ __forceinline__ R sutherland(R T)
+{
+    R t = T / R(kTref);
+    return R(kMu0) * t * sqrt(t) * R(kTref + kSuth) / (T + R(kSuth));
+}
+
+// ======================================================================
+//  Phase-change source (Sec. 2.2), FP64
+// ======================================================================
+__device__ __forceinline__ double ln_psat(const Sonntag &s, double T)
+{
+    return s.a / T + s.b + s.c * T + s.d * T * T + s.e * log(T) + kLn100;
+}
+
+// T_sat(p_v): Newton in x = 1/T, four steps from the gas temperature (Eq. 1).
+__device__ __forceinline__ double t_sat(const Sonntag &s, double lnpv, double T)
+{
+    double x = 1.0 / T;
+    #pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        double ix = 1.0 / x;
+        double g = s.a * x + s.b + s.c * ix + s.d * ix * ix - s.e * log(x) + kLn100 - lnpv;
+        double gp = s.a - s.c * ix * ix - 2.0 * s.d * ix * ix * ix - s.e * ix;
+        x -= g / gp;
+    }
+    return 1.0 / x;
+}
+
+__device__ __forceinline__ double surface_tension(double T)
+{
+    double tau = 1.0 - T / 647.096;              // IAPWS 1994
+    return 0.2358 * pow(tau, 1.256) * (1.0 - 0.625 * tau);
+}
+
+// Young's parameter nu (Eq. 16) with gamma, c_p of the vapour and q_c.
+__device__ __forceinline__ double young_nu(double Tsat, double h)
+{
+    return kRv * Tsat / h * (kYoungA - 0.5 - (2.0 - kQc) / (2.0 * kQc) * (kGv + 1.0) / (2.0 * kGv) * kCpv * Tsat / h);
+}
+
+// Young's growth law, beta = 0 (Eq. 16): Kn = lbar / 2r.
+__device__ __forceinline__ double young_G(double lam, double drive, double r, double rho_p, double h,
+                                          double nu, double lbar)
+{
+    double Kn = lbar / (2.0 * r);
+    return lam * drive / (rho_p * h * r * (1.0 + 3.78 * (1.0 - nu) * Kn / kPrV));
+}
+
+// A particle population (mu0 > N_MIN) is valid while r20 and r30 are at least a
+// molecular radius (1e-10 m); below that its mass has evaporated.
+__device__ __forceinline__ bool pop_valid(double m0, double m2, double m3)
+{
+    return m0 > kNmin && m2 > m0 * kRmin2 && m3 > m0 * kRmin3;
+}
+
+struct CellThermo {      // quantities of one state that the rates need
+    double T, u, v, rho, cpm, Rm, p;
+};
+
+__device__ __forceinline__ void cell_thermo(const double *U, CellThermo &c)
+{
+    c.rho = U[0];
+    c.u = U[1] / U[0];
+    c.v = U[2] / U[0];
+    double Y = U[4] / U[0];
+    double e = U[3] / U[0] - 0.5 * (c.u * c.u + c.v * c.v);
+    c.T = gas_T<double>(e, Y);
+    c.Rm = gas_R<double>(Y);
+    c.cpm = gas_cp<double>(Y);
+    c.p = c.rho * c.Rm * c.T;
+}
+
+struct Rates {
+    double dM[4], dN[4], act, mdot_f, Gl, Gs;
+    bool gone_l, gone_s;   // droplets / crystals left without mass (r20 below 1e-10 m)
+};
+
+// One evaluation of nucleation (Eq. 3-11), growth (Eq. 16, 21), freezing
+// (Eq. 12-15) and moment rates (Eq. 21); h bounds the activation rate.
+__device__ inline void phase_rates(const double *U, double h, const SourceParams &sp, const CellThermo &th,
+                                   Rates &r)
+{
+    const double T = th.T;
+    const double rv = U[4];
+    const double M0 = U[5], M1 = U[6], M2 = U[7], M3 = U[8];
+    const double N0 = U[9], N1 = U[10], N2 = U[11];
+    const double Ns = U[13], Na = U[14];
+
+    double pv = fmax(rv * kRv * T, kPvFloor);
+    const double lnpv = log(pv);
+    const double lw = ln_psat(kSonW, T);
+    const double lnSl = lnpv - lw;
+    const double sig = surface_tension(T);
+    const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+    const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+    const double mu = sutherland<double>(T);
+    const double lam = th.cpm * mu / kPr;
+    const double lbar = 1.5 * mu * sqrt(th.Rm * T) / th.p;
+
+    double Jl = 0.0, rc = 0.0;
+    r.act = 0.0;
+    if (lnSl > 0.0 && rv > 0.0) {
+        rc = 2.0 * sig / (kRhoL * kRv * T * lnSl);                      // Eq. 3
+        const double x = kFourThirdsPi * sig * rc * rc / (kKb * T);     // dG*/kT
+        const double K = sp.cnt_const * sqrt(sig) * rv * rv;            // Eq. 4
+        const double phi = 2.0 * kQc * kGv / ((kGv + 1.0) * kCpv)
+                           * (hfg * hfg / (kRv * T * T) - hfg / T);     // Eq. 5
+        const double inv1p = 1.0 / (1.0 + phi);
+        Jl = K * exp(-x) * inv1p;
+        if (Ns > Na) {                                                  // Eq. 10 on free soot
+            double Jh = K * exp(-sp.f_theta * x) * inv1p;
+            r.act = fmin(Jh, (Ns - Na) / h);
+        }
+        Jl += r.act;
+    }
+
+    r.Gl = 0.0;
+    r.Gs = 0.0;
+    const bool liq = pop_valid(M0, M2, M3);
+    const bool ice = pop_valid(N0, N2, U[12]);
+    r.gone_l = M0 > kNmin && !liq;
+    r.gone_s = N0 > kNmin && !ice;
+    if (liq) {
+        double r20 = sqrt(M2 / M0);
+        double Ts = t_sat(kSonW, lnpv, T);
+        double dT = Ts - T;
+        double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
+                                          : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+        r.Gl = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
+    }
+    if (ice) {
+        double r20 = sqrt(N2 / N0);
+        double Ts = t_sat(kSonI, lnpv, T);
+        r.Gs = young_G(lam, Ts - T, r20, kRhoS, hsg, young_nu(Ts, hsg), lbar);
+    }
+
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    r.mdot_f = 0.0;
+    if (T < kTref && liq) {
+        double l2 = log(M2 / M0), l3 = log(M3 / M0);
+        double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
+        double lrg = 0.5 * l2 - s2;
+        double daw = 1.0 - exp(ln_psat(kSonI, T) - lw);
+        daw = fmin(fmax(daw, 0.26), 0.34);
+        double lg = -906.7 + 8502.0 * daw - 26924.0 * daw * daw + 29180.0 * daw * daw * daw;
+        double Jf = 1.0e6 * exp(lg * 2.302585092994046) + sp.het_freeze * Ns;   // Eq. 12 + 14
+        double c = Jf * kFourThirdsPi;
+        F[0] = c * M3;
+        F[1] = c * M0 * exp(4.0 * lrg + 8.0 * s2);
+        F[2] = c * M0 * exp(5.0 * lrg + 12.5 * s2);
+        F[3] = c * M0 * exp(6.0 * lrg + 18.0 * s2);
+        r.mdot_f = kRhoL * kFourThirdsPi * F[3];
+    }
+
+    const double Mm[3] = {M0, M1, M2};
+    const double Nm[3] = {N0, N1, N2};
+    double rk = 1.0;
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double gl = k ? k * Mm[k - 1] * r.Gl : 0.0;
+        double gs = k ? k * Nm[k - 1] * r.Gs : 0.0;
+        r.dM[k] = gl + Jl * rk - F[k];
+        r.dN[k] = gs + sp.ice_ratio[k] * F[k];
+        rk *= rc;
+    }
+}
+
+// Source vector from moment rates (Eq. 25-26 exchange): water exact to rounding.
+__device__ __forceinline__ void exchange(const CellThermo &th, const double *dM, const double *dN, double act,
+                                         double mdot_f, double *S)
+{
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) { S[5 + k] = dM[k]; S[9 + k] = dN[k]; }
+    S[13] = 0.0;
+    S[14] = act;
+    S[4] = -kFourThirdsPi * (kRhoL * S[8] + kRhoS * S[12]);
+    S[0] = S[4];
+    S[1] = S[4] * th.u;
+    S[2] = S[4] * th.v;
+    const double T = th.T;
+    const double ml = kFourThirdsPi * kRhoL * S[8] + mdot_f;
+    const double ms = kFourThirdsPi * kRhoS * S[12] - mdot_f;
+    const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+    const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+    const double hv = kLv0 + kCpv * (T - kTref);
+    const double ke = 0.5 * (th.u * th.u + th.v * th.v);
+    S[3] = -ml * (hv - hfg + ke) - ms * (hv - hsg + ke) + mdot_f * (hsg - hfg);
+}
+
+// True when every phase-change rate vanishes identically at U (subsaturated
+// vapour, no droplets, no crystals): Q = 0 exactly, no sub-cycling needed.
+__device__ __forceinline__ bool source_inactive(const double *U, double T)
+{
+    if (U[5] > kNmin || U[9] > kNmin) return false;
+    if (!(U[4] > 0.0)) return true;
+    double pv = fmax(U[4] * kRv * T, kPvFloor);
+    return !(log(pv) - ln_psat(kSonW, T) > 0.0);
+}
+
+// Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
+// scaling, complete evaporation / sublimation and the mu1 realisability clamp.
+// Returns the number of sub-steps (0 when the cell is inactive).
+__device__ inline int source_integrate(const double *U0, double dt, const SourceParams &sp, double *Q)
+{
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Q[v] = 0.0;
+    if (!sp.enabled) return 0;
+    CellThermo th;
+    cell_thermo(U0, th);
+    if (source_inactive(U0, th.T)) return 0;
+
+    double U[NVAR];
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) U[v] = U0[v];
+    Rates r;
+    double S[NVAR];
+    phase_rates(U, dt, sp, th, r);
+    exchange(th, r.dM, r.dN, r.act, r.mdot_f, S);
+    double tau = __builtin_huge_val();
+    for (int c = 4; c <= 12; ++c)
+        if (S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
+    int nsub = 1;
+    if (tau < __builtin_huge_val()) {
+        double want = ceil(dt / (kSubSafety * tau));
+        if (want > (double)sp.n_sub_max) nsub = sp.n_sub_max;
+        else if (want > 1.0) nsub = (int)want;
+    }
+    const double h = dt / nsub;
+    for (int s = 0; s < nsub; ++s) {
+        if (s > 0) cell_thermo(U, th);
+        phase_rates(U, h, sp, th, r);
+        double act = r.act, mdf = r.mdot_f;
+        bool el = false, es = false;
+        if (r.gone_l || (r.Gl < 0.0 && U[8] + h * r.dM[3] <= 0.0)) {
+            el = true;
+            #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.dM[k] = -U[5 + k] / h;
+                r.dN[k] = k ? k * U[8 + k] * r.Gs : 0.0;
+            }
+            mdf = 0.0;
+            act = -U[14] / h;
+        }
+        if (r.gone_s || (r.Gs < 0.0 && U[12] + h * r.dN[3] <= 0.0)) {
+            es = true;
+            #pragma unroll
+            for (int k = 0; k < 4; ++k) r.dN[k] = -U[9 + k] / h;
+        }
+        exchange(th, r.dM, r.dN, act, mdf, S);
+        // positivity scaling; components of an evaporating population reach zero at
+        // theta = 1 exactly and do not take part
+        double theta = 1.0;
+        for (int c = 4; c <= 12; ++c) {
+            const bool skip = (el && c >= 5 && c <= 8) || (es && c >= 9);
+            if (!skip && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+        }
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) U[v] = U[v] + theta * h * S[v];
+        if (theta == 1.0) {
+            if (el) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if (es) { U[9] = U[10] = U[11] = U[12] = 0.0; }
+        }
+        #pragma unroll
+        for (int b = 5; b <= 9; b += 4) {
+            if (pop_valid(U[b], U[b + 2], U[b + 3])) {
+                // Hoelder interval for mu1; an empty interval collapses to its upper end
+                double hi = sqrt(U[b] * U[b + 2]);
+                double lo = fmin(U[b + 2] * U[b + 2] / U[b + 3], hi);
+                U[b + 1] = fmin(fmax(U[b + 1], lo), hi);
+            }
+        }
+    }
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Q[v] = (U[v] - U0[v]) / dt;
+    return nsub;
+}
+
+// ======================================================================
+//  Fluxes (Sec. 3.2), templated arithmetic
+// ======================================================================
+template <class R> __device__ __forceinline__ R van_leer(R a, R b)
+{
+    return (a * b > R(0)) ? R(2) * a * b / (a + b) : R(0);
+}
+
+// Roe flux on (rho, rho u_n, rho u_t, rho E) of the two-species gas in primitive-
+// jump form with Harten's entropy fix on the acoustic waves.  q = (rho, u_n, u_t,
+// p, Y).  F[0..3] mass, normal and tangential momentum, energy.
+template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R *qR, R *F)
+{
+    const R rl = qL[0], unl = qL[1], utl = qL[2], pl = qL[3], Yl = qL[4];
+    const R rr = qR[0], unr = qR[1], utr = qR[2], pr = qR[3], Yr = qR[4];
+    const R Hl = gas_cp(Yl) * (pl / (rl * gas_R(Yl))) + gas_h0(Yl) + R(0.5) * (unl * unl + utl * utl);
+    const R Hr = gas_cp(Yr) * (pr / (rr * gas_R(Yr))) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
+    const R ml = rl * unl, mr = rr * unr;
+
+    const R sl = sqrt(rl), sr = sqrt(rr);
+    const R isum = R(1) / (sl + sr);
+    const R wl = sl * isum, wr = sr * isum;
+    const R rho = sl * sr;
+    const R un = wl * unl + wr * unr;
+    const R ut = wl * utl + wr * utr;
+    const R H = wl * Hl + wr * Hr;
+    const R Y = wl * Yl + wr * Yr;
+    const R q2 = un * un + ut * ut;
+    const R cpm = gas_cp(Y), Rm = gas_R(Y);
+    const R h0 = gas_h0(Y);
+    const R T = (H - R(0.5) * q2 - h0) / cpm;
+    const R c2 = cpm / (cpm - Rm) * Rm * T;
+    const R c = sqrt(c2);
+
+    const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
+    const R i2c2 = R(0.5) / c2;
+    const R a1 = (dp - rho * c * dun) * i2c2;
+    const R a2 = dr - dp / c2;
+    const R a3 = rho * dut;
+    const R a4 = (dp + rho * c * dun) * i2c2;
+    R l1 = fabs(un - c), l4 = fabs(un + c);
+    const R l2 = fabs(un);
+    const R del = R(0.1) * c;
+    if (l1 < del) l1 = (l1 * l1 + del * del) / (R(2) * del);
+    if (l4 < del) l4 = (l4 * l4 + del * del) / (R(2) * del);
+    const R w1 = l1 * a1, w2 = l2 * a2, w3 = l2 * a3, w4 = l4 * a4;
+    // eigenvectors: (1, un-c, ut, H-un c), (1, un, ut, q2/2 + h0), (0, 0, 1, ut), (1, un+c, ut, H+un c)
+    F[0] = R(0.5) * (ml + mr) - R(0.5) * (w1 + w2 + w4);
+    F[1] = R(0.5) * (ml * unl + pl + mr * unr + pr) - R(0.5) * (w1 * (un - c) + w2 * un + w4 * (un + c));
+    F[2] = R(0.5) * (ml * utl + mr * utr) - R(0.5) * ((w1 + w2 + w4) * ut + w3);
+    F[3] = R(0.5) * (ml * Hl + mr * Hr)
+           - R(0.5) * (w1 * (H - un * c) + w2 * (R(0.5) * q2 + h0) + w3 * ut + w4 * (H + un * c));
+}
+
+}  // namespace cp
