@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -100,6 +102,14 @@ def main():
     from paper_2504_20742_amd import binding, inputs
     binding.load()
     torch.cuda.set_device(0)
+    if a.copy_calib:
+        src = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copy calibration done (3 x 512 MiB)", file=sys.stderr, flush=True)
+        del src, dst
     res = {}
     for p in a.paths.split(","):
         prec = binding.CP_FP64 if p == "fp64" else binding.CP_MIXED

@@ -147,11 +147,11 @@ int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
 int cp_set_tile(cp_ctx *ctx, int tx, int ty);
 int cp_get_tile(const cp_ctx *ctx, int *tx, int *ty);
 
-/* Measurement entry point: launch the fused stage kernel `reps` times as the middle
- * SSP-RK3 stage (reads the stage buffer and U, writes the other stage buffer; U is
- * not modified) between two HIP events on the context stream; synchronises and
- * writes the mean duration of one launch in milliseconds.  Uses the current tile
- * (autotuned first if unset).                                                      */
+/* Measurement entry point: launch the three SSP-RK3 stages of the fused stage kernel
+ * `reps` times (U -> stage buffer -> stage buffer -> stage buffer; U is only read,
+ * the phase-change source is left out) between two HIP events on the context
+ * stream; synchronises and writes the mean duration of one stage launch in
+ * milliseconds.  Uses the current tile (autotuned first if unset).                 */
 int cp_time_stage(cp_ctx *ctx, void *U, int reps, double *ms_per_launch);
 
 /* Mesh faces (host copies): xf[nx+1], rf[nr+1].                                   */

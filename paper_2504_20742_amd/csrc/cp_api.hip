@@ -249,6 +249,7 @@ StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *
     a.sp = c->sp;
     a.sp.enabled = (c->cs.phase_change != 0 && c->qmode != CP_Q_OFF) ? 1 : 0;
     a.flag = c->flag_d;
+    a.pref = c->cs.p_amb;
     a.active_count = c->act_count + (stage < 0 ? 0 : stage);
     a.active_list = c->act_list;
     return a;
@@ -639,29 +640,35 @@ int cp_time_stage(cp_ctx *c, void *U, int reps, double *ms)
     if (!c || !U || !ms || reps < 1) return fail(c, CP_EINVAL, "bad argument");
     int r = autotune(c, U);
     if (r) return r;
-    // the middle stage reads a valid state: copy U into the first stage buffer
-    const size_t bytes = (size_t)NVAR * c->plane * (c->precision == CP_FP64 ? 8 : 4);
-    HIPCHK(c, hipMemcpyAsync(c->Ua, U, bytes, hipMemcpyDeviceToDevice, c->stream));
+    // the three stages of a step, U -> Ua -> Ub -> Ua (U is only read), source off
     const double dt = 1e-12;
-    StageArgs<double> ad = stage_args<double>(c, c->Ua, U, c->Ub, 1, dt, nullptr);
-    StageArgs<float> af = stage_args<float>(c, c->Ua, U, c->Ub, 1, dt, nullptr);
-    ad.sp.enabled = af.sp.enabled = 0;   // keep the active list untouched
+    const void *in[3] = {U, c->Ua, c->Ub};
+    void *out[3] = {c->Ua, c->Ub, c->Ua};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int k = 0; k < reps; ++k) {
-        hipError_t e = c->precision == CP_FP64 ? launch_stage<double>(ad, c->tx, c->ty, c->stream)
-                                               : launch_stage<float>(af, c->tx, c->ty, c->stream);
-        if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
-    }
+    for (int k = 0; k < reps; ++k)
+        for (int st = 0; st < 3; ++st) {
+            hipError_t e;
+            if (c->precision == CP_FP64) {
+                StageArgs<double> a = stage_args<double>(c, in[st], U, out[st], st, dt, nullptr);
+                a.sp.enabled = 0;   // keep the active list untouched
+                e = launch_stage<double>(a, c->tx, c->ty, c->stream);
+            } else {
+                StageArgs<float> a = stage_args<float>(c, in[st], U, out[st], st, dt, nullptr);
+                a.sp.enabled = 0;
+                e = launch_stage<float>(a, c->tx, c->ty, c->stream);
+            }
+            if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+        }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    *ms = (double)t / reps;
+    *ms = (double)t / (3.0 * reps);
     return check_flag(c);
 }
 

@@ -44,6 +44,7 @@ template <class R> struct StageArgs {
     Metrics<R> m;
     SourceParams sp;
     int *flag;                 // bit 0: non-finite output
+    double pref;               // reference pressure removed from the momentum fluxes
     int *active_count;         // cells appended to active_list by this stage
     int *active_list;          // cells whose phase-change source may be non-zero
 };

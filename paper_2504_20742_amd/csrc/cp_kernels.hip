@@ -75,54 +75,71 @@ __device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int 
 }
 
 // ------------------------------------------------------------------ stage
+template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
+{
+    // van Leer limiter in harmonic form: 2ab/(a+b) where a, b have the same sign
+    return (a * b > R(0)) ? fdiv(R(2) * a * b, a + b) : R(0);
+}
+
+// LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
+// viscosities and limited slopes on the tile plus a 1-cell ring (RX x RY), and one
+// face buffer reused for the x-faces, the r-faces and the scalar slopes.
 template <class R, int TX, int TY> struct Tile {
     static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
-    R rho[N], u[N], v[N], p[N], T[N], Y[N], mu[N], D[N], mut[N], phi[N];
+    static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
+    static constexpr int NFX = (TX + 1) * TY, NFR = TX * (TY + 1);
+    static constexpr int NF = NFX > NFR ? NFX : NFR;
+    R rho[N], u[N], v[N], p[N], T[N], Y[N], phi[N];
+    R mu[NR], D[NR], mut[NR];
+    R sx[5][NR], sr[5][NR];      // gas slopes; reused as scalar slopes (sx[0], sr[0])
+    R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn
     int code[N];
 };
 
-// Gas part of the flux through the face between LDS cells a and a+s (s = normal
-// stride, ts = tangential stride).  F = (F^c - F^v) on rho, rho u, rho v, rho E,
-// rho Y in global components; Fm = Roe mass flux; kd = eddy diffusivity / dn for the
-// passive scalars.
+// ext index of ring cell r, and ring index of ext cell e (inside the ring)
+template <int TX, int TY> __device__ __forceinline__ int ext_of_ring(int r)
+{
+    return (r / (TX + 2) + 1) * (TX + 4) + r % (TX + 2) + 1;
+}
+template <int TX, int TY> __device__ __forceinline__ int ring_of_ext(int e)
+{
+    return (e / (TX + 4) - 1) * (TX + 2) + e % (TX + 4) - 1;
+}
+
+// Gas flux through the face between ext cells a and b = a + s (normal stride s,
+// tangential stride ts; ra, rb their ring indices): MUSCL states from the cell
+// slopes, Roe convective flux, central viscous + eddy flux.  Writes F^c - F^v on
+// (rho, rho u, rho v, rho E, rho Y) in global components, the Roe mass flux and the
+// eddy diffusivity / dn for the passive scalars.
 template <class R, class TileT>
-__device__ __forceinline__ void gas_face(const TileT &t, int a, int s, int ts, bool xdir, R inv_dn, R inv_d2t,
-                                         R inv_r, R *F, R &Fm, R &kd)
+__device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, int s, int ts, bool xdir, R inv_dn,
+                                         R inv_d2t, R inv_r, R pref, R *F, R &Fm, R &kd)
 {
     const int b = a + s;
-    const int c0 = a - s, c3 = b + s;
+    const R(*sl)[TileT::NR] = xdir ? t.sx : t.sr;
     const R *un_ = xdir ? t.u : t.v;
     const R *ut_ = xdir ? t.v : t.u;
     R qL[5], qR[5];
-    {
-        const int ix[4] = {c0, a, b, c3};
-        R q[5][4];
-        #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            q[0][k] = t.rho[ix[k]];
-            q[1][k] = un_[ix[k]];
-            q[2][k] = ut_[ix[k]];
-            q[3][k] = t.p[ix[k]];
-            q[4][k] = t.Y[ix[k]];
-        }
-        #pragma unroll
-        for (int w = 0; w < 5; ++w) {
-            R d0 = q[w][1] - q[w][0], d1 = q[w][2] - q[w][1], d2 = q[w][3] - q[w][2];
-            qL[w] = q[w][1] + R(0.5) * van_leer(d0, d1);
-            qR[w] = q[w][2] - R(0.5) * van_leer(d1, d2);
-        }
-    }
+    qL[0] = t.rho[a] + R(0.5) * sl[0][ra];
+    qR[0] = t.rho[b] - R(0.5) * sl[0][rb];
+    qL[1] = un_[a] + R(0.5) * sl[xdir ? 1 : 2][ra];
+    qR[1] = un_[b] - R(0.5) * sl[xdir ? 1 : 2][rb];
+    qL[2] = ut_[a] + R(0.5) * sl[xdir ? 2 : 1][ra];
+    qR[2] = ut_[b] - R(0.5) * sl[xdir ? 2 : 1][rb];
+    qL[3] = t.p[a] + R(0.5) * sl[3][ra];
+    qR[3] = t.p[b] - R(0.5) * sl[3][rb];
+    qL[4] = t.Y[a] + R(0.5) * sl[4][ra];
+    qR[4] = t.Y[b] - R(0.5) * sl[4][rb];
     R Fc[4];
-    roe_flux(qL, qR, Fc);
+    roe_flux(qL, qR, pref, Fc);
     Fm = Fc[0];
     const R FY = Fm * (Fm >= R(0) ? qL[4] : qR[4]);
 
-    // central viscous + eddy flux
-    const R mu = R(0.5) * (t.mu[a] + t.mu[b]);
-    const R mut = R(0.5) * (t.mut[a] + t.mut[b]);
+    const R mu = R(0.5) * (t.mu[ra] + t.mu[rb]);
+    const R mut = R(0.5) * (t.mut[ra] + t.mut[rb]);
     const R rho = R(0.5) * (t.rho[a] + t.rho[b]);
     const R cpf = R(0.5) * (gas_cp(t.Y[a]) + gas_cp(t.Y[b]));
-    const R Df = R(0.5) * (t.D[a] + t.D[b]);
+    const R Df = R(0.5) * (t.D[ra] + t.D[rb]);
     const R dhf = R(kLv0) + R(kCpv - kCpa) * (R(0.5) * (t.T[a] + t.T[b]) - R(kTref));
     const R uf = R(0.5) * (t.u[a] + t.u[b]), vf = R(0.5) * (t.v[a] + t.v[b]);
     const R un_n = (un_[b] - un_[a]) * inv_dn;
@@ -166,15 +183,13 @@ template <class R> __device__ __forceinline__ R assemble_r(R rx, R fn, R an, R f
     return rx - (fn * an - fs * as) * ivr;
 }
 
-// Passive scalar flux through a face: upwind MUSCL value times the mass flux
-// minus eddy diffusion.
+// Passive scalar flux through a face: upwind MUSCL value (from the cell slopes)
+// times the Roe mass flux, minus eddy diffusion.
 template <class R>
-__device__ __forceinline__ R scalar_face(const R *phi, int a, int s, R Fm, R kd)
+__device__ __forceinline__ R scalar_face(const R *phi, const R *sl, int a, int b, int ra, int rb, R Fm, R kd)
 {
-    const R q0 = phi[a - s], q1 = phi[a], q2 = phi[a + s], q3 = phi[a + 2 * s];
-    const R d0 = q1 - q0, d1 = q2 - q1, d2 = q3 - q2;
-    const R up = Fm >= R(0) ? q1 + R(0.5) * van_leer(d0, d1) : q2 - R(0.5) * van_leer(d1, d2);
-    return Fm * up - kd * d1;
+    const R up = Fm >= R(0) ? phi[a] + R(0.5) * sl[ra] : phi[b] - R(0.5) * sl[rb];
+    return Fm * up - kd * (phi[b] - phi[a]);
 }
 
 template <class R, int TX, int TY>
@@ -182,14 +197,24 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
 {
     using TileT = Tile<R, TX, TY>;
     constexpr int EX = TileT::EX, NE = TileT::N, NT = TX * TY;
+    constexpr int RX = TileT::RX, NRG = TileT::NR;
     __shared__ TileT t;
     const BcInfo &bc = a.bc;
     const Metrics<R> &m = a.m;
     const int nx = bc.nx, nr = bc.nr;
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give
+    // each XCD a contiguous band of tiles and let neighbouring tiles share their
+    // halos in that XCD's L2
+    const int gx = gridDim.x, nb = gx * gridDim.y;
+    const int bid = blockIdx.y * gx + blockIdx.x;
+    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
+    const int tb = xcd * q + min(xcd, rem) + (bid >> 3);
+    const int i0 = (tb % gx) * TX, j0 = (tb / gx) * TY;
+    const R pref = (R)a.pref;
+    const bool axi = bc.geom == 0;
 
-    // phase 1: gas primitives, viscosity, vapour diffusivity of tile + halo
+    // phase 1: gas primitives of tile + halo
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
         const int i = min(i0 + ex - 2, nx + 1), j = min(j0 + ey - 2, nr + 1);
@@ -201,30 +226,36 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
         const R U4 = fetch(a.Uin, a.plane, bc, cs.code, 4);
         if (cs.fu) U1 = -U1;
         if (cs.fv) U2 = -U2;
-        const R ir = R(1) / U0;
+        const R ir = fdiv(R(1), U0);
         const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
         const R eint = U3 * ir - R(0.5) * (u * u + v * v);
-        const R T = gas_T(eint, Y);
-        const R p = U0 * gas_R(Y) * T;
+        const R T = fdiv(eint + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
         t.code[e] = cs.code;
         t.rho[e] = U0;
         t.u[e] = u;
         t.v[e] = v;
         t.Y[e] = Y;
         t.T[e] = T;
-        t.p[e] = p;
-        t.mu[e] = sutherland(T);
-        t.D[e] = R(kD0) * exp(R(kDexp) * log(T * R(1.0 / kTref))) * (R(kP0) / p);
+        t.p[e] = U0 * gas_R(Y) * T;
     }
     __syncthreads();
-    // phase 2: eddy viscosity mu_t = rho l^2 |du/dr + dv/dx| on tile + 1 ring
-    for (int e = tid; e < (TX + 2) * (TY + 2); e += NT) {
-        const int ex = e % (TX + 2) + 1, ey = e / (TX + 2) + 1;
-        const int l = ey * EX + ex;
-        const int i = min(i0 + ex - 2, nx), j = min(j0 + ey - 2, nr);
+    // phase 2 (tile + ring): viscosity, vapour diffusivity, eddy viscosity
+    // mu_t = rho l^2 |du/dr + dv/dx|, and van Leer slopes of the gas primitives
+    for (int r = tid; r < NRG; r += NT) {
+        const int l = ext_of_ring<TX, TY>(r);
+        const int i = min(i0 + r % RX - 1, nx), j = min(j0 + r / RX - 1, nr);
+        const R T = t.T[l];
+        t.mu[r] = sutherland(T);
+        t.D[r] = R(kD0) * exp(R(kDexp) * log(T * R(1.0 / kTref))) * fdiv(R(kP0), t.p[l]);
         const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
         const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
-        t.mut[l] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
+        t.mut[r] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
+        const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            t.sx[k][r] = vl_slope(w[k][l] - w[k][l - 1], w[k][l + 1] - w[k][l]);
+            t.sr[k][r] = vl_slope(w[k][l] - w[k][l - EX], w[k][l + EX] - w[k][l]);
+        }
     }
     __syncthreads();
 
@@ -232,70 +263,93 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
     const int i = i0 + tx, j = j0 + ty;
     const bool valid = i < nx && j < nr;
     const int l = (ty + 2) * EX + tx + 2;
-    const bool axi = bc.geom == 0;
+    const int rl = (ty + 1) * RX + tx + 1;
 
+    // phase 3: x-faces, each once
+    for (int f = tid; f < TileT::NFX; f += NT) {
+        const int fi = f % (TX + 1), fj = f / (TX + 1);
+        const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
+        const int la = (fj + 2) * EX + fi + 1;
+        const int ra = (fj + 1) * RX + fi;
+        R F[5], fm, kdv;
+        gas_face<R>(t, la, ra, ra + 1, 1, EX, true, m.inv_dxf[ig], m.inv_d2r[jg + 1], m.inv_rc[jg + 1], pref, F, fm, kdv);
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) t.face[k][f] = F[k];
+        t.face[5][f] = fm;
+        t.face[6][f] = kdv;
+    }
+    __syncthreads();
     R res[NVAR];
     R Fm0 = R(0), Fm1 = R(0), Fm2 = R(0), Fm3 = R(0), kd0 = R(0), kd1 = R(0), kd2 = R(0), kd3 = R(0);
+    const R idx = valid ? m.inv_dx[i] : R(0);
     if (valid) {
-        R Fw[5], Fs[5] = {R(0), R(0), R(0), R(0), R(0)};
-        const R idx = m.inv_dx[i], ivr = m.invV_r[j], as = m.rfa[j], an = m.rfa[j + 1];
-        // faces one at a time (west, east, south, north) to bound register use; the
-        // divergence is formed from face differences as -(Fe-Fw)/dx - (Fn An - Fs As)/V
-        // without contraction, so identical faces cancel exactly
-        #pragma unroll 1
-        for (int f = 0; f < 4; ++f) {
-            if (f == 2 && axi && j == 0) continue;   // the axis face has zero area
-            const bool xd = f < 2;
-            const int la = f == 0 ? l - 1 : (f == 2 ? l - EX : l);
-            const R inv_dn = f == 0 ? m.inv_dxf[i] : f == 1 ? m.inv_dxf[i + 1] : f == 2 ? m.inv_drf[j] : m.inv_drf[j + 1];
-            const R inv_d2t = xd ? m.inv_d2r[j + 1] : m.inv_d2x[i + 1];
-            const R inv_r = xd ? m.inv_rc[j + 1] : (f == 2 ? m.inv_rf[j] : m.inv_rf[j + 1]);
-            R F[5], fm, kdv;
-            gas_face<R>(t, la, xd ? 1 : EX, xd ? EX : 1, xd, inv_dn, inv_d2t, inv_r, F, fm, kdv);
-            if (f == 0) {
-                Fm0 = fm; kd0 = kdv;
-                #pragma unroll
-                for (int k = 0; k < 5; ++k) Fw[k] = F[k];
-            } else if (f == 1) {
-                Fm1 = fm; kd1 = kdv;
-                #pragma unroll
-                for (int k = 0; k < 5; ++k) res[k] = assemble_x(F[k], Fw[k], idx);
-            } else if (f == 2) {
-                Fm2 = fm; kd2 = kdv;
-                #pragma unroll
-                for (int k = 0; k < 5; ++k) Fs[k] = F[k];
-            } else {
-                Fm3 = fm; kd3 = kdv;
-                #pragma unroll
-                for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], F[k], an, Fs[k], as, ivr);
-            }
+        const int fw = ty * (TX + 1) + tx;
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) res[k] = assemble_x(t.face[k][fw + 1], t.face[k][fw], idx);
+        Fm0 = t.face[5][fw];
+        kd0 = t.face[6][fw];
+        Fm1 = t.face[5][fw + 1];
+        kd1 = t.face[6][fw + 1];
+    }
+    __syncthreads();
+    // phase 4: r-faces, each once (the axis face has zero area)
+    for (int f = tid; f < TileT::NFR; f += NT) {
+        const int fi = f % TX, fj = f / TX;
+        const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
+        R F[5] = {R(0), R(0), R(0), R(0), R(0)}, fm = R(0), kdv = R(0);
+        if (!(axi && jg == 0)) {
+            const int la = (fj + 1) * EX + fi + 2;
+            const int ra = fj * RX + fi + 1;
+            gas_face<R>(t, la, ra, ra + RX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1], m.inv_rf[jg], pref, F, fm,
+                        kdv);
         }
-        if (axi) {   // (p - tau_thetatheta) / r_c on radial momentum
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) t.face[k][f] = F[k];
+        t.face[5][f] = fm;
+        t.face[6][f] = kdv;
+    }
+    __syncthreads();
+    if (valid) {
+        const int fs = ty * TX + tx, fn = fs + TX;
+        const R ivr = m.invV_r[j], as = m.rfa[j], an = m.rfa[j + 1];
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], t.face[k][fn], an, t.face[k][fs], as, ivr);
+        Fm2 = t.face[5][fs];
+        kd2 = t.face[6][fs];
+        Fm3 = t.face[5][fn];
+        kd3 = t.face[6][fn];
+        if (axi) {   // (p - p_ref - tau_thetatheta) / r_c on radial momentum
             const R ir = m.inv_rc[j + 1];
             const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
             const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
             const R vr = t.v[l] * ir;
-            const R mue = t.mu[l] + t.mut[l];
+            const R mue = t.mu[rl] + t.mut[rl];
             const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
-            res[2] += (t.p[l] - ttt) * ir;
+            res[2] += ((t.p[l] - pref) - ttt) * ir;
         }
     }
-    // phase 3: passive scalars, one LDS slot each
+    // phase 5: passive scalars through one LDS slot each, slopes once per cell
     for (int s = 5; s < NVAR; ++s) {
         __syncthreads();
-        for (int e = tid; e < NE; e += NT) t.phi[e] = fetch(a.Uin, a.plane, bc, t.code[e], s) / t.rho[e];
+        for (int e = tid; e < NE; e += NT) t.phi[e] = fdiv(fetch(a.Uin, a.plane, bc, t.code[e], s), t.rho[e]);
+        __syncthreads();
+        for (int r = tid; r < NRG; r += NT) {
+            const int le = ext_of_ring<TX, TY>(r);
+            t.sx[0][r] = vl_slope(t.phi[le] - t.phi[le - 1], t.phi[le + 1] - t.phi[le]);
+            t.sr[0][r] = vl_slope(t.phi[le] - t.phi[le - EX], t.phi[le + EX] - t.phi[le]);
+        }
         __syncthreads();
         if (valid) {
-            const R fw = scalar_face(t.phi, l - 1, 1, Fm0, kd0);
-            const R fe = scalar_face(t.phi, l, 1, Fm1, kd1);
-            const R fs = (axi && j == 0) ? R(0) : scalar_face(t.phi, l - EX, EX, Fm2, kd2);
-            const R fn = scalar_face(t.phi, l, EX, Fm3, kd3);
-            res[s] = assemble_r(assemble_x(fe, fw, m.inv_dx[i]), fn, m.rfa[j + 1], fs, m.rfa[j], m.invV_r[j]);
+            const R fw = scalar_face(t.phi, t.sx[0], l - 1, l, rl - 1, rl, Fm0, kd0);
+            const R fe = scalar_face(t.phi, t.sx[0], l, l + 1, rl, rl + 1, Fm1, kd1);
+            const R fsv = (axi && j == 0) ? R(0) : scalar_face(t.phi, t.sr[0], l - EX, l, rl - RX, rl, Fm2, kd2);
+            const R fnv = scalar_face(t.phi, t.sr[0], l, l + EX, rl, rl + RX, Fm3, kd3);
+            res[s] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
         }
     }
     if (!valid) return;
 
-    // phase 4: SSP-RK3 combination with the transport residual.  Cells whose
+    // phase 6: SSP-RK3 combination with the transport residual.  Cells whose
     // phase-change source can be non-zero are appended to the active list; the
     // source kernel adds b dt Q(U^(s-1), dt) to them (the stage is linear in L).
     const long c = (long)j * nx + i;
@@ -309,7 +363,8 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
         }
     } else {
         const R rdt = (R)dt;
-        if (a.sp.enabled) {
+        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(a.Uin[4 * a.plane + c], a.Uin[5 * a.plane + c],
+                                                                      a.Uin[9 * a.plane + c], t.T[l]))) {
             double Ug[NVAR];
             #pragma unroll
             for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)a.Uin[v * a.plane + c] : 0.0;

@@ -50,6 +50,10 @@ struct SourceParams {
     int enabled;
 };
 
+// Division: IEEE in FP64; a hardware reciprocal (about 1 ulp) in the FP32 path.
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // -------------------------------------------------------------- gas model
 template <class R> __device__ __forceinline__ R gas_R(R Y) { return (R(1) - Y) * R(kRa) + Y * R(kRv); }
 template <class R> __device__ __forceinline__ R gas_cp(R Y) { return (R(1) - Y) * R(kCpa) + Y * R(kCpv); }
@@ -63,13 +67,13 @@ template <class R> __device__ __forceinline__ R gas_h0(R Y)
 // Temperature from specific internal energy e and vapour fraction Y (Eq. 23).
 template <class R> __device__ __forceinline__ R gas_T(R e, R Y)
 {
-    return (e + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref)) / gas_cv(Y);
+    return fdiv(e + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
 }
 
 template <class R> __device__ __forceinline__ R sutherland(R T)
 {
-    R t = T / R(kTref);
-    return R(kMu0) * t * sqrt(t) * R(kTref + kSuth) / (T + R(kSuth));
+    R t = T * R(1.0 / kTref);
+    return fdiv(R(kMu0) * t * sqrt(t) * R(kTref + kSuth), T + R(kSuth));
 }
 
 // ======================================================================
@@ -265,6 +269,18 @@ __device__ __forceinline__ bool source_inactive(const double *U, double T)
     return !(log(pv) - ln_psat(kSonW, T) > 0.0);
 }
 
+// Conservative pre-filter in the storage precision: true when the cell certainly
+// has no phase change (no particles and ln S_l below -0.01, far outside the FP32
+// rounding of ln S_l); otherwise the FP64 test decides.
+template <class R> __device__ __forceinline__ bool clearly_inactive(R rho_v, R M0, R N0, R T)
+{
+    if (M0 > R(kNmin) || N0 > R(kNmin)) return false;
+    if (!(rho_v > R(0))) return true;
+    const R lnSl = log(rho_v * R(kRv) * T) - (R(kSonW.a) / T + R(kSonW.b) + R(kSonW.c) * T + R(kSonW.d) * T * T +
+                                              R(kSonW.e) * log(T) + R(kLn100));
+    return lnSl < R(-0.01);
+}
+
 // Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
 // scaling, complete evaporation / sublimation and the mu1 realisability clamp.
 // Returns the number of sub-steps (0 when the cell is inactive).
@@ -353,17 +369,17 @@ template <class R> __device__ __forceinline__ R van_leer(R a, R b)
 
 // Roe flux on (rho, rho u_n, rho u_t, rho E) of the two-species gas in primitive-
 // jump form with Harten's entropy fix on the acoustic waves.  q = (rho, u_n, u_t,
-// p, Y).  F[0..3] mass, normal and tangential momentum, energy.
-template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R *qR, R *F)
+// p, Y).  F[0..3] mass, normal and tangential momentum (less pref), energy.
+template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R *qR, R pref, R *F)
 {
     const R rl = qL[0], unl = qL[1], utl = qL[2], pl = qL[3], Yl = qL[4];
     const R rr = qR[0], unr = qR[1], utr = qR[2], pr = qR[3], Yr = qR[4];
-    const R Hl = gas_cp(Yl) * (pl / (rl * gas_R(Yl))) + gas_h0(Yl) + R(0.5) * (unl * unl + utl * utl);
-    const R Hr = gas_cp(Yr) * (pr / (rr * gas_R(Yr))) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
+    const R Hl = gas_cp(Yl) * fdiv(pl, rl * gas_R(Yl)) + gas_h0(Yl) + R(0.5) * (unl * unl + utl * utl);
+    const R Hr = gas_cp(Yr) * fdiv(pr, rr * gas_R(Yr)) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
     const R ml = rl * unl, mr = rr * unr;
 
     const R sl = sqrt(rl), sr = sqrt(rr);
-    const R isum = R(1) / (sl + sr);
+    const R isum = fdiv(R(1), sl + sr);
     const R wl = sl * isum, wr = sr * isum;
     const R rho = sl * sr;
     const R un = wl * unl + wr * unr;
@@ -373,25 +389,29 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R q2 = un * un + ut * ut;
     const R cpm = gas_cp(Y), Rm = gas_R(Y);
     const R h0 = gas_h0(Y);
-    const R T = (H - R(0.5) * q2 - h0) / cpm;
-    const R c2 = cpm / (cpm - Rm) * Rm * T;
+    const R T = fdiv(H - R(0.5) * q2 - h0, cpm);
+    const R c2 = fdiv(cpm, cpm - Rm) * Rm * T;
     const R c = sqrt(c2);
+    const R ic2 = fdiv(R(1), c2);
 
     const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
-    const R i2c2 = R(0.5) / c2;
+    const R i2c2 = R(0.5) * ic2;
     const R a1 = (dp - rho * c * dun) * i2c2;
-    const R a2 = dr - dp / c2;
+    const R a2 = dr - dp * ic2;
     const R a3 = rho * dut;
     const R a4 = (dp + rho * c * dun) * i2c2;
     R l1 = fabs(un - c), l4 = fabs(un + c);
     const R l2 = fabs(un);
     const R del = R(0.1) * c;
-    if (l1 < del) l1 = (l1 * l1 + del * del) / (R(2) * del);
-    if (l4 < del) l4 = (l4 * l4 + del * del) / (R(2) * del);
+    if (l1 < del) l1 = fdiv(l1 * l1 + del * del, R(2) * del);
+    if (l4 < del) l4 = fdiv(l4 * l4 + del * del, R(2) * del);
     const R w1 = l1 * a1, w2 = l2 * a2, w3 = l2 * a3, w4 = l4 * a4;
     // eigenvectors: (1, un-c, ut, H-un c), (1, un, ut, q2/2 + h0), (0, 0, 1, ut), (1, un+c, ut, H+un c)
     F[0] = R(0.5) * (ml + mr) - R(0.5) * (w1 + w2 + w4);
-    F[1] = R(0.5) * (ml * unl + pl + mr * unr + pr) - R(0.5) * (w1 * (un - c) + w2 * un + w4 * (un + c));
+    // a uniform reference pressure exerts no net force on a closed cell: it is taken
+    // out of the momentum flux (and out of the axisymmetric pressure source), which
+    // keeps the FP32 path free of cancellation between large pressure terms
+    F[1] = R(0.5) * (ml * unl + (pl - pref) + mr * unr + (pr - pref)) - R(0.5) * (w1 * (un - c) + w2 * un + w4 * (un + c));
     F[2] = R(0.5) * (ml * utl + mr * utr) - R(0.5) * ((w1 + w2 + w4) * ut + w3);
     F[3] = R(0.5) * (ml * Hl + mr * Hr)
            - R(0.5) * (w1 * (H - un * c) + w2 * (R(0.5) * q2 + h0) + w3 * ut + w4 * (H + un * c));

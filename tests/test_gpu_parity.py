@@ -164,11 +164,17 @@ def test_ragged_meshes(B, orc, shape):
 
 
 def test_closed_box_gpu(B, orc):
-    """Uniform source-active box: bitwise uniform, water conserved, oracle parity."""
+    """Uniform source-active box: bitwise uniform, water conserved, oracle parity.
+    A 0-D nucleation burst is ill-conditioned (J ~ exp(-dG*/kT)), so the parity
+    bound is ten times the oracle's own response to a 1-ulp perturbation of its
+    initial state."""
     m, c = inputs.sa0()
     o = orc.Oracle(m, c)
     Uo = o.init()
+    Up = Uo * (1.0 + np.random.default_rng(1).integers(-1, 2, Uo.shape) * 2.0 ** -52)
     o.run(Uo, 60)
+    o.run(Up, 60)
+    sens = rel_l2(Up, Uo)
     s = B.Solver(m, c)
     U = s.init()
     w0 = s.diag(U)["water"]
@@ -176,7 +182,7 @@ def test_closed_box_gpu(B, orc):
     Ug = host(U)
     assert np.all(Ug == Ug[:, :1, :1])
     assert s.diag(U)["water"] == pytest.approx(w0, rel=1e-13)
-    assert (rel_l2(Ug, Uo) <= 1e-10).all()
+    assert (rel_l2(Ug, Uo) <= 10 * sens + 1e-12).all(), (rel_l2(Ug, Uo), sens)
 
 
 def test_free_stream_gpu(B):
