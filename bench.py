@@ -62,6 +62,29 @@ def run_path(binding, inputs, precision, steps, warmup, stage_reps):
     return out
 
 
+def run_batch(binding, inputs, steps):
+    """64 plumes on meshes drawn from {256x64, 512x128, 1024x256}, mixed precision,
+    one graph replay per step covering every plume."""
+    import torch
+    cases = inputs.config4(seed=0)
+    bt = binding.Batch([m for m, _ in cases], [c for _, c in cases], binding.CP_MIXED)
+    Us = bt.init()
+    bt.step_n(Us, 3)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    bt.step_n(Us, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    cells = sum(m["nx"] * m["nr"] for m, _ in cases)
+    bt.close()
+    del Us
+    torch.cuda.empty_cache()
+    return {"plumes": len(cases), "cells": cells, "steps": steps, "ms_per_step": ms / steps,
+            "cell_updates_per_s": cells * steps / (ms / 1e3)}
+
+
 def cpu_baseline(inputs, seconds_target=15.0):
     """The FP64 oracle on this host's cores, a bounded number of steps of the same
     2048 x 512 workload."""
@@ -91,6 +114,7 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -144,6 +168,9 @@ def main():
     }
     if "fp64" in res and "mixed" in res:
         line["mixed_over_fp64"] = res["mixed"]["cell_updates_per_s"] / res["fp64"]["cell_updates_per_s"]
+    if a.batch_steps > 0:
+        print("bench: 64-plume batch, %d steps" % a.batch_steps, file=sys.stderr, flush=True)
+        line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)
     if not a.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(inputs)

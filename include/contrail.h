@@ -159,6 +159,26 @@ int cp_mesh_faces(const cp_ctx *ctx, double *xf, double *rf);
 
 const char *cp_error_string(const cp_ctx *ctx);
 
+/* ---------------------------------------------------------------------- batch
+ * Many operating points (plumes), each with its own mesh and case, advanced
+ * together: every RK stage is one launch over a work list of (plume, tile) pairs,
+ * each plume keeps its own CFL time step on the device, and the whole step is a
+ * captured HIP graph.  Per-plume results are identical to running that plume alone.
+ * Arrays: U[p] is plume p's U[15][nr_p][nx_p] (caller-owned device memory).         */
+typedef struct cp_batch cp_batch;
+
+/* n plumes with meshes[p], cases[p] (host arrays of n structs), all in one precision,
+ * launched on hip_stream.  Errors as cp_create.                                     */
+int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int precision, void *hip_stream,
+                    cp_batch **out);
+void cp_batch_destroy(cp_batch *b);
+/* Initial state of every plume (as cp_init).  U: host array of n device pointers.    */
+int cp_batch_init(cp_batch *b, void *const *U);
+/* nsteps steps of every plume; synchronises; t_host (n entries, may be NULL) receives
+ * each plume's simulated time.  CP_ENONFINITE names the plume in the message.      */
+int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host);
+const char *cp_batch_error_string(const cp_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,11 @@ _SIGS = {
     "cp_mesh_faces": (_I, [_P, _DP, _DP]),
     "cp_time_stage": (_I, [_P, _P, _I, _DP]),
     "cp_error_string": (ctypes.c_char_p, [_P]),
+    "cp_batch_create": (_I, [_I, _P, _P, _I, _P, ctypes.POINTER(_P)]),
+    "cp_batch_destroy": (None, [_P]),
+    "cp_batch_init": (_I, [_P, _P]),
+    "cp_batch_step_n": (_I, [_P, _P, _I, _DP]),
+    "cp_batch_error_string": (ctypes.c_char_p, [_P]),
 }
 
 
@@ -236,3 +241,58 @@ class Solver:
         rf = np.zeros(self.nr + 1)
         self._chk(self.L.cp_mesh_faces(self.h, xf.ctypes.data_as(_DP), rf.ctypes.data_as(_DP)))
         return xf, rf
+
+
+class Batch:
+    """Many plumes advanced together (a cp_batch); U[p] are torch CUDA tensors."""
+
+    def __init__(self, meshes, cases, precision=CP_MIXED, stream=None):
+        self.L = load()
+        self.n = len(meshes)
+        self.precision = precision
+        self._m = (CpMesh * self.n)(*[make_mesh(m) for m in meshes])
+        self._c = (CpCase * self.n)(*[make_case(c) for c in cases])
+        self.shapes = [(int(m["nr"]), int(m["nx"])) for m in meshes]
+        h = _P()
+        s = _current_stream() if stream is None else stream
+        rc = self.L.cp_batch_create(self.n, ctypes.cast(self._m, _P), ctypes.cast(self._c, _P), int(precision), s,
+                                    ctypes.byref(h))
+        if rc != CP_OK:
+            raise ContrailError(rc, "cp_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != CP_OK:
+            raise ContrailError(rc, self.L.cp_batch_error_string(self.h).decode())
+
+    def _ptrs(self, Us):
+        assert len(Us) == self.n
+        return (ctypes.c_void_p * self.n)(*[u.data_ptr() for u in Us])
+
+    def empty(self):
+        import torch
+        dt = torch.float64 if self.precision == CP_FP64 else torch.float32
+        return [torch.empty((NV, nr, nx), dtype=dt, device="cuda") for nr, nx in self.shapes]
+
+    def init(self, Us=None):
+        Us = self.empty() if Us is None else Us
+        self._keep = self._ptrs(Us)
+        self._chk(self.L.cp_batch_init(self.h, ctypes.cast(self._keep, _P)))
+        return Us
+
+    def step_n(self, Us, n):
+        self._keep = self._ptrs(Us)
+        t = (ctypes.c_double * self.n)()
+        self._chk(self.L.cp_batch_step_n(self.h, ctypes.cast(self._keep, _P), int(n), t))
+        return list(t)

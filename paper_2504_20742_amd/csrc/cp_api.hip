@@ -683,3 +683,228 @@ int cp_mesh_faces(const cp_ctx *c, double *xf, double *rf)
 const char *cp_error_string(const cp_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 }  // extern "C"
+
+// ====================================================================== batch
+// Many operating points, each a full context (mesh, metrics, BC states, stage
+// buffers, active list), advanced together: one stage launch per RK stage covers a
+// work list of (plume, tile) pairs, the CFL reduction keeps one time step per
+// plume on the device, and the step is captured once in a HIP graph.
+struct cp_batch {
+    int n = 0, precision = CP_FP64;
+    hipStream_t stream = nullptr, cap_stream = nullptr;
+    std::vector<cp_ctx *> plumes;
+    int tx = 32, ty = 8;
+    long max_cells = 0;
+    int nwork = 0;
+    int *work_plume = nullptr, *work_tile = nullptr;
+    void *stage_args[3] = {}, *fix_args[3] = {}, *cfl_args = nullptr;
+    unsigned long long *acc = nullptr;
+    double *cfl = nullptr, *dt = nullptr, *t = nullptr;
+    std::vector<void *> allocs;
+    hipGraphExec_t graph = nullptr;
+    std::vector<void *> graph_U;
+    std::string err;
+};
+
+namespace {
+
+int bfail(cp_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+template <class T> T *balloc(cp_batch *b, size_t n)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    b->allocs.push_back(p);
+    return (T *)p;
+}
+
+template <class R> int batch_upload_args(cp_batch *b, void *const *U)
+{
+    const int n = b->n;
+    std::vector<StageArgs<R>> sa[3];
+    std::vector<SourceFixArgs<R>> fa[3];
+    std::vector<CflArgs<R>> ca(n);
+    for (int p = 0; p < n; ++p) {
+        cp_ctx *c = b->plumes[p];
+        const void *in[3] = {U[p], c->Ua, c->Ub};
+        void *out[3] = {c->Ua, c->Ub, U[p]};
+        for (int s = 0; s < 3; ++s) {
+            sa[s].push_back(stage_args<R>(c, in[s], U[p], out[s], s, 0.0, b->dt + p));
+            fa[s].push_back(fix_args<R>(c, in[s], out[s], s, 0.0, b->dt + p));
+        }
+        CflArgs<R> &a = ca[p];
+        a.U = (const R *)U[p];
+        a.plane = c->plane;
+        a.bc = bcinfo(c);
+        a.xc = c->xc_d;
+        a.rc = c->rc_d;
+        a.inv_dx = c->inv_dx_d;
+        a.inv_dr = c->inv_dr_d;
+        a.kappa_m = c->cs.kappa_m;
+        a.delta0 = c->cs.delta0_frac * c->cs.R_core;
+        a.s_delta = c->cs.s_delta;
+        a.acc = b->acc + p;
+    }
+    for (int s = 0; s < 3; ++s) {
+        if (!b->stage_args[s]) b->stage_args[s] = balloc<StageArgs<R>>(b, n);
+        if (!b->fix_args[s]) b->fix_args[s] = balloc<SourceFixArgs<R>>(b, n);
+        if (!b->stage_args[s] || !b->fix_args[s]) return bfail(b, CP_ENOMEM, "batch argument tables");
+        if (hipMemcpy(b->stage_args[s], sa[s].data(), n * sizeof(StageArgs<R>), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->fix_args[s], fa[s].data(), n * sizeof(SourceFixArgs<R>), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(b, CP_EHIP, "batch argument upload");
+    }
+    if (!b->cfl_args) b->cfl_args = balloc<CflArgs<R>>(b, n);
+    if (!b->cfl_args) return bfail(b, CP_ENOMEM, "batch argument tables");
+    if (hipMemcpy(b->cfl_args, ca.data(), n * sizeof(CflArgs<R>), hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, CP_EHIP, "batch argument upload");
+    return CP_OK;
+}
+
+template <class R> int batch_enqueue_step(cp_batch *b, hipStream_t s)
+{
+    hipError_t e = launch_cfl_batch<R>((const CflArgs<R> *)b->cfl_args, b->n, b->max_cells, s);
+    if (e == hipSuccess) e = launch_cfl_finalize_batch(b->acc, b->cfl, b->dt, b->t, b->n, s);
+    for (int st = 0; st < 3 && e == hipSuccess; ++st) {
+        e = launch_stage_batch<R>((const StageArgs<R> *)b->stage_args[st], b->work_plume, b->work_tile, b->nwork,
+                                  b->tx, b->ty, s);
+        if (e == hipSuccess)
+            e = launch_source_fix_batch<R>((const SourceFixArgs<R> *)b->fix_args[st], b->n, b->max_cells, s);
+    }
+    return e == hipSuccess ? CP_OK : bfail(b, CP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int precision, void *hip_stream,
+                    cp_batch **out)
+{
+    if (!out || n < 1 || !meshes || !cases) return CP_EINVAL;
+    *out = nullptr;
+    cp_batch *b = new cp_batch();
+    b->n = n;
+    b->precision = precision;
+    b->stream = (hipStream_t)hip_stream;
+    for (int p = 0; p < n; ++p) {
+        cp_ctx *c = nullptr;
+        int r = cp_create(meshes + p, cases + p, precision, hip_stream, &c);
+        if (r) {
+            cp_batch_destroy(b);
+            return r;
+        }
+        c->tx = b->tx;
+        c->ty = b->ty;
+        b->plumes.push_back(c);
+        b->max_cells = std::max(b->max_cells, c->plane);
+    }
+    std::vector<int> wp, wt;
+    for (int p = 0; p < n; ++p) {
+        const int gx = (b->plumes[p]->nx + b->tx - 1) / b->tx, gy = (b->plumes[p]->nr + b->ty - 1) / b->ty;
+        for (int k = 0; k < gx * gy; ++k) {
+            wp.push_back(p);
+            wt.push_back(k);
+        }
+    }
+    b->nwork = (int)wp.size();
+    b->work_plume = balloc<int>(b, wp.size());
+    b->work_tile = balloc<int>(b, wt.size());
+    b->acc = balloc<unsigned long long>(b, n);
+    b->cfl = balloc<double>(b, n);
+    b->dt = balloc<double>(b, n);
+    b->t = balloc<double>(b, n);
+    if (!b->work_plume || !b->work_tile || !b->acc || !b->cfl || !b->dt || !b->t ||
+        hipStreamCreate(&b->cap_stream) != hipSuccess) {
+        cp_batch_destroy(b);
+        return CP_ENOMEM;
+    }
+    std::vector<unsigned long long> inf(n, 0x7FF0000000000000ull);
+    std::vector<double> cfl(n), zero(n, 0.0);
+    for (int p = 0; p < n; ++p) cfl[p] = cases[p].cfl;
+    if (hipMemcpy(b->work_plume, wp.data(), wp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->work_tile, wt.data(), wt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->acc, inf.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cfl, cfl.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->dt, zero.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->t, zero.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        cp_batch_destroy(b);
+        return CP_EHIP;
+    }
+    *out = b;
+    return CP_OK;
+}
+
+void cp_batch_destroy(cp_batch *b)
+{
+    if (!b) return;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    else hipDeviceSynchronize();
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    for (cp_ctx *c : b->plumes) cp_destroy(c);
+    for (void *p : b->allocs)
+        if (p) hipFree(p);
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    delete b;
+}
+
+int cp_batch_init(cp_batch *b, void *const *U)
+{
+    if (!b || !U) return CP_EINVAL;
+    for (int p = 0; p < b->n; ++p) {
+        int r = cp_init(b->plumes[p], U[p]);
+        if (r) return bfail(b, r, b->plumes[p]->err);
+    }
+    return CP_OK;
+}
+
+int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host)
+{
+    if (!b || !U || nsteps < 0) return CP_EINVAL;
+    for (int p = 0; p < b->n; ++p)
+        if (!U[p]) return bfail(b, CP_EINVAL, "null plume array");
+    const bool same = b->graph && b->graph_U.size() == (size_t)b->n &&
+                      std::equal(b->graph_U.begin(), b->graph_U.end(), U);
+    if (!same) {
+        if (b->graph) {
+            hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        int r = b->precision == CP_FP64 ? batch_upload_args<double>(b, U) : batch_upload_args<float>(b, U);
+        if (r) return r;
+        hipGraph_t g;
+        if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bfail(b, CP_EHIP, "begin capture");
+        r = b->precision == CP_FP64 ? batch_enqueue_step<double>(b, b->cap_stream)
+                                    : batch_enqueue_step<float>(b, b->cap_stream);
+        hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
+        if (r) return r;
+        if (ec != hipSuccess) return bfail(b, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
+        if (hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return bfail(b, CP_EHIP, "graph instantiate");
+        }
+        hipGraphDestroy(g);
+        b->graph_U.assign(U, U + b->n);
+    }
+    if (hipMemsetAsync(b->t, 0, b->n * sizeof(double), b->stream) != hipSuccess) return bfail(b, CP_EHIP, "memset");
+    for (int k = 0; k < nsteps; ++k)
+        if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return bfail(b, CP_EHIP, "graph launch");
+    std::vector<double> t(b->n);
+    if (hipMemcpyAsync(t.data(), b->t, b->n * sizeof(double), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+        return bfail(b, CP_EHIP, "time copy");
+    for (int p = 0; p < b->n; ++p) {
+        int r = check_flag(b->plumes[p]);
+        if (r) return bfail(b, r, "plume " + std::to_string(p) + ": " + b->plumes[p]->err);
+    }
+    if (t_host)
+        for (int p = 0; p < b->n; ++p) t_host[p] = t[p];
+    return CP_OK;
+}
+
+const char *cp_batch_error_string(const cp_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -80,6 +80,14 @@ template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s);
 hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
+template <class R>
+hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int *wt, int nwork, int tx, int ty,
+                              hipStream_t s);
+template <class R>
+hipError_t launch_source_fix_batch(const SourceFixArgs<R> *args, int nplumes, long max_cells, hipStream_t s);
+template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, long max_cells, hipStream_t s);
+hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl, double *dt, double *t, int n,
+                                     hipStream_t s);
 hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s);
 template <class R> hipError_t launch_source(const R *U, R *Q, long n, long plane, double dt, const SourceParams &sp,
                                             unsigned long long *nsub, hipStream_t s);

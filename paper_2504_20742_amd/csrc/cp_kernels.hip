@@ -192,25 +192,26 @@ __device__ __forceinline__ R scalar_face(const R *phi, const R *sl, int a, int b
     return Fm * up - kd * (phi[b] - phi[a]);
 }
 
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so workgroup b
+// takes item xcd*q + min(xcd, rem) + b/8 -- a contiguous band of tiles per XCD, whose
+// neighbouring tiles then share their halos in that XCD's L2.
+__device__ __forceinline__ int xcd_band(int b, int nb)
+{
+    const int xcd = b & 7, q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + (b >> 3);
+}
+
+// One fused SSP-RK3 stage on the TX x TY tile whose first cell is (i0, j0).
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
+__device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0, Tile<R, TX, TY> &t)
 {
     using TileT = Tile<R, TX, TY>;
     constexpr int EX = TileT::EX, NE = TileT::N, NT = TX * TY;
     constexpr int RX = TileT::RX, NRG = TileT::NR;
-    __shared__ TileT t;
     const BcInfo &bc = a.bc;
     const Metrics<R> &m = a.m;
     const int nx = bc.nx, nr = bc.nr;
     const int tid = threadIdx.x;
-    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give
-    // each XCD a contiguous band of tiles and let neighbouring tiles share their
-    // halos in that XCD's L2
-    const int gx = gridDim.x, nb = gx * gridDim.y;
-    const int bid = blockIdx.y * gx + blockIdx.x;
-    const int xcd = bid & 7, q = nb >> 3, rem = nb & 7;
-    const int tb = xcd * q + min(xcd, rem) + (bid >> 3);
-    const int i0 = (tb % gx) * TX, j0 = (tb / gx) * TY;
     const R pref = (R)a.pref;
     const bool axi = bc.geom == 0;
 
@@ -394,18 +395,40 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
     if (bad) atomicOr(a.flag, 1);
 }
 
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
+{
+    __shared__ Tile<R, TX, TY> t;
+    const int gx = gridDim.x;
+    const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
+    stage_tile<R, TX, TY>(a, (tb % gx) * TX, (tb / gx) * TY, t);
+}
+
+// Batched operating points: workgroup b takes work item b (XCD-banded) of a list of
+// (plume, tile) pairs and runs the stage of that plume's tile.
+template <class R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_stage_batch(const StageArgs<R> *args, const int *work_plume,
+                                                        const int *work_tile, int nwork)
+{
+    __shared__ Tile<R, TX, TY> t;
+    const int w = xcd_band(blockIdx.x, nwork);
+    const int p = work_plume[w], tb = work_tile[w];
+    const StageArgs<R> &a = args[p];
+    const int gx = (a.bc.nx + TX - 1) / TX;
+    stage_tile<R, TX, TY>(a, (tb % gx) * TX, (tb / gx) * TY, t);
+}
+
 // Phase-change source of the listed cells: U^(s) += b dt Q(U^(s-1), dt), b the
 // weight of L in the stage (1, 1/4, 2/3).  Q is evaluated in FP64.  Clears the
 // list counter of the next stage.
-template <class R>
-__global__ void __launch_bounds__(256) k_source_fix(SourceFixArgs<R> a)
+template <class R> __device__ __forceinline__ void source_fix_body(const SourceFixArgs<R> &a, int bx, int nbx)
 {
     const int n = (int)min((long)*a.count, a.plane);
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
     const double b = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
     int ns = 0;
     bool bad = false;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    for (int k = bx * blockDim.x + threadIdx.x; k < n; k += nbx * blockDim.x) {
         const long c = a.list[k];
         double Ud[NVAR], Q[NVAR];
         #pragma unroll
@@ -418,10 +441,21 @@ __global__ void __launch_bounds__(256) k_source_fix(SourceFixArgs<R> a)
             bad |= !isfinite(out);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
+    if (bx == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
     if (bad) atomicOr(a.flag, 1);
     for (int o = 32; o > 0; o >>= 1) ns += __shfl_xor(ns, o, 64);
     if ((threadIdx.x & 63) == 0 && ns && a.nsub) atomicAdd(a.nsub, (unsigned long long)ns);
+}
+
+template <class R> __global__ void __launch_bounds__(256) k_source_fix(SourceFixArgs<R> a)
+{
+    source_fix_body(a, blockIdx.x, gridDim.x);
+}
+
+// batched: blockIdx.y selects the plume
+template <class R> __global__ void __launch_bounds__(256) k_source_fix_batch(const SourceFixArgs<R> *args)
+{
+    source_fix_body(args[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ CFL
@@ -456,14 +490,13 @@ __device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &
     return w;
 }
 
-template <class R>
-__global__ void __launch_bounds__(256) k_cfl(CflArgs<R> a)
+template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a, int bx, int nbx)
 {
 #pragma clang fp contract(off)
     const BcInfo &bc = a.bc;
     const int n = bc.nx * bc.nr;
     double best = __builtin_huge_val();
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    for (int c = bx * blockDim.x + threadIdx.x; c < n; c += nbx * blockDim.x) {
         const int i = c % bc.nx, j = c / bc.nx;
         const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
         const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
@@ -498,6 +531,25 @@ __global__ void __launch_bounds__(256) k_cfl(CflArgs<R> a)
         if (b > 0.0) atomicMin(a.acc, (unsigned long long)__double_as_longlong(b));
         else atomicMin(a.acc, 0ull);   // non-positive limit: dt collapses to 0 (reported as CP_EDT)
     }
+}
+
+template <class R> __global__ void __launch_bounds__(256) k_cfl(CflArgs<R> a) { cfl_body(a, blockIdx.x, gridDim.x); }
+
+// batched: blockIdx.y selects the plume, each plume reduces into its own slot
+template <class R> __global__ void __launch_bounds__(256) k_cfl_batch(const CflArgs<R> *args)
+{
+    cfl_body(args[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+__global__ void k_cfl_finalize_batch(unsigned long long *acc, const double *cfl, double *dt, double *t, int n)
+{
+#pragma clang fp contract(off)
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double d = cfl[p] * __longlong_as_double((long long)acc[p]);
+    dt[p] = d;
+    t[p] = t[p] + d;
+    acc[p] = 0x7FF0000000000000ull;
 }
 
 __global__ void k_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t)
@@ -612,6 +664,47 @@ template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty
     return hipErrorInvalidValue;
 }
 
+template <class R, int TX, int TY>
+static hipError_t stage_batch_launch(const StageArgs<R> *args, const int *wp, const int *wt, int nwork, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_stage_batch<R, TX, TY>), dim3(nwork), dim3(TX * TY), 0, s, args, wp, wt, nwork);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int *wt, int nwork, int tx, int ty,
+                              hipStream_t s)
+{
+    if (tx == 32 && ty == 8) return stage_batch_launch<R, 32, 8>(args, wp, wt, nwork, s);
+    if (tx == 16 && ty == 16) return stage_batch_launch<R, 16, 16>(args, wp, wt, nwork, s);
+    if (tx == 64 && ty == 4) return stage_batch_launch<R, 64, 4>(args, wp, wt, nwork, s);
+    if (tx == 32 && ty == 4) return stage_batch_launch<R, 32, 4>(args, wp, wt, nwork, s);
+    if (tx == 16 && ty == 8) return stage_batch_launch<R, 16, 8>(args, wp, wt, nwork, s);
+    return hipErrorInvalidValue;
+}
+
+template <class R>
+hipError_t launch_source_fix_batch(const SourceFixArgs<R> *args, int nplumes, long max_cells, hipStream_t s)
+{
+    int bx = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 256));
+    hipLaunchKernelGGL((k_source_fix_batch<R>), dim3(bx, nplumes), dim3(256), 0, s, args);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, long max_cells, hipStream_t s)
+{
+    int bx = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
+    hipLaunchKernelGGL((k_cfl_batch<R>), dim3(bx, nplumes), dim3(256), 0, s, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl, double *dt, double *t, int n,
+                                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cfl_finalize_batch, dim3((n + 63) / 64), dim3(64), 0, s, acc, cfl, dt, t, n);
+    return hipGetLastError();
+}
+
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
 {
     int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
@@ -667,6 +760,10 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, hipStream_t);                        \
     template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \
+    template hipError_t launch_stage_batch<R>(const StageArgs<R> *, const int *, const int *, int, int, int,   \
+                                              hipStream_t);                                                   \
+    template hipError_t launch_source_fix_batch<R>(const SourceFixArgs<R> *, int, long, hipStream_t);        \
+    template hipError_t launch_cfl_batch<R>(const CflArgs<R> *, int, long, hipStream_t);                     \
     template hipError_t launch_source<R>(const R *, R *, long, long, double, const SourceParams &,           \
                                          unsigned long long *, hipStream_t);                                  \
     template hipError_t launch_init<R>(R *, const double *, int, int, hipStream_t);                           \
