@@ -179,6 +179,33 @@ int cp_batch_init(cp_batch *b, void *const *U);
 int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host);
 const char *cp_batch_error_string(const cp_batch *b);
 
+/* -------------------------------------------------------------- learned source
+ * Multilayer perceptron n_in -> n_hidden -> n_hidden -> n_out with GELU (tanh form)
+ * after each hidden layer, used as a surrogate of the stiff phase-change source.
+ * bfloat16 weights and activations, FP32 accumulation on the matrix cores, FP32
+ * master weights and Adam moments, mean-squared-error loss.  Parameters are flat
+ * FP32 in the order W1[n_in][n_hidden], b1, W2[n_hidden][n_hidden], b2,
+ * W3[n_hidden][n_out], b3 (row-major).  X, T, Y are caller-owned DEVICE arrays,
+ * row-major [rows][features].                                                      */
+typedef struct cp_mlp cp_mlp;
+
+int cp_mlp_create(int n_in, int n_hidden, int n_out, void *hip_stream, cp_mlp **out);
+void cp_mlp_destroy(cp_mlp *mlp);
+long cp_mlp_num_params(const cp_mlp *mlp);
+/* Host FP32 parameters in / out (set also resets the Adam moments).             */
+int cp_mlp_set_params(cp_mlp *mlp, const float *host_params);
+int cp_mlp_get_params(cp_mlp *mlp, float *host_params);
+/* Y[rows][n_out] = network(X[rows][n_in]); X is rounded to bfloat16.            */
+int cp_mlp_forward(cp_mlp *mlp, const float *X, int rows, float *Y);
+/* Forward + backward of the MSE loss mean((Y - T)^2) over rows and outputs; the
+ * gradient is kept for cp_mlp_adam; *loss_host (nullable) gets the loss,
+ * grad_host (nullable, cp_mlp_num_params floats) a host copy of the gradient.
+ * Synchronises the stream.                                                      */
+int cp_mlp_loss_grad(cp_mlp *mlp, const float *X, const float *T, int rows, double *loss_host, float *grad_host);
+/* One Adam step with the last gradient (bias-corrected moments).               */
+int cp_mlp_adam(cp_mlp *mlp, double lr, double beta1, double beta2, double eps);
+const char *cp_mlp_error_string(const cp_mlp *mlp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,15 @@ _SIGS = {
     "cp_batch_init": (_I, [_P, _P]),
     "cp_batch_step_n": (_I, [_P, _P, _I, _DP]),
     "cp_batch_error_string": (ctypes.c_char_p, [_P]),
+    "cp_mlp_create": (_I, [_I, _I, _I, _P, ctypes.POINTER(_P)]),
+    "cp_mlp_destroy": (None, [_P]),
+    "cp_mlp_num_params": (ctypes.c_long, [_P]),
+    "cp_mlp_set_params": (_I, [_P, _P]),
+    "cp_mlp_get_params": (_I, [_P, _P]),
+    "cp_mlp_forward": (_I, [_P, _P, _I, _P]),
+    "cp_mlp_loss_grad": (_I, [_P, _P, _P, _I, _DP, _P]),
+    "cp_mlp_adam": (_I, [_P, _D, _D, _D, _D]),
+    "cp_mlp_error_string": (ctypes.c_char_p, [_P]),
 }
 
 
@@ -296,3 +305,64 @@ class Batch:
         t = (ctypes.c_double * self.n)()
         self._chk(self.L.cp_batch_step_n(self.h, ctypes.cast(self._keep, _P), int(n), t))
         return list(t)
+
+
+class MLP:
+    """BF16 MFMA multilayer perceptron of the C ABI (cp_mlp); X, T, Y are float32
+    CUDA tensors [rows][features]; parameters move as float32 numpy arrays."""
+
+    def __init__(self, n_in=17, n_hidden=256, n_out=15, stream=None):
+        self.L = load()
+        self.dims = (n_in, n_hidden, n_out)
+        h = _P()
+        s = _current_stream() if stream is None else stream
+        rc = self.L.cp_mlp_create(n_in, n_hidden, n_out, s, ctypes.byref(h))
+        if rc != CP_OK:
+            raise ContrailError(rc, "cp_mlp_create failed")
+        self.h = h
+        self.n_params = int(self.L.cp_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cp_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != CP_OK:
+            raise ContrailError(rc, self.L.cp_mlp_error_string(self.h).decode())
+
+    def set_params(self, theta):
+        import numpy as np
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == self.n_params
+        self._chk(self.L.cp_mlp_set_params(self.h, t.ctypes.data))
+
+    def get_params(self):
+        import numpy as np
+        t = np.zeros(self.n_params, dtype=np.float32)
+        self._chk(self.L.cp_mlp_get_params(self.h, t.ctypes.data))
+        return t
+
+    def forward(self, X):
+        import torch
+        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous()
+        Y = torch.empty((X.shape[0], self.dims[2]), dtype=torch.float32, device="cuda")
+        self._chk(self.L.cp_mlp_forward(self.h, X.data_ptr(), int(X.shape[0]), Y.data_ptr()))
+        return Y
+
+    def loss_grad(self, X, T, want_grad=False):
+        import numpy as np
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32) if want_grad else None
+        self._chk(self.L.cp_mlp_loss_grad(self.h, X.data_ptr(), T.data_ptr(), int(X.shape[0]), ctypes.byref(loss),
+                                          g.ctypes.data if want_grad else None))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._chk(self.L.cp_mlp_adam(self.h, float(lr), float(beta1), float(beta2), float(eps)))
