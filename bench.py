@@ -1,15 +1,26 @@
 """Benchmark: cell-updates/s of the SSP-RK3 step at 2048 x 512 on one MI355X.
 
 A cell-update is one cell advanced by one full step (CFL reduction, three fused
-stages with the phase-change source).  The workload is the production jet mesh
-(2048 x 512, axially stretched 1.002, radially clustered about the core lip,
-ambient 218 K / 23.8 kPa / ice RH 1.1, synthetic inputs).  Timed: K steps of the
-captured step graph with inputs resident in HBM, bracketed by synchronisation.
+stages with the phase-change source).  Workloads, all synthetic and seeded:
 
-Prints ONE JSON line.  Headline ``value``: the mixed-precision path (FP32 storage,
-fluxes and RK update, FP64 source); the plain FP64 path is reported beside it.
+* production jet 2048 x 512 (axial stretch 1.002, radial clustering about the core
+  lip, ambient 218 K / 23.8 kPa / ice RH 1.1, lognormal soot), run three ways:
+  plain FP64, mixed precision (FP32 storage, fluxes and RK update; FP64 source),
+  and mixed precision with the learned source attached (the headline);
+* its source-active twin (hydrogen-like core water, cold bypass) on the same
+  mesh, where the phase-change source is live: the same three paths, the gain of
+  the surrogate (mixed exact step time / mixed surrogate step time), the share of
+  active cells it takes, and the error of each path against the FP64 path;
+* 64 plumes of uneven size advanced in one captured graph (mixed precision).
+
+Timed regions: K steps of the captured step graph with inputs resident in HBM,
+bracketed by synchronisation.  The roofline entry is the fused stage kernel of the
+headline path, timed with HIP events on the stream it is launched on.
+
+Prints ONE JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s at 2048x512 (mixed+surrogate vs plain FP64), % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_stage_mixed_2048x512_counters.txt")
+KERNEL_SOURCES = ["paper_2504_20742_amd/csrc/cp_kernels.hip", "paper_2504_20742_amd/csrc/cp_physics.hpp",
+                  "paper_2504_20742_amd/csrc/cp_internal.hpp"]
 
 
 def stage_bytes_per_cell(esz):
@@ -28,17 +42,41 @@ def stage_bytes_per_cell(esz):
     return (2 * 15 * esz + 3 * 15 * esz + 3 * 15 * esz) / 3.0
 
 
-def step_bytes_per_cell(esz):
-    # 3 stages (8 array passes of 15 variables) + CFL pass over 5 gas variables
-    return 8 * 15 * esz + 5 * esz
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def run_path(binding, inputs, precision, steps, warmup, stage_reps):
+def measured_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if
+    it was taken on the kernel sources as they are now (else None)."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    vals = {}
+    for line in open(COUNTER_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False):
     import torch
-    m, c = inputs.config2(0)
     s = binding.Solver(m, c, precision)
     U = s.init()
+    if sur is not None:
+        s.sur_set(sur[0], sur[1])
+        s.set_qmode(binding.CP_Q_SURROGATE)
     s.step_n(U, max(warmup, 1))            # includes autotuning + graph capture
+    d0 = s.diag(U)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -50,16 +88,68 @@ def run_path(binding, inputs, precision, steps, warmup, stage_reps):
     ms = ev0.elapsed_time(ev1)
     cells = m["nx"] * m["nr"]
     d = s.diag(U)
-    stage_ms = s.time_stage(U, stage_reps)
-    esz = 8 if precision == binding.CP_FP64 else 4
     out = dict(cell_updates_per_s=cells * steps / (ms / 1e3), ms_per_step=ms / steps, wall_s=wall,
-               sim_time_s=sim_t, tile=list(s.get_tile()), stage_ms=stage_ms,
-               stage_bytes=stage_bytes_per_cell(esz) * cells, max_lnS_l=d["max_lnS_l"],
-               active_cells=d["active_cells"], esz=esz, cells=cells)
+               sim_time_s=sim_t, tile=list(s.get_tile()), max_lnS_l=d["max_lnS_l"],
+               active_cells=d["active_cells"], esz=8 if precision == binding.CP_FP64 else 4, cells=cells)
+    if sur is not None:
+        n_net = d["surrogate_cells"] - d0["surrogate_cells"]
+        n_fb = d["fallback_cells"] - d0["fallback_cells"]
+        out["network_cell_stages"] = n_net
+        out["fallback_cell_stages"] = n_fb
+        out["network_share"] = n_net / max(n_net + n_fb, 1.0)
+    if stage_reps:
+        out["stage_ms"] = s.time_stage(U, stage_reps)
+        out["stage_bytes"] = stage_bytes_per_cell(out["esz"]) * cells
     s.close()
-    del U
-    torch.cuda.empty_cache()
+    if keep:
+        out["U"] = U
+    else:
+        del U
+        torch.cuda.empty_cache()
     return out
+
+
+def rel_errors(U, Uref):
+    """Relative L2 errors of U against Uref: gas state (rho, rho E, rho Y_v each, and
+    the momentum vector), ice number (v = 9), total condensate+vapour water."""
+    import torch
+    a, b = U.double(), Uref.double()
+
+    def rel(x, y):
+        n = torch.linalg.vector_norm(y)
+        return float(torch.linalg.vector_norm(x - y) / n) if float(n) > 0 else float(x.abs().max())
+
+    mom = float(torch.sqrt(((a[1:3] - b[1:3]) ** 2).sum() / (b[1:3] ** 2).sum()))
+    return {"gas": max(rel(a[0], b[0]), rel(a[3], b[3]), rel(a[4], b[4]), mom), "ice_mu0": rel(a[9], b[9])}
+
+
+def run_source_active(binding, inputs, steps, warmup, log):
+    """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate."""
+    import torch
+    from paper_2504_20742_amd import surrogate
+    m, c = inputs.sa2(0)
+    t0 = time.perf_counter()
+    net, norm, rep = surrogate.build(binding, [(m, c)], snapshots=8, every=25, epochs=8, max_rows=1000000)
+    train_s = time.perf_counter() - t0
+    log("bench: surrogate trained on %d rows in %.1f s (val loss %.3f)" % (rep["rows"], train_s,
+                                                                           rep["final_val_loss"]))
+    res = {}
+    res["fp64"] = run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True)
+    res["mixed"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True)
+    res["mixed_surrogate"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, sur=(net, norm.pack()),
+                                      keep=True)
+    Uref = res["fp64"].pop("U")
+    for k in ("mixed", "mixed_surrogate"):
+        res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)
+    del Uref
+    torch.cuda.empty_cache()
+    out = {k: {kk: v for kk, v in d.items() if kk not in ("esz", "cells", "wall_s")} for k, d in res.items()}
+    out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
+    out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": train_s,
+                                 "val_loss": rep["final_val_loss"]}
+    out["steps"] = steps
+    out["warmup"] = warmup
+    return out, (net, norm)
 
 
 def run_batch(binding, inputs, steps):
@@ -113,36 +203,47 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--stage-reps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--paths", default="fp64,mixed,mixed_surrogate")
+    ap.add_argument("--active-steps", type=int, default=100, help="timed steps of the source-active jet (0: skip)")
+    ap.add_argument("--active-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+              "(multi-GPU sharding is designed but not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2504_20742_amd import binding, inputs
     binding.load()
     torch.cuda.set_device(0)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if a.copy_calib:
         src = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print("bench: copy calibration done (3 x 512 MiB)", file=sys.stderr, flush=True)
+        log("bench: copy calibration done (3 x 512 MiB)")
         del src, dst
+    paths = a.paths.split(",")
+    active = None
+    sur = None
+    if a.active_steps > 0 or "mixed_surrogate" in paths:
+        log("bench: source-active jet 2048x512 (surrogate training, 3 paths x %d steps)" % max(a.active_steps, 1))
+        active, sur = run_source_active(binding, inputs, max(a.active_steps, 1), a.active_warmup, log)
+    m, c = inputs.config2(0)
     res = {}
-    for p in a.paths.split(","):
+    for p in paths:
         prec = binding.CP_FP64 if p == "fp64" else binding.CP_MIXED
-        print("bench: path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps), file=sys.stderr, flush=True)
-        res[p] = run_path(binding, inputs, prec, a.steps, a.warmup, a.stage_reps)
-    head = res.get("mixed") or res.get("fp64")
-    head_name = "mixed" if "mixed" in res else "fp64"
-    dom = head
-    achieved = dom["stage_bytes"] / (dom["stage_ms"] / 1e3) / 1e9
+        log("bench: production jet, path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps))
+        attach = (sur[0], sur[1].pack()) if p == "mixed_surrogate" else None
+        res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach)
+    head_name = "mixed_surrogate" if "mixed_surrogate" in res else ("mixed" if "mixed" in res else "fp64")
+    head = res[head_name]
+    achieved = head["stage_bytes"] / (head["stage_ms"] / 1e3) / 1e9
+    traffic = measured_traffic()
     line = {
         "metric": METRIC,
         "value": head["cell_updates_per_s"],
@@ -154,25 +255,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head_name == "mixed" else "f64",
+        "dtype": "f64" if head_name == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "production jet 2048x512 (x-stretch 1.002, r-clustered), SSP-RK3 CFL 0.5, "
                                "path=%s" % head_name,
                    "nx": 2048, "nr": 512, "cells": head["cells"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage (%s, tile %dx%d)" % (head_name, *head["tile"]),
-                     "bytes_per_launch": dom["stage_bytes"], "ms_per_launch": dom["stage_ms"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_stage (%s, tile %dx%d)" % ("f32" if head["esz"] == 4 else "f64", *head["tile"]),
+                     "bytes_per_launch": head["stage_bytes"], "ms_per_launch": head["stage_ms"]},
         "paths": {k: {kk: v[kk] for kk in ("cell_updates_per_s", "ms_per_step", "stage_ms", "tile",
-                                            "max_lnS_l", "active_cells")} for k, v in res.items()},
+                                            "max_lnS_l", "active_cells") if kk in v} for k, v in res.items()},
     }
-    if "fp64" in res and "mixed" in res:
-        line["mixed_over_fp64"] = res["mixed"]["cell_updates_per_s"] / res["fp64"]["cell_updates_per_s"]
+    if "fp64" in res:
+        line["over_fp64"] = {k: v["cell_updates_per_s"] / res["fp64"]["cell_updates_per_s"]
+                             for k, v in res.items() if k != "fp64"}
+    if active is not None:
+        line["source_active_2048x512"] = active
     if a.batch_steps > 0:
-        print("bench: 64-plume batch, %d steps" % a.batch_steps, file=sys.stderr, flush=True)
+        log("bench: 64-plume batch, %d steps" % a.batch_steps)
         line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)
     if not a.no_cpu:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        log("bench: CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(inputs)
     print(json.dumps(line), flush=True)
 

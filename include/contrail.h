@@ -116,7 +116,9 @@ int cp_residual(cp_ctx *ctx, const void *U, void *R);
 
 /* Phase-change source integrated over dt (Sec. 2.2 rates, evaluated explicitly per
  * cell, Sec. 3.2): Q(U, dt) = (Phi_dt(U) - U) / dt, computed in FP64 for both
- * precisions.  dt > 0, else CP_EDT.                                               */
+ * precisions.  dt > 0, else CP_EDT.  With CP_Q_SURROGATE selected, the cells the
+ * surrogate gate hands to the network get the network's closed source instead
+ * (exactly as a step would use it); every other cell keeps the exact source.       */
 int cp_source(cp_ctx *ctx, const void *U, double dt, void *Q);
 
 /* One SSP-RK3 step of size dt, in place: L(U) = R(U) + Q(U, dt).                 */
@@ -138,8 +140,9 @@ int cp_set_qmode(cp_ctx *ctx, int qmode);
 /* Diagnostics (synchronises): out[0] total water mass per radian
  * (vapour + 4pi/3 (rho_l M3 + rho_s N3), Eq. 25-26), out[1] max ln S_l (Eq. 1),
  * out[2] total ice number, out[3] gas mass, out[4] cells with an active source,
- * out[5] source sub-steps of the last cp_source call, out[6] surrogate cells of the
- * last stage, out[7] fallback cells of the last stage.                           */
+ * out[5] source sub-steps of the last cp_source call, out[6] and out[7] running
+ * totals of the active cells the surrogate (CP_Q_SURROGATE) sent to the network and
+ * to the exact fallback, summed over every stage since cp_sur_set.              */
 int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
 
 /* Tile shape of the stage kernel: (tx, ty) from the built set, or (0, 0) to run the
@@ -205,6 +208,38 @@ int cp_mlp_loss_grad(cp_mlp *mlp, const float *X, const float *T, int rows, doub
 /* One Adam step with the last gradient (bias-corrected moments).               */
 int cp_mlp_adam(cp_mlp *mlp, double lr, double beta1, double beta2, double eps);
 const char *cp_mlp_error_string(const cp_mlp *mlp);
+
+/* Attach a trained 17 -> 15 network as the source of a context (CP_Q_SURROGATE).
+ * The context keeps a pointer (the caller keeps ownership and must keep the network
+ * alive while the mode is used).  norm: n_norm = 117 host floats in the order
+ *   s_in[15], mu_in[17], sd_in[17], lo[17], hi[17], mu_out[15], sd_out[15],
+ *   lnS_gate, lnS_lo, lnS_hi, df_max
+ * Features of an active cell: f_v = asinh(U_v / s_in[v]) for the 15 state variables,
+ * ln dt, log10 max(N_soot, 1), standardised with (mu_in, sd_in).  The network takes
+ * the cell when every standardised feature lies in [lo, hi] and ln S_l in
+ * [lnS_lo, lnS_hi] (the training envelope) and |ln S_l| >= lnS_gate (away from
+ * nucleation onset); otherwise the exact sub-cycled source is used (Sec. 3.2).
+ * Output v (v = 5..12 particle moments, 14 activated soot) is the standardised
+ * increment of f_v over dt: U'_v = s_in[v] sinh(max(f_v + y_v sd_out[v] + mu_out[v], 0)),
+ * Q_v = (U'_v - U_v) / dt.  The remaining sources are closed exactly: vapour sink
+ * -(4 pi/3)(rho_l Q_M3 + rho_s Q_N3) (water conserved, Eq. 25-26), gas mass and
+ * momentum follow the vapour, the gas energy loses the condensate enthalpy, the soot
+ * number is unchanged.  A network cell falls back to the exact source when any
+ * predicted increment exceeds df_max in magnitude, when a particle population is not
+ * realizable after the update (neither empty nor positive, log-convex moments with a
+ * mean radius in [0.1 nm, 1 mm]) or when its vapour would turn negative.  The context allocates its own inference activations (bf16, 2 x n_hidden
+ * + 17 values and 15 floats per cell); the network keeps only the weights.
+ * Attaching a network drops the captured step and leaves a context that was in
+ * CP_Q_SURROGATE in CP_Q_EXACT: select CP_Q_SURROGATE again afterwards.
+ * Errors: CP_EINVAL (null, n_norm != 117, network not 17 -> 15), CP_ENOMEM, CP_EHIP. */
+int cp_sur_set(cp_ctx *ctx, cp_mlp *mlp, const float *norm, int n_norm);
+
+/* Training-set features of every cell of U (the gate's own computation): F is a
+ * caller-owned DEVICE float array [nr*nx][18], row j*nx+i holding
+ *   asinh(U_v / s_in[v]) (v = 0..14), ln dt, log10 max(N_soot, 1), ln S_l
+ * (unstandardised).  s_in: 15 positive host floats.  Stream-ordered, no sync.
+ * Errors: CP_EINVAL, CP_EDT (dt <= 0), CP_EHIP.                                    */
+int cp_sur_features(cp_ctx *ctx, const void *U, double dt, const float *s_in, float *F);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,8 @@ _SIGS = {
     "cp_mlp_loss_grad": (_I, [_P, _P, _P, _I, _DP, _P]),
     "cp_mlp_adam": (_I, [_P, _D, _D, _D, _D]),
     "cp_mlp_error_string": (ctypes.c_char_p, [_P]),
+    "cp_sur_set": (_I, [_P, _P, _P, _I]),
+    "cp_sur_features": (_I, [_P, _P, _D, _P, _P]),
 }
 
 
@@ -243,6 +245,26 @@ class Solver:
         ms = ctypes.c_double()
         self._chk(self.L.cp_time_stage(self.h, _ptr(U), int(reps), ctypes.byref(ms)))
         return ms.value
+
+    def sur_set(self, mlp, norm):
+        """Attach a trained network (an MLP) with its 149-float normalisation."""
+        import numpy as np
+        nm = np.ascontiguousarray(norm, dtype=np.float32)
+        self._sur_keep = (mlp, nm)
+        self._chk(self.L.cp_sur_set(self.h, mlp.h, nm.ctypes.data, int(nm.size)))
+
+    def sur_features(self, U, dt, s_in, F=None):
+        """Per-cell network features [nr*nx][18] (float32 CUDA): 15 scaled states,
+        ln dt, log10 N_soot, ln S_l."""
+        import numpy as np
+        import torch
+        self._check(U)
+        if F is None:
+            F = torch.empty((self.nr * self.nx, 18), dtype=torch.float32, device="cuda")
+        si = np.ascontiguousarray(s_in, dtype=np.float32)
+        assert si.size == NV and F.is_contiguous() and F.numel() == self.nr * self.nx * 18
+        self._chk(self.L.cp_sur_features(self.h, _ptr(U), float(dt), si.ctypes.data, _ptr(F)))
+        return F
 
     def faces(self):
         import numpy as np

@@ -37,6 +37,14 @@ struct cp_ctx {
     unsigned long long *acc_d = nullptr, *nsub_d = nullptr;
     int *flag_d = nullptr;
     int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
+    cp_mlp *mlp = nullptr;                          // learned source (not owned)
+    SurNorm nm{};
+    int *sur_cnt = nullptr, *sur_cells = nullptr, *fb_list = nullptr;
+    unsigned long long *sur_tot = nullptr;   // running totals of network / fallback cells
+    int *src_cnt = nullptr, *src_list = nullptr;   // active cells of a cp_source call
+    uint16_t *sur_X = nullptr, *sur_H1 = nullptr, *sur_H2 = nullptr;   // in-step inference activations
+    float *sur_Y = nullptr;
+    int sur_nh = 0;
     SourceParams sp{};
     int qmode = CP_Q_EXACT;
     int tx = 0, ty = 0;                             // 0: autotune on first use
@@ -275,6 +283,77 @@ SourceFixArgs<R> fix_args(const cp_ctx *c, const void *Uin, void *Uout, int stag
     return a;
 }
 
+template <class R>
+SurArgs<R> sur_args(const cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev)
+{
+    SurArgs<R> a;
+    a.Uin = (const R *)Uin;
+    a.Uout = (R *)Uout;
+    a.dt_dev = dt_dev;
+    a.dt = dt;
+    a.plane = c->plane;
+    a.stage = stage;
+    a.count = c->act_count + stage;
+    a.list = c->act_list;
+    a.cnt = c->sur_cnt;
+    a.mlp_cells = c->sur_cells;
+    a.fb_list = c->fb_list;
+    a.X = c->sur_X;
+    a.Y = c->sur_Y;
+    a.nm = c->nm;
+    a.flag = c->flag_d;
+    a.q_only = 0;
+    return a;
+}
+
+// Learned source for the active cells of a stage: split them (network / exact),
+// run the network on its rows, decode + project + apply, exact source for the rest.
+template <class R>
+int surrogate_stage(cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev, hipStream_t s)
+{
+    SurArgs<R> a = sur_args<R>(c, Uin, Uout, stage, dt, dt_dev);
+    hipError_t e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
+    if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
+    int r = mlp_forward_into(c->mlp, (int)c->plane, c->sur_cnt, c->sur_X, c->sur_H1, c->sur_H2, c->sur_Y, s);
+    if (r) return fail(c, r, "surrogate forward");
+    e = launch_sur_apply<R>(a, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate apply: ") + hipGetErrorString(e));
+    SourceFixArgs<R> f = fix_args<R>(c, Uin, Uout, stage, dt, dt_dev);
+    f.count = c->sur_cnt + 1;
+    f.list = c->fb_list;
+    e = launch_source_fix<R>(f, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("fallback source: ") + hipGetErrorString(e));
+    return CP_OK;
+}
+
+// cp_source in surrogate mode: Q already holds the exact source of every cell; the
+// network's (closed) source replaces it in the cells the gate hands to the network.
+template <class R> int surrogate_source(cp_ctx *c, const void *U, double dt, void *Q)
+{
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemsetAsync(c->src_cnt, 0, sizeof(int), s));
+    hipError_t e = launch_active_list<R>((const R *)U, c->plane, c->src_cnt, c->src_list, s);
+    SurArgs<R> a = sur_args<R>(c, U, Q, 0, dt, nullptr);
+    a.count = c->src_cnt;
+    a.list = c->src_list;
+    a.q_only = 1;
+    if (e == hipSuccess) e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
+    if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
+    int r = mlp_forward_into(c->mlp, (int)c->plane, c->sur_cnt, c->sur_X, c->sur_H1, c->sur_H2, c->sur_Y, s);
+    if (r) return fail(c, r, "surrogate forward");
+    e = launch_sur_apply<R>(a, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate apply: ") + hipGetErrorString(e));
+    return CP_OK;
+}
+
+int surrogate_any(cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev, hipStream_t s)
+{
+    return c->precision == CP_FP64 ? surrogate_stage<double>(c, Uin, Uout, stage, dt, dt_dev, s)
+                                   : surrogate_stage<float>(c, Uin, Uout, stage, dt, dt_dev, s);
+}
+
 int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage, double dt, const double *dt_dev,
               hipStream_t s)
 {
@@ -286,6 +365,7 @@ int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage,
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
     const bool src = stage >= 0 && c->cs.phase_change != 0 && c->qmode != CP_Q_OFF;
     if (!src) return CP_OK;
+    if (c->qmode == CP_Q_SURROGATE) return surrogate_any(c, Uin, Uout, stage, dt, dt_dev, s);
     if (c->precision == CP_FP64)
         e = launch_source_fix<double>(fix_args<double>(c, Uin, Uout, stage, dt, dt_dev), c->plane, s);
     else
@@ -514,6 +594,8 @@ int cp_source(cp_ctx *c, const void *U, double dt, void *Q)
                        : launch_source<float>((const float *)U, (float *)Q, c->plane, c->plane, dt, sp, c->nsub_d,
                                               c->stream);
     if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    if (c->qmode == CP_Q_SURROGATE && sp.enabled)
+        return c->precision == CP_FP64 ? surrogate_source<double>(c, U, dt, Q) : surrogate_source<float>(c, U, dt, Q);
     return CP_OK;
 }
 
@@ -571,11 +653,60 @@ int cp_step_n(cp_ctx *c, void *U, int n, double *t_host)
     return CP_OK;
 }
 
+int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
+{
+    if (!c || !mlp || !norm) return fail(c, CP_EINVAL, "null argument");
+    if (n_norm != (int)(sizeof(SurNorm) / sizeof(float))) return fail(c, CP_EINVAL, "normalisation size");
+    int ni, no;
+    mlp_dims(mlp, &ni, &no);
+    if (ni != 17 || no != 15) return fail(c, CP_EINVAL, "network must map 17 features to 15 sources");
+    // the captured step refers to the previous network and buffers: drop it first
+    if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp = nullptr;
+    if (c->qmode == CP_Q_SURROGATE) c->qmode = CP_Q_EXACT;   // select it again after a new network
+    memcpy(&c->nm, norm, sizeof(SurNorm));
+    if (!c->sur_cnt) {
+        c->sur_cnt = dalloc<int>(c, 3);
+        if (!c->sur_cnt) return fail(c, CP_ENOMEM, "surrogate counters");
+        HIPCHK(c, hipMemset(c->sur_cnt, 0, 3 * sizeof(int)));
+    }
+    if (!c->sur_tot) {
+        c->sur_tot = dalloc<unsigned long long>(c, 2);
+        if (!c->sur_tot) return fail(c, CP_ENOMEM, "surrogate counters");
+        HIPCHK(c, hipMemset(c->sur_tot, 0, 2 * sizeof(unsigned long long)));
+    }
+    if (!c->src_cnt && !(c->src_cnt = dalloc<int>(c, 1))) return fail(c, CP_ENOMEM, "surrogate lists");
+    if (!c->sur_cells && !(c->sur_cells = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
+    if (!c->fb_list && !(c->fb_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
+    if (!c->src_list && !(c->src_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
+    const int nh = mlp_hidden(mlp);
+    if (nh > c->sur_nh) {   // activation buffers for every cell of the mesh
+        for (void *q : {(void *)c->sur_X, (void *)c->sur_H1, (void *)c->sur_H2, (void *)c->sur_Y}) {
+            if (!q) continue;
+            hipFree(q);
+            c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), q));
+        }
+        c->sur_nh = 0;
+        c->sur_X = dalloc<uint16_t>(c, (size_t)c->plane * 17);
+        c->sur_H1 = dalloc<uint16_t>(c, (size_t)c->plane * nh);
+        c->sur_H2 = dalloc<uint16_t>(c, (size_t)c->plane * nh);
+        c->sur_Y = dalloc<float>(c, (size_t)c->plane * 15);
+        if (!c->sur_X || !c->sur_H1 || !c->sur_H2 || !c->sur_Y) return fail(c, CP_ENOMEM, "network activation buffers");
+        c->sur_nh = nh;
+    }
+    c->mlp = mlp;
+    return CP_OK;
+}
+
 int cp_set_qmode(cp_ctx *c, int qmode)
 {
     if (!c) return CP_EINVAL;
-    if (qmode == CP_Q_SURROGATE) return fail(c, CP_EUNSUPPORTED, "surrogate source not loaded");
-    if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF) return fail(c, CP_EINVAL, "bad qmode");
+    if (qmode == CP_Q_SURROGATE && !c->mlp) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
+    if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE) return fail(c, CP_EINVAL, "bad qmode");
     c->qmode = qmode;
     if (c->graph) {
         hipGraphExecDestroy(c->graph);
@@ -604,8 +735,30 @@ int cp_diag(cp_ctx *c, const void *U, double out[8])
     memcpy(&h[1], &bits, 8);
     for (int k = 0; k < 5; ++k) out[k] = h[k];
     out[5] = (double)ns;
-    out[6] = 0.0;
-    out[7] = 0.0;
+    int sc[3] = {0, 0, 0};
+    unsigned long long st[2] = {0, 0};
+    if (c->sur_cnt) {
+        HIPCHK(c, hipMemcpyAsync(sc, c->sur_cnt, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(st, c->sur_tot, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    out[6] = (double)(st[0] + (unsigned long long)(sc[0] - sc[2]));
+    out[7] = (double)(st[1] + (unsigned long long)sc[1]);
+    return CP_OK;
+}
+
+int cp_sur_features(cp_ctx *c, const void *U, double dt, const float *s_in, float *F)
+{
+    if (!c || !U || !s_in || !F) return fail(c, CP_EINVAL, "null argument");
+    if (!(dt > 0.0)) return fail(c, CP_EDT, "dt must be positive");
+    for (int v = 0; v < NVAR; ++v)
+        if (!(s_in[v] > 0.f)) return fail(c, CP_EINVAL, "feature scales must be positive");
+    SurNorm nm{};
+    memcpy(nm.s_in, s_in, sizeof(nm.s_in));
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_sur_features<double>((const double *)U, c->plane, dt, nm, F, c->stream)
+                       : launch_sur_features<float>((const float *)U, c->plane, dt, nm, F, c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
     return CP_OK;
 }
 

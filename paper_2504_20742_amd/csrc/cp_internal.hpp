@@ -74,6 +74,17 @@ template <class R> struct CflArgs {
 };
 
 struct Ctx;   // host context (cp_api.hip)
+}  // namespace cp
+
+struct cp_mlp;
+namespace cp {
+// network hooks used by the solver (cp_mlp.hip).  The solver owns the activation
+// buffers of its in-step inference (bf16 X[rows][n_in], H1, H2 [rows][n_hidden],
+// FP32 Y[rows][n_out]); only the weights belong to the network.
+int mlp_hidden(const cp_mlp *n);
+int mlp_forward_into(cp_mlp *n, int max_rows, const int *rows_dev, const uint16_t *X, uint16_t *H1, uint16_t *H2,
+                     float *Y, hipStream_t s);
+void mlp_dims(const cp_mlp *n, int *n_in, int *n_out);
 
 // launchers (cp_kernels.hip)
 template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s);
@@ -94,6 +105,41 @@ template <class R> hipError_t launch_source(const R *U, R *Q, long n, long plane
 template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, hipStream_t s);
 template <class R> hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol,
                                           double *out, hipStream_t s);
+// normalisation of the learned source (feature / target transforms, envelope)
+struct SurNorm {
+    float s_in[15];            // feature v = asinh(U_v / s_in[v]) for the 15 state variables
+    float mu_in[17], sd_in[17];
+    float lo[17], hi[17];      // envelope of the standardised training features
+    float mu_out[15], sd_out[15];  // output v = standardised increment of feature v over dt
+    float lnS_gate;            // exact source where |ln S_l| < lnS_gate (nucleation onset)
+    float lnS_lo, lnS_hi;      // ln S_l range of the training set (part of the envelope)
+    float df_max;              // trust bound on every predicted feature increment
+};
+
+template <class R> struct SurArgs {
+    const R *Uin;
+    R *Uout;
+    const double *dt_dev;
+    double dt;
+    long plane;
+    int stage;
+    const int *count, *list;   // active cells of the stage
+    int *cnt;                  // [0] cells gated to the network, [1] exact-fallback cells,
+                               // [2] network cells rejected at decode (also in [1])
+    int *mlp_cells, *fb_list;
+    uint16_t *X;               // bf16 features [rows][17]
+    const float *Y;            // network output [rows][15]
+    SurNorm nm;
+    int *flag;
+    int q_only;                // write Q itself to Uout (cp_source) instead of adding b dt Q
+};
+template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s);
+template <class R> hipError_t launch_sur_apply(const SurArgs<R> &a, long max_cells, hipStream_t s);
+hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s);
+template <class R> hipError_t launch_active_list(const R *U, long plane, int *count, int *list, hipStream_t s);
+template <class R>
+hipError_t launch_sur_features(const R *U, long plane, double dt, const SurNorm &nm, float *F, hipStream_t s);
+
 bool tile_supported(int tx, int ty);
 const std::vector<std::pair<int, int>> &tile_list();
 

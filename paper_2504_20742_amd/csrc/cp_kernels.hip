@@ -458,6 +458,184 @@ template <class R> __global__ void __launch_bounds__(256) k_source_fix_batch(con
     source_fix_body(args[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
+// ------------------------------------------------------------------ surrogate
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// Raw network features of one cell (asinh-scaled state, ln dt, log10 of the soot
+// number) and its liquid saturation ln S_l; shared by the gate and the feature
+// export used to build training sets, so both see identical inputs.
+template <class R>
+__device__ __forceinline__ double sur_raw_features(const R *U, long plane, long c, double dt, const float *s_in,
+                                                   float *f)
+{
+    double Ud[NVAR];
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
+    CellThermo th;
+    cell_thermo(Ud, th);
+    const double pv = fmax(Ud[4] * kRv * th.T, kPvFloor);
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) f[v] = asinhf((float)(Ud[v] / (double)s_in[v]));
+    f[15] = (float)log(dt);
+    f[16] = (float)log10(fmax(Ud[13], 1.0));
+    return log(pv) - ln_psat(kSonW, th.T);
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_sur_features(const R *U, long plane, double dt, SurNorm nm, float *F)
+{
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < plane; c += (long)gridDim.x * blockDim.x) {
+        float f[17];
+        const double lnSl = sur_raw_features(U, plane, c, dt, nm.s_in, f);
+        #pragma unroll
+        for (int q = 0; q < 17; ++q) F[c * 18 + q] = f[q];
+        F[c * 18 + 17] = (float)lnSl;
+    }
+}
+
+// Split the active cells: the network takes a cell whose standardised features lie
+// inside the training envelope and whose vapour is not near saturation
+// (|ln S_l| >= lnS_gate); every other cell keeps the exact source.
+template <class R> __global__ void __launch_bounds__(256) k_sur_gate(SurArgs<R> a)
+{
+    const int n = (int)min((long)*a.count, a.plane);
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const long c = a.list[k];
+        float f[17];
+        const double lnSl = sur_raw_features(a.Uin, a.plane, c, dt, a.nm.s_in, f);
+        bool inside = fabs(lnSl) >= (double)a.nm.lnS_gate && lnSl >= (double)a.nm.lnS_lo &&
+                      lnSl <= (double)a.nm.lnS_hi;
+        #pragma unroll
+        for (int q = 0; q < 17; ++q) {
+            f[q] = (f[q] - a.nm.mu_in[q]) / a.nm.sd_in[q];
+            inside = inside && f[q] >= a.nm.lo[q] && f[q] <= a.nm.hi[q];
+        }
+        if (inside) {
+            const int slot = atomicAdd(a.cnt, 1);
+            a.mlp_cells[slot] = (int)c;
+            #pragma unroll
+            for (int q = 0; q < 17; ++q) a.X[(long)slot * 17 + q] = to_bf16(f[q]);
+        } else {
+            const int slot = atomicAdd(a.cnt + 1, 1);
+            a.fb_list[slot] = (int)c;
+        }
+    }
+}
+
+// A particle population after a network update is acceptable when it is empty (at
+// most kNmin particles carrying at most the mass of kNmin 1 mm particles) or when
+// its moments are those of a distribution: positive, log-convex (Cauchy-Schwarz,
+// m1^2 <= m0 m2 and m2^2 <= m1 m3) and with a mean radius between 0.1 nm and 1 mm.
+__device__ __forceinline__ bool sur_population_ok(double m0, double m1, double m2, double m3)
+{
+    if (m0 <= kNmin) return m3 <= kNmin * 1e-9;
+    const double slack = 1.0 + 1e-6;
+    return m1 > 0.0 && m2 > 0.0 && m3 > 0.0 && m1 * m1 <= m0 * m2 * slack && m2 * m2 <= m1 * m3 * slack &&
+           m1 >= m0 * 1e-10 && m1 <= m0 * 1e-3;
+}
+
+// Decode the network output into the particle sources and close the rest exactly.
+// The network predicts, for each particle moment and the activated-soot number, the
+// increment of its feature over dt; the new value s sinh(f + df) (floored at zero)
+// gives Q_v = (U'_v - U_v) / dt.  The vapour sink then follows from the condensate
+// sources (water exactly conserved), the gas mass and momentum follow the vapour,
+// the gas energy loses the enthalpy of the condensed water (the freezing enthalpy
+// cancels between the two condensates) and the soot number is unchanged.  A cell
+// whose vapour would turn negative, or whose result is not finite, is handed to the
+// exact fallback list instead (the fallback kernel runs after this one), and so is
+// one whose predicted increments leave the trust bound df_max or whose populations
+// are not realizable after the update.
+template <class R> __global__ void __launch_bounds__(256) k_sur_apply(SurArgs<R> a)
+{
+    const int n = min(a.cnt[0], (int)a.plane);
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    const double b = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
+    bool bad = false;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const long c = a.mlp_cells[k];
+        double Ud[NVAR], Q[NVAR], Un[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
+        bool trust = true;
+        #pragma unroll
+        for (int v = 5; v < NVAR; ++v) {
+            if (v == 13) continue;
+            const double s = (double)a.nm.s_in[v];
+            const double df = (double)(a.Y[(long)k * 15 + v] * a.nm.sd_out[v] + a.nm.mu_out[v]);
+            trust = trust && fabs(df) <= (double)a.nm.df_max;
+            const double f1 = fmax(asinh(Ud[v] / s) + df, 0.0);
+            Un[v] = s * sinh(f1);
+            Q[v] = (Un[v] - Ud[v]) / dt;
+        }
+        Q[13] = 0.0;
+        trust = trust && sur_population_ok(Un[5], Un[6], Un[7], Un[8]) && sur_population_ok(Un[9], Un[10], Un[11], Un[12]);
+        CellThermo th;
+        cell_thermo(Ud, th);
+        const double ml = kFourThirdsPi * kRhoL * Q[8], ms = kFourThirdsPi * kRhoS * Q[12];
+        Q[4] = -(ml + ms);
+        Q[0] = Q[4];
+        Q[1] = Q[4] * th.u;
+        Q[2] = Q[4] * th.v;
+        const double T = th.T;
+        const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+        const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+        const double hv = kLv0 + kCpv * (T - kTref);
+        const double ke = 0.5 * (th.u * th.u + th.v * th.v);
+        Q[3] = -ml * (hv - hfg + ke) - ms * (hv - hsg + ke);
+        bool ok = trust && Ud[4] + dt * Q[4] >= 0.0;
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(Q[v]);
+        if (!ok) {
+            const int slot = atomicAdd(a.cnt + 1, 1);
+            if (!a.q_only) a.fb_list[slot] = (int)c;   // Q already holds the exact source
+            atomicAdd(a.cnt + 2, 1);
+            continue;
+        }
+        if (a.q_only) {
+            #pragma unroll
+            for (int v = 0; v < NVAR; ++v) a.Uout[v * a.plane + c] = (R)Q[v];
+            continue;
+        }
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+            const R out = a.Uout[v * a.plane + c] + (R)(b * dt * Q[v]);
+            a.Uout[v * a.plane + c] = out;
+            bad |= !isfinite(out);
+        }
+    }
+    if (bad) atomicOr(a.flag, 1);
+}
+
+// Cells whose phase-change source does not vanish identically (the FP64 test the
+// stage kernel applies after its storage-precision pre-filter).
+template <class R> __global__ void __launch_bounds__(256) k_active_list(const R *U, long plane, int *count, int *list)
+{
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < plane; c += (long)gridDim.x * blockDim.x) {
+        double Ud[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
+        CellThermo th;
+        cell_thermo(Ud, th);
+        if (!source_inactive(Ud, th.T)) list[atomicAdd(count, 1)] = (int)c;
+    }
+}
+
+// Fold the previous stage's counts into the running totals and clear them.
+__global__ void k_sur_reset(int *cnt, unsigned long long *tot)
+{
+    tot[0] += (unsigned long long)(cnt[0] - cnt[2]);
+    tot[1] += (unsigned long long)cnt[1];
+    cnt[0] = 0;
+    cnt[1] = 0;
+    cnt[2] = 0;
+}
+
 // ------------------------------------------------------------------ CFL
 // Per-cell limit 1/((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)), written
 // without contraction so that the FP64 result is reproducible operation by
@@ -712,6 +890,41 @@ template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long 
     return hipGetLastError();
 }
 
+template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s)
+{
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
+    hipLaunchKernelGGL((k_sur_gate<R>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_sur_apply(const SurArgs<R> &a, long max_cells, hipStream_t s)
+{
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
+    hipLaunchKernelGGL((k_sur_apply<R>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_sur_features(const R *U, long plane, double dt, const SurNorm &nm, float *F,
+                                                  hipStream_t s)
+{
+    int blocks = (int)std::max<long>(1, std::min<long>((plane + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_sur_features<R>), dim3(blocks), dim3(256), 0, s, U, plane, dt, nm, F);
+    return hipGetLastError();
+}
+
+template <class R> hipError_t launch_active_list(const R *U, long plane, int *count, int *list, hipStream_t s)
+{
+    int blocks = (int)std::max<long>(1, std::min<long>((plane + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_active_list<R>), dim3(blocks), dim3(256), 0, s, U, plane, count, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sur_reset, dim3(1), dim3(1), 0, s, cnt, tot);
+    return hipGetLastError();
+}
+
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s)
 {
     const long n = (long)a.bc.nx * a.bc.nr;
@@ -759,6 +972,10 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
 #define CP_INSTANTIATE(R)                                                                                   \
     template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, hipStream_t);                        \
     template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
+    template hipError_t launch_sur_gate<R>(const SurArgs<R> &, long, hipStream_t);                           \
+    template hipError_t launch_sur_apply<R>(const SurArgs<R> &, long, hipStream_t);                          \
+    template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
+    template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \
     template hipError_t launch_stage_batch<R>(const StageArgs<R> *, const int *, const int *, int, int, int,   \
                                               hipStream_t);                                                   \

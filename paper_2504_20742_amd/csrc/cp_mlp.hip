@@ -67,10 +67,11 @@ template <int EPI> __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g
     __shared__ uint16_t As[64][16 + 4];
     __shared__ uint16_t Bs[16][64 + 4];
     const int M = g.M_dev ? min(*g.M_dev, g.M) : g.M;
-    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-    if (m0 >= M) return;
+    const int n0 = blockIdx.y * 64;
     const int k_begin = blockIdx.z * g.kchunk, k_end = min(g.K, k_begin + g.kchunk);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // grid-stride over 64-row tiles: the row count may only be known on the device
+    for (int m0 = blockIdx.x * 64; m0 < M; m0 += gridDim.x * 64) {
     f32x4 acc[4];
     #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -117,10 +118,11 @@ template <int EPI> __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g
                 g.Hb[m * g.ldh + n] = f2bf(v * gelu_grad_f(g.Zs[m * g.ldz + n]));
             } else {
                 const float z = v + (g.bias ? g.bias[n] : 0.f);
-                g.Cf[m * g.ldc + n] = z;
+                if (g.Cf) g.Cf[m * g.ldc + n] = z;   // pre-activation kept for training only
                 if (EPI == EPI_BIAS_GELU) g.Hb[m * g.ldh + n] = f2bf(gelu_f(z));
             }
         }
+    }
     }
 }
 
@@ -254,7 +256,7 @@ int ensure_cap(cp_mlp *n, long rows)
 template <int EPI>
 hipError_t gemm(const GemmArgs &a, int splits, hipStream_t s)
 {
-    dim3 grid((a.M + 63) / 64, (a.N + 63) / 64, splits);
+    dim3 grid((unsigned)std::min(512, (a.M + 63) / 64), (a.N + 63) / 64, splits);
     hipLaunchKernelGGL((k_gemm_bf16<EPI>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -275,34 +277,47 @@ GemmArgs gargs(const uint16_t *A, long sam, long sak, const uint16_t *B, long sb
     return a;
 }
 
-// Forward pass on n rows already in Xb; M_dev (nullable) caps the rows on the device.
-int forward_rows(cp_mlp *n, int rows, const int *M_dev, hipStream_t s)
+// Activation buffers of one forward pass (Z1, Z2 nullable: inference keeps no
+// pre-activations).
+struct FwdBufs {
+    const uint16_t *X;
+    uint16_t *H1, *H2;
+    float *Z1, *Z2, *Y;
+};
+
+// Forward pass on `rows` rows of b.X; M_dev (nullable) caps the rows on the device.
+int forward_rows(cp_mlp *n, int rows, const int *M_dev, const FwdBufs &b, hipStream_t s)
 {
     const uint16_t *W1 = n->pb + n->off[0], *W2 = n->pb + n->off[2], *W3 = n->pb + n->off[4];
     const float *b1 = n->p + n->off[1], *b2 = n->p + n->off[3], *b3 = n->p + n->off[5];
-    GemmArgs a = gargs(n->Xb, n->n_in, 1, W1, n->n_h, 1, rows, n->n_h, n->n_in);
+    GemmArgs a = gargs(b.X, n->n_in, 1, W1, n->n_h, 1, rows, n->n_h, n->n_in);
     a.M_dev = M_dev;
     a.bias = b1;
-    a.Cf = n->Z1;
+    a.Cf = b.Z1;
     a.ldc = n->n_h;
-    a.Hb = n->H1;
+    a.Hb = b.H1;
     a.ldh = n->n_h;
     if (gemm<EPI_BIAS_GELU>(a, 1, s) != hipSuccess) return mfail(n, CP_EHIP, "gemm 1");
-    a = gargs(n->H1, n->n_h, 1, W2, n->n_h, 1, rows, n->n_h, n->n_h);
+    a = gargs(b.H1, n->n_h, 1, W2, n->n_h, 1, rows, n->n_h, n->n_h);
     a.M_dev = M_dev;
     a.bias = b2;
-    a.Cf = n->Z2;
+    a.Cf = b.Z2;
     a.ldc = n->n_h;
-    a.Hb = n->H2;
+    a.Hb = b.H2;
     a.ldh = n->n_h;
     if (gemm<EPI_BIAS_GELU>(a, 1, s) != hipSuccess) return mfail(n, CP_EHIP, "gemm 2");
-    a = gargs(n->H2, n->n_h, 1, W3, n->n_out, 1, rows, n->n_out, n->n_h);
+    a = gargs(b.H2, n->n_h, 1, W3, n->n_out, 1, rows, n->n_out, n->n_h);
     a.M_dev = M_dev;
     a.bias = b3;
-    a.Cf = n->Yf;
+    a.Cf = b.Y;
     a.ldc = n->n_out;
     if (gemm<EPI_BIAS>(a, 1, s) != hipSuccess) return mfail(n, CP_EHIP, "gemm 3");
     return CP_OK;
+}
+
+int forward_rows(cp_mlp *n, int rows, hipStream_t s)
+{
+    return forward_rows(n, rows, nullptr, FwdBufs{n->Xb, n->H1, n->H2, n->Z1, n->Z2, n->Yf}, s);
 }
 
 // weight gradient dW[K_in][N_out] = A^T dZ over `rows` rows, split over the batch
@@ -332,6 +347,20 @@ int weight_grad(cp_mlp *n, const uint16_t *Aact, int kin, const uint16_t *dZ, in
 }
 
 }  // namespace
+
+namespace cp {
+int mlp_hidden(const cp_mlp *n) { return n->n_h; }
+int mlp_forward_into(cp_mlp *n, int max_rows, const int *rows_dev, const uint16_t *X, uint16_t *H1, uint16_t *H2,
+                     float *Y, hipStream_t s)
+{
+    return forward_rows(n, max_rows, rows_dev, FwdBufs{X, H1, H2, nullptr, nullptr, Y}, s);
+}
+void mlp_dims(const cp_mlp *n, int *n_in, int *n_out)
+{
+    *n_in = n->n_in;
+    *n_out = n->n_out;
+}
+}  // namespace cp
 
 extern "C" {
 
@@ -406,7 +435,7 @@ int cp_mlp_forward(cp_mlp *n, const float *X, int rows, float *Y)
     if (r) return r;
     const long nx = (long)rows * n->n_in;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, n->stream, X, nx, n->Xb);
-    if ((r = forward_rows(n, rows, nullptr, n->stream))) return r;
+    if ((r = forward_rows(n, rows, n->stream))) return r;
     if (hipMemcpyAsync(Y, n->Yf, (long)rows * n->n_out * 4, hipMemcpyDeviceToDevice, n->stream) != hipSuccess)
         return mfail(n, CP_EHIP, "output copy");
     return CP_OK;
@@ -420,7 +449,7 @@ int cp_mlp_loss_grad(cp_mlp *n, const float *X, const float *T, int rows, double
     hipStream_t s = n->stream;
     const long nx = (long)rows * n->n_in, ny = (long)rows * n->n_out;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, X, nx, n->Xb);
-    if ((r = forward_rows(n, rows, nullptr, s))) return r;
+    if ((r = forward_rows(n, rows, s))) return r;
     const int nb = (int)((ny + 255) / 256);
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, n->Yf, T, ny, 1.0f / (float)ny, n->dY, n->lossp);
     const uint16_t *W2 = n->pb + n->off[2], *W3 = n->pb + n->off[4];
