@@ -50,9 +50,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(tile):
     """HBM bytes per stage launch from the committed rocprofv3 counter summary, if
-    it was taken on the kernel sources as they are now (else None)."""
+    it was taken on the kernel sources as they are now and on this tile shape
+    (else None)."""
     if not os.path.exists(COUNTER_FILE):
         return None
     vals = {}
@@ -61,6 +62,8 @@ def measured_traffic():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if vals.get("tile") != "%dx%d" % tuple(tile):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -123,16 +126,24 @@ def rel_errors(U, Uref):
     return {"gas": max(rel(a[0], b[0]), rel(a[3], b[3]), rel(a[4], b[4]), mom), "ice_mu0": rel(a[9], b[9])}
 
 
-def run_source_active(binding, inputs, steps, warmup, log):
-    """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate."""
-    import torch
+def train_surrogate(binding, inputs, log):
+    """The network of the learned source, trained on the source-active jet on the
+    production mesh (exact FP64 source of the library as the teacher)."""
     from paper_2504_20742_amd import surrogate
     m, c = inputs.sa2(0)
     t0 = time.perf_counter()
     net, norm, rep = surrogate.build(binding, [(m, c)], snapshots=8, every=25, epochs=8, max_rows=1000000)
-    train_s = time.perf_counter() - t0
-    log("bench: surrogate trained on %d rows in %.1f s (val loss %.3f)" % (rep["rows"], train_s,
+    rep["seconds"] = time.perf_counter() - t0
+    log("bench: surrogate trained on %d rows in %.1f s (val loss %.3f)" % (rep["rows"], rep["seconds"],
                                                                            rep["final_val_loss"]))
+    return net, norm, rep
+
+
+def run_source_active(binding, inputs, steps, warmup, trained):
+    """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate."""
+    import torch
+    net, norm, rep = trained
+    m, c = inputs.sa2(0)
     res = {}
     res["fp64"] = run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True)
     res["mixed"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True)
@@ -145,11 +156,11 @@ def run_source_active(binding, inputs, steps, warmup, log):
     torch.cuda.empty_cache()
     out = {k: {kk: v for kk, v in d.items() if kk not in ("esz", "cells", "wall_s")} for k, d in res.items()}
     out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
-    out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": train_s,
+    out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": rep["seconds"],
                                  "val_loss": rep["final_val_loss"]}
     out["steps"] = steps
     out["warmup"] = warmup
-    return out, (net, norm)
+    return out
 
 
 def run_batch(binding, inputs, steps):
@@ -229,21 +240,24 @@ def main():
         del src, dst
     paths = a.paths.split(",")
     active = None
-    sur = None
+    trained = None
     if a.active_steps > 0 or "mixed_surrogate" in paths:
-        log("bench: source-active jet 2048x512 (surrogate training, 3 paths x %d steps)" % max(a.active_steps, 1))
-        active, sur = run_source_active(binding, inputs, max(a.active_steps, 1), a.active_warmup, log)
+        trained = train_surrogate(binding, inputs, log)
+    if a.active_steps > 0:
+        log("bench: source-active jet 2048x512, 3 paths x (%d warmup + %d timed steps)"
+            % (a.active_warmup, a.active_steps))
+        active = run_source_active(binding, inputs, a.active_steps, a.active_warmup, trained)
     m, c = inputs.config2(0)
     res = {}
     for p in paths:
         prec = binding.CP_FP64 if p == "fp64" else binding.CP_MIXED
         log("bench: production jet, path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps))
-        attach = (sur[0], sur[1].pack()) if p == "mixed_surrogate" else None
+        attach = (trained[0], trained[1].pack()) if p == "mixed_surrogate" else None
         res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach)
     head_name = "mixed_surrogate" if "mixed_surrogate" in res else ("mixed" if "mixed" in res else "fp64")
     head = res[head_name]
     achieved = head["stage_bytes"] / (head["stage_ms"] / 1e3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(head["tile"])
     line = {
         "metric": METRIC,
         "value": head["cell_updates_per_s"],
