@@ -83,15 +83,15 @@ template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
 // viscosities and limited slopes on the tile plus a 1-cell ring (RX x RY), and one
-// face buffer reused for the x-faces, the r-faces and the scalar slopes.
+// face buffer reused for the x-faces and the r-faces.
 template <class R, int TX, int TY> struct Tile {
     static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
     static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     static constexpr int NFX = (TX + 1) * TY, NFR = TX * (TY + 1);
     static constexpr int NF = NFX > NFR ? NFX : NFR;
-    R rho[N], u[N], v[N], p[N], T[N], Y[N], phi[N];
+    R rho[N], u[N], v[N], p[N], T[N], Y[N];   // u..Y are reused for 5 scalars at a time
     R mu[NR], D[NR], mut[NR];
-    R sx[5][NR], sr[5][NR];      // gas slopes; reused as scalar slopes (sx[0], sr[0])
+    R sx[5][NR], sr[5][NR];      // gas slopes; reused as the scalars' slopes
     R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn
     int code[N];
 };
@@ -192,6 +192,20 @@ __device__ __forceinline__ R scalar_face(const R *phi, const R *sl, int a, int b
     return Fm * up - kd * (phi[b] - phi[a]);
 }
 
+// Slot k of a group of five passive scalars: the primitive arrays are free once the
+// gas fluxes are assembled.
+template <class TileT> __device__ __forceinline__ auto *scalar_slot(TileT &t, int k)
+{
+    return k == 0 ? t.u : (k == 1 ? t.v : (k == 2 ? t.p : (k == 3 ? t.T : t.Y)));
+}
+
+// phi = U / rho with one reciprocal per cell in FP32 (the same rounding as fdiv);
+// IEEE division in FP64.
+__device__ __forceinline__ float inv_rho(float rho) { return __builtin_amdgcn_rcpf(rho); }
+__device__ __forceinline__ double inv_rho(double) { return 0.0; }
+__device__ __forceinline__ float per_mass(float U, float, float ir) { return U * ir; }
+__device__ __forceinline__ double per_mass(double U, double rho, double) { return U / rho; }
+
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so workgroup b
 // takes item xcd*q + min(xcd, rem) + b/8 -- a contiguous band of tiles per XCD, whose
 // neighbouring tiles then share their halos in that XCD's L2.
@@ -247,7 +261,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int i = min(i0 + r % RX - 1, nx), j = min(j0 + r / RX - 1, nr);
         const R T = t.T[l];
         t.mu[r] = sutherland(T);
-        t.D[r] = R(kD0) * exp(R(kDexp) * log(T * R(1.0 / kTref))) * fdiv(R(kP0), t.p[l]);
+        t.D[r] = R(kD0) * fpow_pos(T * R(1.0 / kTref), R(kDexp)) * fdiv(R(kP0), t.p[l]);
         const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
         const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
         t.mut[r] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
@@ -329,23 +343,40 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             res[2] += ((t.p[l] - pref) - ttt) * ir;
         }
     }
-    // phase 5: passive scalars through one LDS slot each, slopes once per cell
-    for (int s = 5; s < NVAR; ++s) {
+    // phase 5: passive scalars, five at a time in the freed primitive arrays, slopes
+    // once per cell.  T of the cell is kept for the source-activity test.
+    const R Tcell = valid ? t.T[l] : R(0);
+    #pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int s0 = 5 + 5 * g;
         __syncthreads();
-        for (int e = tid; e < NE; e += NT) t.phi[e] = fdiv(fetch(a.Uin, a.plane, bc, t.code[e], s), t.rho[e]);
+        for (int e = tid; e < NE; e += NT) {
+            const int code = t.code[e];
+            const R rho = t.rho[e], ir = inv_rho(rho);
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) scalar_slot(t, k)[e] = per_mass(fetch(a.Uin, a.plane, bc, code, s0 + k), rho, ir);
+        }
         __syncthreads();
         for (int r = tid; r < NRG; r += NT) {
             const int le = ext_of_ring<TX, TY>(r);
-            t.sx[0][r] = vl_slope(t.phi[le] - t.phi[le - 1], t.phi[le + 1] - t.phi[le]);
-            t.sr[0][r] = vl_slope(t.phi[le] - t.phi[le - EX], t.phi[le + EX] - t.phi[le]);
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const R *ph = scalar_slot(t, k);
+                t.sx[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
+                t.sr[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
+            }
         }
         __syncthreads();
         if (valid) {
-            const R fw = scalar_face(t.phi, t.sx[0], l - 1, l, rl - 1, rl, Fm0, kd0);
-            const R fe = scalar_face(t.phi, t.sx[0], l, l + 1, rl, rl + 1, Fm1, kd1);
-            const R fsv = (axi && j == 0) ? R(0) : scalar_face(t.phi, t.sr[0], l - EX, l, rl - RX, rl, Fm2, kd2);
-            const R fnv = scalar_face(t.phi, t.sr[0], l, l + EX, rl, rl + RX, Fm3, kd3);
-            res[s] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const R *ph = scalar_slot(t, k);
+                const R fw = scalar_face(ph, t.sx[k], l - 1, l, rl - 1, rl, Fm0, kd0);
+                const R fe = scalar_face(ph, t.sx[k], l, l + 1, rl, rl + 1, Fm1, kd1);
+                const R fsv = (axi && j == 0) ? R(0) : scalar_face(ph, t.sr[k], l - EX, l, rl - RX, rl, Fm2, kd2);
+                const R fnv = scalar_face(ph, t.sr[k], l, l + EX, rl, rl + RX, Fm3, kd3);
+                res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+            }
         }
     }
     if (!valid) return;
@@ -365,7 +396,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     } else {
         const R rdt = (R)dt;
         if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(a.Uin[4 * a.plane + c], a.Uin[5 * a.plane + c],
-                                                                      a.Uin[9 * a.plane + c], t.T[l]))) {
+                                                                      a.Uin[9 * a.plane + c], Tcell))) {
             double Ug[NVAR];
             #pragma unroll
             for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)a.Uin[v * a.plane + c] : 0.0;

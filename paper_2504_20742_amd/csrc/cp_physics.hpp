@@ -54,6 +54,16 @@ struct SourceParams {
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Square root and positive power for the transport terms: IEEE in FP64; the
+// hardware instructions (v_sqrt_f32, v_log_f32 / v_exp_f32, about 1 ulp) in FP32.
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fpow_pos(double x, double e) { return exp(e * log(x)); }
+__device__ __forceinline__ float fpow_pos(float x, float e)
+{
+    return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
+}
+
 // -------------------------------------------------------------- gas model
 template <class R> __device__ __forceinline__ R gas_R(R Y) { return (R(1) - Y) * R(kRa) + Y * R(kRv); }
 template <class R> __device__ __forceinline__ R gas_cp(R Y) { return (R(1) - Y) * R(kCpa) + Y * R(kCpv); }
@@ -73,7 +83,7 @@ template <class R> __device__ __forceinline__ R gas_T(R e, R Y)
 template <class R> __device__ __forceinline__ R sutherland(R T)
 {
     R t = T * R(1.0 / kTref);
-    return fdiv(R(kMu0) * t * sqrt(t) * R(kTref + kSuth), T + R(kSuth));
+    return fdiv(R(kMu0) * t * fsqrt(t) * R(kTref + kSuth), T + R(kSuth));
 }
 
 // ======================================================================
@@ -378,7 +388,7 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R Hr = gas_cp(Yr) * fdiv(pr, rr * gas_R(Yr)) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
     const R ml = rl * unl, mr = rr * unr;
 
-    const R sl = sqrt(rl), sr = sqrt(rr);
+    const R sl = fsqrt(rl), sr = fsqrt(rr);
     const R isum = fdiv(R(1), sl + sr);
     const R wl = sl * isum, wr = sr * isum;
     const R rho = sl * sr;
@@ -391,7 +401,7 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R h0 = gas_h0(Y);
     const R T = fdiv(H - R(0.5) * q2 - h0, cpm);
     const R c2 = fdiv(cpm, cpm - Rm) * Rm * T;
-    const R c = sqrt(c2);
+    const R c = fsqrt(c2);
     const R ic2 = fdiv(R(1), c2);
 
     const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
