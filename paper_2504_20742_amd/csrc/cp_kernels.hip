@@ -229,11 +229,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     const R pref = (R)a.pref;
     const bool axi = bc.geom == 0;
 
+    // A tile whose 2-cell halo lies inside the mesh (most tiles) addresses its cells
+    // directly; only boundary tiles go through the ghost-cell mapping.
+    const bool inner = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= nx && j0 + TY + 2 <= nr;
+
     // phase 1: gas primitives of tile + halo
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
         const int i = min(i0 + ex - 2, nx + 1), j = min(j0 + ey - 2, nr + 1);
-        const CellSrc cs = map_cell(i, j, bc);
+        const CellSrc cs = inner ? CellSrc{j * nx + i, false, false} : map_cell(i, j, bc);
         const R U0 = fetch(a.Uin, a.plane, bc, cs.code, 0);
         R U1 = fetch(a.Uin, a.plane, bc, cs.code, 1);
         R U2 = fetch(a.Uin, a.plane, bc, cs.code, 2);
@@ -350,11 +354,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     for (int g = 0; g < 2; ++g) {
         const int s0 = 5 + 5 * g;
         __syncthreads();
-        for (int e = tid; e < NE; e += NT) {
-            const int code = t.code[e];
-            const R rho = t.rho[e], ir = inv_rho(rho);
-            #pragma unroll
-            for (int k = 0; k < 5; ++k) scalar_slot(t, k)[e] = per_mass(fetch(a.Uin, a.plane, bc, code, s0 + k), rho, ir);
+        if (inner) {
+            for (int e = tid; e < NE; e += NT) {
+                const R *src = a.Uin + (long)s0 * a.plane + t.code[e];
+                const R rho = t.rho[e], ir = inv_rho(rho);
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) scalar_slot(t, k)[e] = per_mass(src[k * a.plane], rho, ir);
+            }
+        } else {
+            for (int e = tid; e < NE; e += NT) {
+                const int code = t.code[e];
+                const R rho = t.rho[e], ir = inv_rho(rho);
+                #pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    scalar_slot(t, k)[e] = per_mass(fetch(a.Uin, a.plane, bc, code, s0 + k), rho, ir);
+            }
         }
         __syncthreads();
         for (int r = tid; r < NRG; r += NT) {
@@ -844,7 +858,7 @@ __global__ void __launch_bounds__(256) k_diag(const R *U, long plane, int nx, in
 }
 
 // ------------------------------------------------------------------ launchers
-static const std::vector<std::pair<int, int>> kTiles = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}};
+static const std::vector<std::pair<int, int>> kTiles = {{32, 8}, {16, 16}, {64, 4}, {32, 4}, {16, 8}, {32, 16}, {64, 8}};
 
 const std::vector<std::pair<int, int>> &tile_list() { return kTiles; }
 
@@ -870,6 +884,8 @@ template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty
     if (tx == 64 && ty == 4) return stage_launch<R, 64, 4>(a, s);
     if (tx == 32 && ty == 4) return stage_launch<R, 32, 4>(a, s);
     if (tx == 16 && ty == 8) return stage_launch<R, 16, 8>(a, s);
+    if (tx == 32 && ty == 16) return stage_launch<R, 32, 16>(a, s);
+    if (tx == 64 && ty == 8) return stage_launch<R, 64, 8>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -889,6 +905,8 @@ hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int
     if (tx == 64 && ty == 4) return stage_batch_launch<R, 64, 4>(args, wp, wt, nwork, s);
     if (tx == 32 && ty == 4) return stage_batch_launch<R, 32, 4>(args, wp, wt, nwork, s);
     if (tx == 16 && ty == 8) return stage_batch_launch<R, 16, 8>(args, wp, wt, nwork, s);
+    if (tx == 32 && ty == 16) return stage_batch_launch<R, 32, 16>(args, wp, wt, nwork, s);
+    if (tx == 64 && ty == 8) return stage_batch_launch<R, 64, 8>(args, wp, wt, nwork, s);
     return hipErrorInvalidValue;
 }
 

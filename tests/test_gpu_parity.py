@@ -139,7 +139,7 @@ def test_200_steps_fp64(B, orc, which):
 def test_tile_shapes_bitwise_identical(B, orc):
     m, c = inputs.mesh(70, 37), inputs.sa1(3)[1]
     res = []
-    for tx, ty in ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8)):
+    for tx, ty in ((32, 8), (16, 16), (64, 4), (32, 4), (16, 8), (32, 16), (64, 8)):
         s = B.Solver(m, c)
         s.set_tile(tx, ty)
         U = s.init()
