@@ -82,8 +82,8 @@ template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 }
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
-// viscosities and limited slopes on the tile plus a 1-cell ring (RX x RY), and one
-// face buffer reused for the x-faces and the r-faces.
+// viscosities and limited slopes of one direction on the tile plus a 1-cell ring
+// (RX x RY), and one face buffer reused for the x-faces and the r-faces.
 template <class R, int TX, int TY> struct Tile {
     static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
     static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
@@ -91,9 +91,11 @@ template <class R, int TX, int TY> struct Tile {
     static constexpr int NF = NFX > NFR ? NFX : NFR;
     R rho[N], u[N], v[N], p[N], T[N], Y[N];   // u..Y are reused for 5 scalars at a time
     R mu[NR], D[NR], mut[NR];
-    R sx[5][NR], sr[5][NR];      // gas slopes; reused as the scalars' slopes
-    R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn
+    R sl[5][NR];                 // slopes of one direction (x, then r); the scalars' x slopes
+    R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn;
+                                 // the scalars' r slopes during the scalar phase
     int code[N];
+    static_assert(7 * NF >= 5 * NR, "face buffer must hold five ring arrays");
 };
 
 // ext index of ring cell r, and ring index of ext cell e (inside the ring)
@@ -116,7 +118,7 @@ __device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, 
                                          R inv_d2t, R inv_r, R pref, R *F, R &Fm, R &kd)
 {
     const int b = a + s;
-    const R(*sl)[TileT::NR] = xdir ? t.sx : t.sr;
+    const R(*sl)[TileT::NR] = t.sl;   // slopes of the face-normal direction
     const R *un_ = xdir ? t.u : t.v;
     const R *ut_ = xdir ? t.v : t.u;
     R qL[5], qR[5];
@@ -271,10 +273,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         t.mut[r] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
         const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
         #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            t.sx[k][r] = vl_slope(w[k][l] - w[k][l - 1], w[k][l + 1] - w[k][l]);
-            t.sr[k][r] = vl_slope(w[k][l] - w[k][l - EX], w[k][l + EX] - w[k][l]);
-        }
+        for (int k = 0; k < 5; ++k) t.sl[k][r] = vl_slope(w[k][l] - w[k][l - 1], w[k][l + 1] - w[k][l]);
     }
     __syncthreads();
 
@@ -309,6 +308,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         kd0 = t.face[6][fw];
         Fm1 = t.face[5][fw + 1];
         kd1 = t.face[6][fw + 1];
+    }
+    // r-direction gas slopes, over the x slopes the x-faces no longer need
+    for (int r = tid; r < NRG; r += NT) {
+        const int le = ext_of_ring<TX, TY>(r);
+        const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
+        #pragma unroll
+        for (int k = 0; k < 5; ++k) t.sl[k][r] = vl_slope(w[k][le] - w[k][le - EX], w[k][le + EX] - w[k][le]);
     }
     __syncthreads();
     // phase 4: r-faces, each once (the axis face has zero area)
@@ -371,13 +377,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
         }
         __syncthreads();
+        R(*srs)[NRG] = reinterpret_cast<R(*)[NRG]>(&t.face[0][0]);   // r slopes in the free face buffer
         for (int r = tid; r < NRG; r += NT) {
             const int le = ext_of_ring<TX, TY>(r);
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const R *ph = scalar_slot(t, k);
-                t.sx[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
-                t.sr[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
+                t.sl[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
+                srs[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
             }
         }
         __syncthreads();
@@ -385,10 +392,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const R *ph = scalar_slot(t, k);
-                const R fw = scalar_face(ph, t.sx[k], l - 1, l, rl - 1, rl, Fm0, kd0);
-                const R fe = scalar_face(ph, t.sx[k], l, l + 1, rl, rl + 1, Fm1, kd1);
-                const R fsv = (axi && j == 0) ? R(0) : scalar_face(ph, t.sr[k], l - EX, l, rl - RX, rl, Fm2, kd2);
-                const R fnv = scalar_face(ph, t.sr[k], l, l + EX, rl, rl + RX, Fm3, kd3);
+                const R fw = scalar_face(ph, t.sl[k], l - 1, l, rl - 1, rl, Fm0, kd0);
+                const R fe = scalar_face(ph, t.sl[k], l, l + 1, rl, rl + 1, Fm1, kd1);
+                const R fsv = (axi && j == 0) ? R(0) : scalar_face(ph, srs[k], l - EX, l, rl - RX, rl, Fm2, kd2);
+                const R fnv = scalar_face(ph, srs[k], l, l + EX, rl, rl + RX, Fm3, kd3);
                 res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
             }
         }
