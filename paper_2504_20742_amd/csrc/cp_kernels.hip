@@ -499,7 +499,9 @@ template <class R> __device__ __forceinline__ void source_fix_body(const SourceF
     if ((threadIdx.x & 63) == 0 && ns && a.nsub) atomicAdd(a.nsub, (unsigned long long)ns);
 }
 
-template <class R> __global__ void __launch_bounds__(256) k_source_fix(SourceFixArgs<R> a)
+// One wavefront per workgroup: the active cells are a small, compact fraction of
+// the mesh, so they are spread over as many compute units as possible.
+template <class R> __global__ void __launch_bounds__(64) k_source_fix(SourceFixArgs<R> a)
 {
     source_fix_body(a, blockIdx.x, gridDim.x);
 }
@@ -720,9 +722,54 @@ __device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &
     return w;
 }
 
-template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a, int bx, int nbx)
+// Time-step limit of cell (i, j) from its primitives and the neighbour velocities
+// that enter the eddy viscosity.
+template <class R>
+__device__ __forceinline__ double cfl_limit(const CflArgs<R> &a, int i, int j, const PrimD &w, double uN, double uS,
+                                            double vE, double vW)
 {
 #pragma clang fp contract(off)
+    const double dudr = (uN - uS) / (a.rc[j + 3] - a.rc[j + 1]);
+    const double dvdx = (vE - vW) / (a.xc[i + 3] - a.xc[i + 1]);
+    const double lm = a.kappa_m * (a.delta0 + a.s_delta * a.xc[i + 2]);
+    const double mut = w.rho * lm * lm * fabs(dudr + dvdx);
+    const double Rm = (1.0 - w.Y) * kRa + w.Y * kRv;
+    const double cpm = (1.0 - w.Y) * kCpa + w.Y * kCpv;
+    const double cvm = (1.0 - w.Y) * kCva + w.Y * kCvv;
+    const double gam = cpm / cvm;
+    const double snd = sqrt(gam * Rm * w.T);
+    const double t = w.T / kTref;
+    const double mu = kMu0 * t * sqrt(t) * (kTref + kSuth) / (w.T + kSuth);
+    double fac = gam / kPr;
+    if (fac < 4.0 / 3.0) fac = 4.0 / 3.0;
+    const double nu = (mu + mut) / w.rho * fac;
+    const double idx = a.inv_dx[i], idr = a.inv_dr[j];
+    const double rate = (fabs(w.u) + snd) * idx + (fabs(w.v) + snd) * idr + 2.0 * nu * (idx * idx + idr * idr);
+    return 1.0 / rate;
+}
+
+// Block minimum (wavefront shuffles, then LDS) merged into the running minimum.
+// The running minimum only decreases, so a block whose minimum is not below the
+// value it reads (possibly an older, larger one) has nothing to merge: this keeps
+// the atomics on the single reduction word to a few per launch instead of one per
+// workgroup, which would serialise.
+__device__ __forceinline__ void cfl_block_min(double best, unsigned long long *acc)
+{
+    for (int o = 32; o > 0; o >>= 1) best = fmin(best, __shfl_xor(best, o, 64));
+    __shared__ double part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = part[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmin(b, part[k]);
+        // non-positive limit: dt collapses to 0 (reported as CP_EDT)
+        const unsigned long long key = b > 0.0 ? (unsigned long long)__double_as_longlong(b) : 0ull;
+        if (key < __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(acc, key);
+    }
+}
+
+template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a, int bx, int nbx)
+{
     const BcInfo &bc = a.bc;
     const int n = bc.nx * bc.nr;
     double best = __builtin_huge_val();
@@ -731,39 +778,42 @@ template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a,
         const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
         const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
         const double vE = cfl_prim(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim(a.U, a.plane, bc, i - 1, j).v;
-        const double dudr = (uN - uS) / (a.rc[j + 3] - a.rc[j + 1]);
-        const double dvdx = (vE - vW) / (a.xc[i + 3] - a.xc[i + 1]);
-        const double lm = a.kappa_m * (a.delta0 + a.s_delta * a.xc[i + 2]);
-        const double mut = w.rho * lm * lm * fabs(dudr + dvdx);
-        const double Rm = (1.0 - w.Y) * kRa + w.Y * kRv;
-        const double cpm = (1.0 - w.Y) * kCpa + w.Y * kCpv;
-        const double cvm = (1.0 - w.Y) * kCva + w.Y * kCvv;
-        const double gam = cpm / cvm;
-        const double snd = sqrt(gam * Rm * w.T);
-        const double t = w.T / kTref;
-        const double mu = kMu0 * t * sqrt(t) * (kTref + kSuth) / (w.T + kSuth);
-        double fac = gam / kPr;
-        if (fac < 4.0 / 3.0) fac = 4.0 / 3.0;
-        const double nu = (mu + mut) / w.rho * fac;
-        const double idx = a.inv_dx[i], idr = a.inv_dr[j];
-        const double rate = (fabs(w.u) + snd) * idx + (fabs(w.v) + snd) * idr + 2.0 * nu * (idx * idx + idr * idr);
-        const double d = 1.0 / rate;
+        const double d = cfl_limit(a, i, j, w, uN, uS, vE, vW);
         if (d < best) best = d;
     }
-    // wavefront min (64 lanes) then block min through LDS
-    for (int o = 32; o > 0; o >>= 1) best = fmin(best, __shfl_xor(best, o, 64));
-    __shared__ double part[4];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = part[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmin(b, part[k]);
-        if (b > 0.0) atomicMin(a.acc, (unsigned long long)__double_as_longlong(b));
-        else atomicMin(a.acc, 0ull);   // non-positive limit: dt collapses to 0 (reported as CP_EDT)
-    }
+    cfl_block_min(best, a.acc);
 }
 
-template <class R> __global__ void __launch_bounds__(256) k_cfl(CflArgs<R> a) { cfl_body(a, blockIdx.x, gridDim.x); }
+// Tiled form: the primitives of a BX x BY tile and its 1-cell ring are computed
+// once into LDS and shared by the neighbouring cells' limits (same arithmetic as
+// cfl_body, so the minimum is bit-identical).
+template <class R, int BX, int BY> __global__ void __launch_bounds__(BX *BY) k_cfl_tile(CflArgs<R> a)
+{
+    constexpr int EXC = BX + 2, NEC = EXC * (BY + 2);
+    __shared__ double pr[5][NEC];
+    const BcInfo &bc = a.bc;
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    for (int e = threadIdx.x; e < NEC; e += BX * BY) {
+        const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
+        const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
+        pr[0][e] = w.rho;
+        pr[1][e] = w.u;
+        pr[2][e] = w.v;
+        pr[3][e] = w.T;
+        pr[4][e] = w.Y;
+    }
+    __syncthreads();
+    double best = __builtin_huge_val();
+    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i < bc.nx && j < bc.nr) {
+        const int l = (ty + 1) * EXC + tx + 1;
+        const PrimD w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
+        const double d = cfl_limit(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
+        if (d < best) best = d;
+    }
+    cfl_block_min(best, a.acc);
+}
 
 // batched: blockIdx.y selects the plume, each plume reduces into its own slot
 template <class R> __global__ void __launch_bounds__(256) k_cfl_batch(const CflArgs<R> *args)
@@ -941,8 +991,8 @@ hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
 
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
 {
-    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
-    hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(256), 0, s, a);
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 4096));
+    hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -983,9 +1033,9 @@ hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s)
 
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s)
 {
-    const long n = (long)a.bc.nx * a.bc.nr;
-    int blocks = (int)std::min<long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL((k_cfl<R>), dim3(blocks), dim3(256), 0, s, a);
+    constexpr int BX = 64, BY = 4;
+    dim3 grid((a.bc.nx + BX - 1) / BX, (a.bc.nr + BY - 1) / BY);
+    hipLaunchKernelGGL((k_cfl_tile<R, BX, BY>), grid, dim3(BX * BY), 0, s, a);
     return hipGetLastError();
 }
 
