@@ -78,7 +78,7 @@ __device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int 
 template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 {
     // van Leer limiter in harmonic form: 2ab/(a+b) where a, b have the same sign
-    return (a * b > R(0)) ? fdiv(R(2) * a * b, a + b) : R(0);
+    return (a * b > R(0)) ? tdiv(R(2) * a * b, a + b) : R(0);
 }
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
@@ -201,12 +201,9 @@ template <class TileT> __device__ __forceinline__ auto *scalar_slot(TileT &t, in
     return k == 0 ? t.u : (k == 1 ? t.v : (k == 2 ? t.p : (k == 3 ? t.T : t.Y)));
 }
 
-// phi = U / rho with one reciprocal per cell in FP32 (the same rounding as fdiv);
-// IEEE division in FP64.
-__device__ __forceinline__ float inv_rho(float rho) { return __builtin_amdgcn_rcpf(rho); }
-__device__ __forceinline__ double inv_rho(double) { return 0.0; }
-__device__ __forceinline__ float per_mass(float U, float, float ir) { return U * ir; }
-__device__ __forceinline__ double per_mass(double U, double rho, double) { return U / rho; }
+// phi = U / rho with one transport reciprocal per cell and group.
+template <class R> __device__ __forceinline__ R inv_rho(R rho) { return trcp(rho); }
+template <class R> __device__ __forceinline__ R per_mass(R U, R, R ir) { return U * ir; }
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so workgroup b
 // takes item xcd*q + min(xcd, rem) + b/8 -- a contiguous band of tiles per XCD, whose
@@ -247,10 +244,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const R U4 = fetch(a.Uin, a.plane, bc, cs.code, 4);
         if (cs.fu) U1 = -U1;
         if (cs.fv) U2 = -U2;
-        const R ir = fdiv(R(1), U0);
+        const R ir = trcp(U0);
         const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
         const R eint = U3 * ir - R(0.5) * (u * u + v * v);
-        const R T = fdiv(eint + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
+        const R T = tdiv(eint + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
         t.code[e] = cs.code;
         t.rho[e] = U0;
         t.u[e] = u;
@@ -266,8 +263,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int l = ext_of_ring<TX, TY>(r);
         const int i = min(i0 + r % RX - 1, nx), j = min(j0 + r / RX - 1, nr);
         const R T = t.T[l];
-        t.mu[r] = sutherland(T);
-        t.D[r] = R(kD0) * fpow_pos(T * R(1.0 / kTref), R(kDexp)) * fdiv(R(kP0), t.p[l]);
+        t.mu[r] = sutherland_t(T);
+        t.D[r] = R(kD0) * fpow_pos(T * R(1.0 / kTref), R(kDexp)) * tdiv(R(kP0), t.p[l]);
         const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
         const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
         t.mut[r] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);

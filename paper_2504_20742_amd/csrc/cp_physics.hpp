@@ -54,6 +54,24 @@ struct SourceParams {
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Division for the transport terms: FP32 as fdiv; FP64 from the hardware
+// reciprocal refined by two Newton steps, with one residual correction of the
+// quotient (within about 1 ulp of the IEEE quotient, at a fraction of its cost).
+// The phase-change source keeps IEEE division.
+__device__ __forceinline__ double trcp(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    return fma(fma(-b, r, 1.0), r, r);
+}
+__device__ __forceinline__ float trcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double tdiv(double a, double b)
+{
+    const double r = trcp(b), q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ float tdiv(float a, float b) { return fdiv(a, b); }
+
 // Square root and positive power for the transport terms: IEEE in FP64; the
 // hardware instructions (v_sqrt_f32, v_log_f32 / v_exp_f32, about 1 ulp) in FP32.
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
@@ -84,6 +102,12 @@ template <class R> __device__ __forceinline__ R sutherland(R T)
 {
     R t = T * R(1.0 / kTref);
     return fdiv(R(kMu0) * t * fsqrt(t) * R(kTref + kSuth), T + R(kSuth));
+}
+// the same law with the transport division, for the flux kernels
+template <class R> __device__ __forceinline__ R sutherland_t(R T)
+{
+    R t = T * R(1.0 / kTref);
+    return tdiv(R(kMu0) * t * fsqrt(t) * R(kTref + kSuth), T + R(kSuth));
 }
 
 // ======================================================================
@@ -384,12 +408,12 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
 {
     const R rl = qL[0], unl = qL[1], utl = qL[2], pl = qL[3], Yl = qL[4];
     const R rr = qR[0], unr = qR[1], utr = qR[2], pr = qR[3], Yr = qR[4];
-    const R Hl = gas_cp(Yl) * fdiv(pl, rl * gas_R(Yl)) + gas_h0(Yl) + R(0.5) * (unl * unl + utl * utl);
-    const R Hr = gas_cp(Yr) * fdiv(pr, rr * gas_R(Yr)) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
+    const R Hl = gas_cp(Yl) * tdiv(pl, rl * gas_R(Yl)) + gas_h0(Yl) + R(0.5) * (unl * unl + utl * utl);
+    const R Hr = gas_cp(Yr) * tdiv(pr, rr * gas_R(Yr)) + gas_h0(Yr) + R(0.5) * (unr * unr + utr * utr);
     const R ml = rl * unl, mr = rr * unr;
 
     const R sl = fsqrt(rl), sr = fsqrt(rr);
-    const R isum = fdiv(R(1), sl + sr);
+    const R isum = tdiv(R(1), sl + sr);
     const R wl = sl * isum, wr = sr * isum;
     const R rho = sl * sr;
     const R un = wl * unl + wr * unr;
@@ -399,10 +423,10 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R q2 = un * un + ut * ut;
     const R cpm = gas_cp(Y), Rm = gas_R(Y);
     const R h0 = gas_h0(Y);
-    const R T = fdiv(H - R(0.5) * q2 - h0, cpm);
-    const R c2 = fdiv(cpm, cpm - Rm) * Rm * T;
+    const R T = tdiv(H - R(0.5) * q2 - h0, cpm);
+    const R c2 = tdiv(cpm, cpm - Rm) * Rm * T;
     const R c = fsqrt(c2);
-    const R ic2 = fdiv(R(1), c2);
+    const R ic2 = tdiv(R(1), c2);
 
     const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
     const R i2c2 = R(0.5) * ic2;
@@ -413,8 +437,8 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     R l1 = fabs(un - c), l4 = fabs(un + c);
     const R l2 = fabs(un);
     const R del = R(0.1) * c;
-    if (l1 < del) l1 = fdiv(l1 * l1 + del * del, R(2) * del);
-    if (l4 < del) l4 = fdiv(l4 * l4 + del * del, R(2) * del);
+    if (l1 < del) l1 = tdiv(l1 * l1 + del * del, R(2) * del);
+    if (l4 < del) l4 = tdiv(l4 * l4 + del * del, R(2) * del);
     const R w1 = l1 * a1, w2 = l2 * a2, w3 = l2 * a3, w4 = l4 * a4;
     // eigenvectors: (1, un-c, ut, H-un c), (1, un, ut, q2/2 + h0), (0, 0, 1, ut), (1, un+c, ut, H+un c)
     F[0] = R(0.5) * (ml + mr) - R(0.5) * (w1 + w2 + w4);
