@@ -78,7 +78,8 @@ __device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int 
 template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 {
     // van Leer limiter in harmonic form: 2ab/(a+b) where a, b have the same sign
-    return (a * b > R(0)) ? tdiv(R(2) * a * b, a + b) : R(0);
+    const R q = tdiv(R(2) * a * b, a + b);   // selected away where a b <= 0
+    return (a * b > R(0)) ? q : R(0);
 }
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
@@ -187,11 +188,15 @@ template <class R> __device__ __forceinline__ R assemble_r(R rx, R fn, R an, R f
 
 // Passive scalar flux through a face: upwind MUSCL value (from the cell slopes)
 // times the Roe mass flux, minus eddy diffusion.
+// Both one-sided states are formed and the upwind one selected, so the flux is
+// branch-free (no divergent LDS reads).
 template <class R>
 __device__ __forceinline__ R scalar_face(const R *phi, const R *sl, int a, int b, int ra, int rb, R Fm, R kd)
 {
-    const R up = Fm >= R(0) ? phi[a] + R(0.5) * sl[ra] : phi[b] - R(0.5) * sl[rb];
-    return Fm * up - kd * (phi[b] - phi[a]);
+    const R pa = phi[a], pb = phi[b];
+    const R upL = pa + R(0.5) * sl[ra];
+    const R upR = pb - R(0.5) * sl[rb];
+    return Fm * (Fm >= R(0) ? upL : upR) - kd * (pb - pa);
 }
 
 // Slot k of a group of five passive scalars: the primitive arrays are free once the
@@ -391,7 +396,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R *ph = scalar_slot(t, k);
                 const R fw = scalar_face(ph, t.sl[k], l - 1, l, rl - 1, rl, Fm0, kd0);
                 const R fe = scalar_face(ph, t.sl[k], l, l + 1, rl, rl + 1, Fm1, kd1);
-                const R fsv = (axi && j == 0) ? R(0) : scalar_face(ph, srs[k], l - EX, l, rl - RX, rl, Fm2, kd2);
+                const R fs_raw = scalar_face(ph, srs[k], l - EX, l, rl - RX, rl, Fm2, kd2);
+                const R fsv = (axi && j == 0) ? R(0) : fs_raw;   // zero-area axis face
                 const R fnv = scalar_face(ph, srs[k], l, l + EX, rl, rl + RX, Fm3, kd3);
                 res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
             }
