@@ -48,13 +48,23 @@ struct cp_ctx {
     SourceParams sp{};
     int qmode = CP_Q_EXACT;
     int tx = 0, ty = 0;                             // 0: autotune on first use
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr, graph_k = nullptr;   // one step, kStepsPerGraph steps
     void *graph_U = nullptr;
     double Y_amb = 0, u_amb = 0;
     std::string err;
 };
 
 namespace {
+
+constexpr int kStepsPerGraph = 8;
+
+// Release the captured step graphs (after any change of what a step launches).
+void drop_graphs(cp_ctx *c)
+{
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->graph_k) hipGraphExecDestroy(c->graph_k);
+    c->graph = c->graph_k = nullptr;
+}
 
 int fail(cp_ctx *c, int code, const std::string &msg)
 {
@@ -556,7 +566,7 @@ void cp_destroy(cp_ctx *c)
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
-    if (c->graph) hipGraphExecDestroy(c->graph);
+    drop_graphs(c);
     for (void *p : c->allocs)
         if (p) hipFree(p);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
@@ -623,31 +633,46 @@ int cp_cfl_dt(cp_ctx *c, const void *U, double *dt_host)
     return CP_OK;
 }
 
+// Capture `steps` consecutive steps (CFL reduction, dt, three stages each) into one
+// executable graph.
+int capture_steps(cp_ctx *c, void *U, int steps, hipGraphExec_t *out)
+{
+    hipGraph_t g;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int r = 0;
+    for (int k = 0; k < steps && !r; ++k) {
+        r = cfl_any(c, U, c->cap_stream);
+        if (!r && launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) != hipSuccess)
+            r = fail(c, CP_EHIP, "finalize launch");
+        if (!r) r = enqueue_step(c, U, 0.0, c->dt_d, c->cap_stream);
+    }
+    hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (r) return r;
+    if (ec != hipSuccess) return fail(c, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
+    hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(c, CP_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    return CP_OK;
+}
+
 int cp_step_n(cp_ctx *c, void *U, int n, double *t_host)
 {
     if (!c || !U || n < 0) return fail(c, CP_EINVAL, "bad argument");
     int r = autotune(c, U);
     if (r) return r;
     if (!c->graph || c->graph_U != U) {
-        if (c->graph) {
-            hipGraphExecDestroy(c->graph);
-            c->graph = nullptr;
+        drop_graphs(c);
+        if ((r = capture_steps(c, U, 1, &c->graph))) return r;
+        if ((r = capture_steps(c, U, kStepsPerGraph, &c->graph_k))) {
+            drop_graphs(c);
+            return r;
         }
-        hipGraph_t g;
-        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        r = cfl_any(c, U, c->cap_stream);
-        if (!r && launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) != hipSuccess)
-            r = fail(c, CP_EHIP, "finalize launch");
-        if (!r) r = enqueue_step(c, U, 0.0, c->dt_d, c->cap_stream);
-        hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
-        if (r) return r;
-        if (ec != hipSuccess) return fail(c, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
-        HIPCHK(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
-        hipGraphDestroy(g);
         c->graph_U = U;
     }
     HIPCHK(c, hipMemsetAsync(c->t_d, 0, sizeof(double), c->stream));
-    for (int k = 0; k < n; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    // whole groups of steps per replay (fewer graph boundaries), then single steps
+    for (int k = 0; k < n / kStepsPerGraph; ++k) HIPCHK(c, hipGraphLaunch(c->graph_k, c->stream));
+    for (int k = 0; k < n % kStepsPerGraph; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     double t = 0.0;
     HIPCHK(c, hipMemcpyAsync(&t, c->t_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if ((r = check_flag(c))) return r;
@@ -663,10 +688,7 @@ int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
     mlp_dims(mlp, &ni, &no);
     if (ni != 17 || no != 15) return fail(c, CP_EINVAL, "network must map 17 features to 15 sources");
     // the captured step refers to the previous network and buffers: drop it first
-    if (c->graph) {
-        hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graphs(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->mlp = nullptr;
     if (c->qmode == CP_Q_SURROGATE) c->qmode = CP_Q_EXACT;   // select it again after a new network
@@ -710,10 +732,7 @@ int cp_set_qmode(cp_ctx *c, int qmode)
     if (qmode == CP_Q_SURROGATE && !c->mlp) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
     if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE) return fail(c, CP_EINVAL, "bad qmode");
     c->qmode = qmode;
-    if (c->graph) {
-        hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graphs(c);
     return CP_OK;
 }
 
@@ -775,10 +794,7 @@ int cp_set_tile(cp_ctx *c, int tx, int ty)
         c->tx = tx;
         c->ty = ty;
     }
-    if (c->graph) {
-        hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graphs(c);
     return CP_OK;
 }
 

@@ -419,29 +419,46 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         }
     } else {
         const R rdt = (R)dt;
-        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(a.Uin[4 * a.plane + c], a.Uin[5 * a.plane + c],
-                                                                      a.Uin[9 * a.plane + c], Tcell))) {
+        // every load of the cell's old states is issued before the first store (the
+        // compiler cannot rule out that Uout aliases them, and would otherwise wait
+        // for each load in turn)
+        R ui[NVAR], un[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) ui[v] = a.Uin[v * a.plane + c];
+        if (a.stage > 0) {
+            #pragma unroll
+            for (int v = 0; v < NVAR; ++v) un[v] = a.Un[v * a.plane + c];
+        }
+        bool act = false;
+        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], ui[5], ui[9], Tcell))) {
             double Ug[NVAR];
             #pragma unroll
-            for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)a.Uin[v * a.plane + c] : 0.0;
+            for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)ui[v] : 0.0;
             CellThermo th;
             cell_thermo(Ug, th);
-            if (!source_inactive(Ug, th.T)) {
-                const int slot = atomicAdd(a.active_count, 1);
+            act = !source_inactive(Ug, th.T);
+        }
+        // append the wavefront's active cells with one atomic
+        const unsigned long long mask = __ballot(act);
+        if (mask) {
+            const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(a.active_count, __popcll(mask));
+            base = __shfl(base, leader, 64);
+            if (act) {
+                const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
                 if (slot < a.plane) a.active_list[slot] = (int)c;
             }
         }
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-            const R ui = a.Uin[v * a.plane + c];
             const R L = res[v];
             R out;
             if (a.stage == 0) {
-                out = ui + rdt * L;
+                out = ui[v] + rdt * L;
             } else {
-                const R un = a.Un[v * a.plane + c];
-                out = a.stage == 1 ? R(0.75) * un + R(0.25) * (ui + rdt * L)
-                                   : R(1.0 / 3.0) * un + R(2.0 / 3.0) * (ui + rdt * L);
+                out = a.stage == 1 ? R(0.75) * un[v] + R(0.25) * (ui[v] + rdt * L)
+                                   : R(1.0 / 3.0) * un[v] + R(2.0 / 3.0) * (ui[v] + rdt * L);
             }
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
@@ -994,7 +1011,9 @@ hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
 
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
 {
-    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 4096));
+    // enough one-wavefront workgroups for every CU; the list length is only known
+    // on the device, so the workgroups stride over it
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 512));
     hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(64), 0, s, a);
     return hipGetLastError();
 }
