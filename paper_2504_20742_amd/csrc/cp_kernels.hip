@@ -506,9 +506,12 @@ template <class R> __device__ __forceinline__ void source_fix_body(const SourceF
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
         ns += source_integrate(Ud, dt, a.sp, Q);
+        R uo[NVAR];   // all loads before the stores (possible aliasing serialises them)
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) uo[v] = a.Uout[v * a.plane + c];
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-            R out = a.Uout[v * a.plane + c] + (R)(b * dt * Q[v]);
+            const R out = uo[v] + (R)(b * dt * Q[v]);
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
         }
@@ -676,9 +679,12 @@ template <class R> __global__ void __launch_bounds__(256) k_sur_apply(SurArgs<R>
             for (int v = 0; v < NVAR; ++v) a.Uout[v * a.plane + c] = (R)Q[v];
             continue;
         }
+        R uo[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) uo[v] = a.Uout[v * a.plane + c];
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
-            const R out = a.Uout[v * a.plane + c] + (R)(b * dt * Q[v]);
+            const R out = uo[v] + (R)(b * dt * Q[v]);
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
         }
