@@ -198,7 +198,9 @@ long cp_mlp_num_params(const cp_mlp *mlp);
 /* Host FP32 parameters in / out (set also resets the Adam moments).             */
 int cp_mlp_set_params(cp_mlp *mlp, const float *host_params);
 int cp_mlp_get_params(cp_mlp *mlp, float *host_params);
-/* Y[rows][n_out] = network(X[rows][n_in]); X is rounded to bfloat16.            */
+/* Y[rows][n_out] = network(X[rows][n_in]); X is rounded to bfloat16.  Networks with
+ * n_in <= 32, n_hidden = 256, n_out <= 16 run all three layers in one fused kernel
+ * (activations in LDS); others run layer by layer.                                */
 int cp_mlp_forward(cp_mlp *mlp, const float *X, int rows, float *Y);
 /* Forward + backward of the MSE loss mean((Y - T)^2) over rows and outputs; the
  * gradient is kept for cp_mlp_adam; *loss_host (nullable) gets the loss,
@@ -209,9 +211,10 @@ int cp_mlp_loss_grad(cp_mlp *mlp, const float *X, const float *T, int rows, doub
 int cp_mlp_adam(cp_mlp *mlp, double lr, double beta1, double beta2, double eps);
 const char *cp_mlp_error_string(const cp_mlp *mlp);
 
-/* Attach a trained 17 -> 15 network as the source of a context (CP_Q_SURROGATE).
- * The context keeps a pointer (the caller keeps ownership and must keep the network
- * alive while the mode is used).  norm: n_norm = 117 host floats in the order
+/* Attach a trained 17 -> 256 -> 256 -> 15 network as the source of a context
+ * (CP_Q_SURROGATE).  The context takes a copy of the weights at this call, packed for
+ * its fused inference kernel: later training or destruction of the network does not
+ * affect it (attach again to update).  norm: n_norm = 117 host floats in the order
  *   s_in[15], mu_in[17], sd_in[17], lo[17], hi[17], mu_out[15], sd_out[15],
  *   lnS_gate, lnS_lo, lnS_hi, df_max
  * Features of an active cell: f_v = asinh(U_v / s_in[v]) for the 15 state variables,
@@ -227,11 +230,13 @@ const char *cp_mlp_error_string(const cp_mlp *mlp);
  * number is unchanged.  A network cell falls back to the exact source when any
  * predicted increment exceeds df_max in magnitude, when a particle population is not
  * realizable after the update (neither empty nor positive, log-convex moments with a
- * mean radius in [0.1 nm, 1 mm]) or when its vapour would turn negative.  The context allocates its own inference activations (bf16, 2 x n_hidden
- * + 17 values and 15 floats per cell); the network keeps only the weights.
- * Attaching a network drops the captured step and leaves a context that was in
+ * mean radius in [0.1 nm, 1 mm]) or when its vapour would turn negative.
+ * The context allocates 17 bf16 feature values and 15 floats of network output per
+ * cell plus the packed weights (150 KB); the hidden activations never leave the
+ * workgroup.  Attaching drops the captured step and leaves a context that was in
  * CP_Q_SURROGATE in CP_Q_EXACT: select CP_Q_SURROGATE again afterwards.
- * Errors: CP_EINVAL (null, n_norm != 117, network not 17 -> 15), CP_ENOMEM, CP_EHIP. */
+ * Errors: CP_EINVAL (null, n_norm != 117, network not 17 -> 15), CP_EUNSUPPORTED
+ * (hidden width other than 256), CP_ENOMEM, CP_EHIP.                               */
 int cp_sur_set(cp_ctx *ctx, cp_mlp *mlp, const float *norm, int n_norm);
 
 /* Training-set features of every cell of U (the gate's own computation): F is a

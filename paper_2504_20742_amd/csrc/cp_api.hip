@@ -37,14 +37,15 @@ struct cp_ctx {
     unsigned long long *acc_d = nullptr, *nsub_d = nullptr;
     int *flag_d = nullptr;
     int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
-    cp_mlp *mlp = nullptr;                          // learned source (not owned)
+    bool sur_ready = false;                         // a network snapshot is attached
     SurNorm nm{};
     int *sur_cnt = nullptr, *sur_cells = nullptr, *fb_list = nullptr;
     unsigned long long *sur_tot = nullptr;   // running totals of network / fallback cells
     int *src_cnt = nullptr, *src_list = nullptr;   // active cells of a cp_source call
-    uint16_t *sur_X = nullptr, *sur_H1 = nullptr, *sur_H2 = nullptr;   // in-step inference activations
+    uint16_t *sur_X = nullptr;   // gated feature rows (bf16) and network outputs
     float *sur_Y = nullptr;
-    int sur_nh = 0;
+    uint16_t *sur_w = nullptr;   // packed snapshot of the attached network's weights
+    float *sur_b = nullptr;
     SourceParams sp{};
     int qmode = CP_Q_EXACT;
     int tx = 0, ty = 0;                             // 0: autotune on first use
@@ -270,6 +271,9 @@ StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *
     a.pref = c->cs.p_amb;
     a.active_count = c->act_count + (stage < 0 ? 0 : stage);
     a.active_list = c->act_list;
+    const bool sur = c->qmode == CP_Q_SURROGATE && c->sur_ready && stage >= 0;
+    a.sur_cnt = sur ? c->sur_cnt : nullptr;
+    a.sur_tot = c->sur_tot;
     return a;
 }
 
@@ -316,24 +320,26 @@ SurArgs<R> sur_args(const cp_ctx *c, const void *Uin, void *Uout, int stage, dou
     return a;
 }
 
+FusedNet sur_net(const cp_ctx *c)
+{
+    return FusedNet{c->sur_w, c->sur_w + kFusedW1, c->sur_w + kFusedW1 + kFusedW2, c->sur_b, c->sur_b + 256,
+                    c->sur_b + 512};
+}
+
 // Learned source for the active cells of a stage: split them (network / exact),
 // run the network on its rows, decode + project + apply, exact source for the rest.
 template <class R>
 int surrogate_stage(cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev, hipStream_t s)
 {
+    // the stage kernel has already folded and cleared the counters
     SurArgs<R> a = sur_args<R>(c, Uin, Uout, stage, dt, dt_dev);
-    hipError_t e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
-    if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
+    hipError_t e = launch_sur_gate<R>(a, c->plane, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
-    int r = mlp_forward_into(c->mlp, (int)c->plane, c->sur_cnt, c->sur_X, c->sur_H1, c->sur_H2, c->sur_Y, s);
-    if (r) return fail(c, r, "surrogate forward");
-    e = launch_sur_apply<R>(a, c->plane, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate apply: ") + hipGetErrorString(e));
-    SourceFixArgs<R> f = fix_args<R>(c, Uin, Uout, stage, dt, dt_dev);
-    f.count = c->sur_cnt + 1;
-    f.list = c->fb_list;
-    e = launch_source_fix<R>(f, c->plane, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("fallback source: ") + hipGetErrorString(e));
+    e = mlp_fused_forward(sur_net(c), c->sur_X, 17, 15, c->sur_cnt, (int)c->plane, c->sur_Y, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
+    const SourceFixArgs<R> f = fix_args<R>(c, Uin, Uout, stage, dt, dt_dev);
+    e = launch_sur_finish<R>(a, f.sp, f.next_count, c->nsub_d, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate finish: ") + hipGetErrorString(e));
     return CP_OK;
 }
 
@@ -351,10 +357,12 @@ template <class R> int surrogate_source(cp_ctx *c, const void *U, double dt, voi
     if (e == hipSuccess) e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
     if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
-    int r = mlp_forward_into(c->mlp, (int)c->plane, c->sur_cnt, c->sur_X, c->sur_H1, c->sur_H2, c->sur_Y, s);
-    if (r) return fail(c, r, "surrogate forward");
-    e = launch_sur_apply<R>(a, c->plane, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate apply: ") + hipGetErrorString(e));
+    e = mlp_fused_forward(sur_net(c), c->sur_X, 17, 15, c->sur_cnt, (int)c->plane, c->sur_Y, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
+    SourceParams sp = c->sp;
+    sp.enabled = 1;
+    e = launch_sur_finish<R>(a, sp, nullptr, nullptr, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate finish: ") + hipGetErrorString(e));
     return CP_OK;
 }
 
@@ -690,7 +698,7 @@ int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
     // the captured step refers to the previous network and buffers: drop it first
     drop_graphs(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->mlp = nullptr;
+    c->sur_ready = false;
     if (c->qmode == CP_Q_SURROGATE) c->qmode = CP_Q_EXACT;   // select it again after a new network
     memcpy(&c->nm, norm, sizeof(SurNorm));
     if (!c->sur_cnt) {
@@ -707,29 +715,24 @@ int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
     if (!c->sur_cells && !(c->sur_cells = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
     if (!c->fb_list && !(c->fb_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
     if (!c->src_list && !(c->src_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
-    const int nh = mlp_hidden(mlp);
-    if (nh > c->sur_nh) {   // activation buffers for every cell of the mesh
-        for (void *q : {(void *)c->sur_X, (void *)c->sur_H1, (void *)c->sur_H2, (void *)c->sur_Y}) {
-            if (!q) continue;
-            hipFree(q);
-            c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), q));
-        }
-        c->sur_nh = 0;
-        c->sur_X = dalloc<uint16_t>(c, (size_t)c->plane * 17);
-        c->sur_H1 = dalloc<uint16_t>(c, (size_t)c->plane * nh);
-        c->sur_H2 = dalloc<uint16_t>(c, (size_t)c->plane * nh);
-        c->sur_Y = dalloc<float>(c, (size_t)c->plane * 15);
-        if (!c->sur_X || !c->sur_H1 || !c->sur_H2 || !c->sur_Y) return fail(c, CP_ENOMEM, "network activation buffers");
-        c->sur_nh = nh;
-    }
-    c->mlp = mlp;
+    if (!mlp_fusable(mlp)) return fail(c, CP_EUNSUPPORTED, "in-step inference needs 256 hidden units");
+    if (!c->sur_X && !(c->sur_X = dalloc<uint16_t>(c, (size_t)c->plane * 17))) return fail(c, CP_ENOMEM, "feature rows");
+    if (!c->sur_Y && !(c->sur_Y = dalloc<float>(c, (size_t)c->plane * 15))) return fail(c, CP_ENOMEM, "output rows");
+    if (!c->sur_w && !(c->sur_w = dalloc<uint16_t>(c, kFusedW1 + kFusedW2 + kFusedW3)))
+        return fail(c, CP_ENOMEM, "packed weights");
+    if (!c->sur_b && !(c->sur_b = dalloc<float>(c, 528))) return fail(c, CP_ENOMEM, "packed biases");
+    // the context keeps its own copy: later training of the network does not change it
+    int r = mlp_snapshot(mlp, c->sur_w, c->sur_b, c->stream);
+    if (r) return fail(c, r, "weight snapshot");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->sur_ready = true;
     return CP_OK;
 }
 
 int cp_set_qmode(cp_ctx *c, int qmode)
 {
     if (!c) return CP_EINVAL;
-    if (qmode == CP_Q_SURROGATE && !c->mlp) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
+    if (qmode == CP_Q_SURROGATE && !c->sur_ready) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
     if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE) return fail(c, CP_EINVAL, "bad qmode");
     c->qmode = qmode;
     drop_graphs(c);
@@ -764,7 +767,7 @@ int cp_diag(cp_ctx *c, const void *U, double out[8])
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     out[6] = (double)(st[0] + (unsigned long long)(sc[0] - sc[2]));
-    out[7] = (double)(st[1] + (unsigned long long)sc[1]);
+    out[7] = (double)(st[1] + (unsigned long long)(sc[1] + sc[2]));
     return CP_OK;
 }
 

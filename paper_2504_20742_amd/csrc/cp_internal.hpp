@@ -47,6 +47,8 @@ template <class R> struct StageArgs {
     double pref;               // reference pressure removed from the momentum fluxes
     int *active_count;         // cells appended to active_list by this stage
     int *active_list;          // cells whose phase-change source may be non-zero
+    int *sur_cnt;              // surrogate counters folded into sur_tot at launch (or null)
+    unsigned long long *sur_tot;
 };
 
 template <class R> struct SourceFixArgs {
@@ -78,12 +80,21 @@ struct Ctx;   // host context (cp_api.hip)
 
 struct cp_mlp;
 namespace cp {
-// network hooks used by the solver (cp_mlp.hip).  The solver owns the activation
-// buffers of its in-step inference (bf16 X[rows][n_in], H1, H2 [rows][n_hidden],
-// FP32 Y[rows][n_out]); only the weights belong to the network.
-int mlp_hidden(const cp_mlp *n);
-int mlp_forward_into(cp_mlp *n, int max_rows, const int *rows_dev, const uint16_t *X, uint16_t *H1, uint16_t *H2,
-                     float *Y, hipStream_t s);
+// Network weights for the fused inference kernel: bf16 weights in MFMA fragment
+// order (w1: 2 x 16 fragments, w2: 16 x 16, w3: 16 x 1; 256 bf16 each) and FP32
+// biases (b1, b2: 256, b3: 16, zero-padded).
+struct FusedNet {
+    const uint16_t *w1, *w2, *w3;
+    const float *b1, *b2, *b3;
+};
+constexpr long kFusedW1 = 2L * 16 * 256, kFusedW2 = 16L * 16 * 256, kFusedW3 = 16L * 1 * 256;
+
+// network hooks used by the solver (cp_mlp.hip).  The solver keeps its own packed
+// snapshot of the weights (taken by mlp_snapshot) and its own input/output rows.
+bool mlp_fusable(const cp_mlp *n);
+int mlp_snapshot(cp_mlp *n, uint16_t *w /* kFusedW1 + kFusedW2 + kFusedW3 */, float *b /* 528 */, hipStream_t s);
+hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int n_out, const int *rows_dev,
+                             int max_rows, float *Y, hipStream_t s);
 void mlp_dims(const cp_mlp *n, int *n_in, int *n_out);
 
 // launchers (cp_kernels.hip)
@@ -124,8 +135,8 @@ template <class R> struct SurArgs {
     long plane;
     int stage;
     const int *count, *list;   // active cells of the stage
-    int *cnt;                  // [0] cells gated to the network, [1] exact-fallback cells,
-                               // [2] network cells rejected at decode (also in [1])
+    int *cnt;                  // [0] cells gated to the network, [1] gate fallback cells,
+                               // [2] network cells rejected at decode (exact source)
     int *mlp_cells, *fb_list;
     uint16_t *X;               // bf16 features [rows][17]
     const float *Y;            // network output [rows][15]
@@ -134,7 +145,9 @@ template <class R> struct SurArgs {
     int q_only;                // write Q itself to Uout (cp_source) instead of adding b dt Q
 };
 template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s);
-template <class R> hipError_t launch_sur_apply(const SurArgs<R> &a, long max_cells, hipStream_t s);
+template <class R>
+hipError_t launch_sur_finish(const SurArgs<R> &a, const SourceParams &sp, int *next_count, unsigned long long *nsub,
+                             long max_cells, hipStream_t s);
 hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s);
 template <class R> hipError_t launch_active_list(const R *U, long plane, int *count, int *list, hipStream_t s);
 template <class R>

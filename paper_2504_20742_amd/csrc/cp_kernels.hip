@@ -210,6 +210,16 @@ template <class TileT> __device__ __forceinline__ auto *scalar_slot(TileT &t, in
 template <class R> __device__ __forceinline__ R inv_rho(R rho) { return trcp(rho); }
 template <class R> __device__ __forceinline__ R per_mass(R U, R, R ir) { return U * ir; }
 
+// Fold the surrogate's per-stage counters into its running totals and clear them.
+__device__ __forceinline__ void sur_fold_counts(int *cnt, unsigned long long *tot)
+{
+    tot[0] += (unsigned long long)(cnt[0] - cnt[2]);   // network cells kept
+    tot[1] += (unsigned long long)(cnt[1] + cnt[2]);   // exact: gate fallback + rejected decodes
+    cnt[0] = 0;
+    cnt[1] = 0;
+    cnt[2] = 0;
+}
+
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so workgroup b
 // takes item xcd*q + min(xcd, rem) + b/8 -- a contiguous band of tiles per XCD, whose
 // neighbouring tiles then share their halos in that XCD's L2.
@@ -471,6 +481,8 @@ template <class R, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
 {
     __shared__ Tile<R, TX, TY> t;
+    // surrogate counters of the previous stage, consumed by now (saves a launch)
+    if (a.sur_cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sur_fold_counts(a.sur_cnt, a.sur_tot);
     const int gx = gridDim.x;
     const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
     stage_tile<R, TX, TY>(a, (tb % gx) * TX, (tb / gx) * TY, t);
@@ -617,69 +629,85 @@ __device__ __forceinline__ bool sur_population_ok(double m0, double m1, double m
            m1 >= m0 * 1e-10 && m1 <= m0 * 1e-3;
 }
 
-// Decode the network output into the particle sources and close the rest exactly.
-// The network predicts, for each particle moment and the activated-soot number, the
-// increment of its feature over dt; the new value s sinh(f + df) (floored at zero)
-// gives Q_v = (U'_v - U_v) / dt.  The vapour sink then follows from the condensate
-// sources (water exactly conserved), the gas mass and momentum follow the vapour,
-// the gas energy loses the enthalpy of the condensed water (the freezing enthalpy
-// cancels between the two condensates) and the soot number is unchanged.  A cell
-// whose vapour would turn negative, or whose result is not finite, is handed to the
-// exact fallback list instead (the fallback kernel runs after this one), and so is
-// one whose predicted increments leave the trust bound df_max or whose populations
-// are not realizable after the update.
-template <class R> __global__ void __launch_bounds__(256) k_sur_apply(SurArgs<R> a)
+// Decode the network output of row k into the particle sources and close the rest
+// exactly.  The network predicts, for each particle moment and the activated-soot
+// number, the increment of its feature over dt; the new value s sinh(f + df)
+// (floored at zero) gives Q_v = (U'_v - U_v) / dt.  The vapour sink then follows
+// from the condensate sources (water exactly conserved), the gas mass and momentum
+// follow the vapour, the gas energy loses the enthalpy of the condensed water (the
+// freezing enthalpy cancels between the two condensates) and the soot number is
+// unchanged.  Returns false (the cell takes the exact source) when a predicted
+// increment leaves the trust bound df_max, a population is not realizable after
+// the update, the vapour would turn negative or a value is not finite.
+template <class R>
+__device__ __forceinline__ bool sur_decode(const SurArgs<R> &a, int k, const double *Ud, double dt, double *Q)
 {
-    const int n = min(a.cnt[0], (int)a.plane);
+    double Un[NVAR];
+    bool trust = true;
+    #pragma unroll
+    for (int v = 5; v < NVAR; ++v) {
+        if (v == 13) continue;
+        const double s = (double)a.nm.s_in[v];
+        const double df = (double)(a.Y[(long)k * 15 + v] * a.nm.sd_out[v] + a.nm.mu_out[v]);
+        trust = trust && fabs(df) <= (double)a.nm.df_max;
+        const double f1 = fmax(asinh(Ud[v] / s) + df, 0.0);
+        Un[v] = s * sinh(f1);
+        Q[v] = (Un[v] - Ud[v]) / dt;
+    }
+    Q[13] = 0.0;
+    trust = trust && sur_population_ok(Un[5], Un[6], Un[7], Un[8]) && sur_population_ok(Un[9], Un[10], Un[11], Un[12]);
+    CellThermo th;
+    cell_thermo(Ud, th);
+    const double ml = kFourThirdsPi * kRhoL * Q[8], ms = kFourThirdsPi * kRhoS * Q[12];
+    Q[4] = -(ml + ms);
+    Q[0] = Q[4];
+    Q[1] = Q[4] * th.u;
+    Q[2] = Q[4] * th.v;
+    const double T = th.T;
+    const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+    const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+    const double hv = kLv0 + kCpv * (T - kTref);
+    const double ke = 0.5 * (th.u * th.u + th.v * th.v);
+    Q[3] = -ml * (hv - hfg + ke) - ms * (hv - hsg + ke);
+    bool ok = trust && Ud[4] + dt * Q[4] >= 0.0;
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(Q[v]);
+    return ok;
+}
+
+// Second half of a surrogate stage: the network rows (decoded, or given the exact
+// source where the decode is rejected) followed by the gate's fallback cells (exact
+// source), each adding b dt Q to the stage output -- or, for cp_source (q_only),
+// writing the network's Q over the exact Q already in place.  Clears the list
+// counter of the next stage like the exact source kernel.
+template <class R> __global__ void __launch_bounds__(64) k_sur_finish(SurArgs<R> a, SourceParams sp,
+                                                                      int *next_count, unsigned long long *nsub)
+{
+    const int n_net = min(a.cnt[0], (int)a.plane), n_fb = min(a.cnt[1], (int)a.plane);
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
     const double b = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
     bool bad = false;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const long c = a.mlp_cells[k];
-        double Ud[NVAR], Q[NVAR], Un[NVAR];
+    int ns = 0, rejected = 0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_net + n_fb; k += gridDim.x * blockDim.x) {
+        const bool net = k < n_net;
+        const long c = net ? a.mlp_cells[k] : a.fb_list[k - n_net];
+        double Ud[NVAR], Q[NVAR];
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
-        bool trust = true;
-        #pragma unroll
-        for (int v = 5; v < NVAR; ++v) {
-            if (v == 13) continue;
-            const double s = (double)a.nm.s_in[v];
-            const double df = (double)(a.Y[(long)k * 15 + v] * a.nm.sd_out[v] + a.nm.mu_out[v]);
-            trust = trust && fabs(df) <= (double)a.nm.df_max;
-            const double f1 = fmax(asinh(Ud[v] / s) + df, 0.0);
-            Un[v] = s * sinh(f1);
-            Q[v] = (Un[v] - Ud[v]) / dt;
+        bool exact = !net;
+        if (net && !sur_decode(a, k, Ud, dt, Q)) {
+            exact = true;
+            ++rejected;
         }
-        Q[13] = 0.0;
-        trust = trust && sur_population_ok(Un[5], Un[6], Un[7], Un[8]) && sur_population_ok(Un[9], Un[10], Un[11], Un[12]);
-        CellThermo th;
-        cell_thermo(Ud, th);
-        const double ml = kFourThirdsPi * kRhoL * Q[8], ms = kFourThirdsPi * kRhoS * Q[12];
-        Q[4] = -(ml + ms);
-        Q[0] = Q[4];
-        Q[1] = Q[4] * th.u;
-        Q[2] = Q[4] * th.v;
-        const double T = th.T;
-        const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
-        const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
-        const double hv = kLv0 + kCpv * (T - kTref);
-        const double ke = 0.5 * (th.u * th.u + th.v * th.v);
-        Q[3] = -ml * (hv - hfg + ke) - ms * (hv - hsg + ke);
-        bool ok = trust && Ud[4] + dt * Q[4] >= 0.0;
-        #pragma unroll
-        for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(Q[v]);
-        if (!ok) {
-            const int slot = atomicAdd(a.cnt + 1, 1);
-            if (!a.q_only) a.fb_list[slot] = (int)c;   // Q already holds the exact source
-            atomicAdd(a.cnt + 2, 1);
+        if (a.q_only) {   // the exact source is already in the output
+            if (!exact) {
+                #pragma unroll
+                for (int v = 0; v < NVAR; ++v) a.Uout[v * a.plane + c] = (R)Q[v];
+            }
             continue;
         }
-        if (a.q_only) {
-            #pragma unroll
-            for (int v = 0; v < NVAR; ++v) a.Uout[v * a.plane + c] = (R)Q[v];
-            continue;
-        }
-        R uo[NVAR];
+        if (exact) ns += source_integrate(Ud, dt, sp, Q);
+        R uo[NVAR];   // all loads before the stores (possible aliasing serialises them)
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) uo[v] = a.Uout[v * a.plane + c];
         #pragma unroll
@@ -689,7 +717,16 @@ template <class R> __global__ void __launch_bounds__(256) k_sur_apply(SurArgs<R>
             bad |= !isfinite(out);
         }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && next_count) *next_count = 0;
     if (bad) atomicOr(a.flag, 1);
+    for (int o = 32; o > 0; o >>= 1) {
+        ns += __shfl_xor(ns, o, 64);
+        rejected += __shfl_xor(rejected, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (ns && nsub) atomicAdd(nsub, (unsigned long long)ns);
+        if (rejected) atomicAdd(a.cnt + 2, rejected);
+    }
 }
 
 // Cells whose phase-change source does not vanish identically (the FP64 test the
@@ -706,15 +743,7 @@ template <class R> __global__ void __launch_bounds__(256) k_active_list(const R 
     }
 }
 
-// Fold the previous stage's counts into the running totals and clear them.
-__global__ void k_sur_reset(int *cnt, unsigned long long *tot)
-{
-    tot[0] += (unsigned long long)(cnt[0] - cnt[2]);
-    tot[1] += (unsigned long long)cnt[1];
-    cnt[0] = 0;
-    cnt[1] = 0;
-    cnt[2] = 0;
-}
+__global__ void k_sur_reset(int *cnt, unsigned long long *tot) { sur_fold_counts(cnt, tot); }
 
 // ------------------------------------------------------------------ CFL
 // Per-cell limit 1/((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)), written
@@ -1031,10 +1060,12 @@ template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cell
     return hipGetLastError();
 }
 
-template <class R> hipError_t launch_sur_apply(const SurArgs<R> &a, long max_cells, hipStream_t s)
+template <class R>
+hipError_t launch_sur_finish(const SurArgs<R> &a, const SourceParams &sp, int *next_count, unsigned long long *nsub,
+                             long max_cells, hipStream_t s)
 {
-    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
-    hipLaunchKernelGGL((k_sur_apply<R>), dim3(blocks), dim3(256), 0, s, a);
+    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 512));
+    hipLaunchKernelGGL((k_sur_finish<R>), dim3(blocks), dim3(64), 0, s, a, sp, next_count, nsub);
     return hipGetLastError();
 }
 
@@ -1107,7 +1138,8 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, hipStream_t);                        \
     template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
     template hipError_t launch_sur_gate<R>(const SurArgs<R> &, long, hipStream_t);                           \
-    template hipError_t launch_sur_apply<R>(const SurArgs<R> &, long, hipStream_t);                          \
+    template hipError_t launch_sur_finish<R>(const SurArgs<R> &, const SourceParams &, int *,                 \
+                                             unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \

@@ -190,6 +190,113 @@ __global__ void __launch_bounds__(256) k_adam(float *p, float *m, float *v, cons
     pb[e] = f2bf(pe);
 }
 
+// ---------------------------------------------------------------- fused inference
+// Weights repacked in MFMA B-fragment order: fragment (kb, nb) of W[K][N] holds, for
+// lane l and i = 0..3, W[16 kb + 4 (l / 16) + i][16 nb + l % 16] (zero beyond K, N),
+// 256 bf16 in a row, fragments ordered kb-major.  Each lane then fetches its B
+// operand with one 8-byte load, and a wavefront reads 512 contiguous bytes.
+__global__ void __launch_bounds__(256) k_pack_frag(const uint16_t *W, int K, int N, int KB, int NB, uint16_t *dst)
+{
+    const long total = (long)KB * NB * 256;   // KB x NB fragments, zero beyond K, N
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long f = e >> 8;
+        const int r = (int)(e & 255), lane = r >> 2, i = r & 3;
+        const int kb = (int)(f / NB), nb = (int)(f % NB);
+        const int k = 16 * kb + 4 * (lane >> 4) + i, n = 16 * nb + (lane & 15);
+        dst[e] = (k < K && n < N) ? W[(long)k * N + n] : (uint16_t)0;
+    }
+}
+
+// All three layers for 64-row tiles in one launch (n_in <= 32, n_h = 256,
+// n_out <= 16): the input tile and each hidden activation stay in LDS, every wave
+// owns 64 output columns of a hidden layer (4 x 4 MFMA tiles of 16 x 16) and one
+// 16-row block of the output layer.  Rows past the device-side count are skipped;
+// the workgroups stride over the row tiles.
+constexpr int kFusedNH = 256, kFusedKin = 32, kFusedPad = 8;
+__global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, int n_out, const int *M_dev, int M_max,
+                                                   FusedNet w, float *Y)
+{
+    __shared__ uint16_t Xs[64][kFusedKin + kFusedPad];
+    __shared__ uint16_t Hs[64][kFusedNH + kFusedPad];
+    const int M = M_dev ? min(*M_dev, M_max) : M_max;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = 4 * (lane >> 4);   // A: row in block, first k; B/D: column
+    constexpr int NB = kFusedNH / 16;
+    for (int m0 = blockIdx.x * 64; m0 < M; m0 += gridDim.x * 64) {
+        for (int e = threadIdx.x; e < 64 * kFusedKin; e += 256) {
+            const int r = e / kFusedKin, k = e % kFusedKin, m = m0 + r;
+            Xs[r][k] = (m < M && k < n_in) ? X[(long)m * n_in + k] : (uint16_t)0;
+        }
+        __syncthreads();
+        f32x4 acc[4][4];
+        // hidden layer 1: K = 32 (two k blocks)
+        #pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        #pragma unroll
+        for (int kb = 0; kb < kFusedKin / 16; ++kb) {
+            bf16x4 a[4], b[4];
+            #pragma unroll
+            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Xs[16 * rb + lr][16 * kb + lk];
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) b[cb] = *(const bf16x4 *)&w.w1[(((long)kb * NB + 4 * wave + cb) * 64 + lane) * 4];
+            #pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                #pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+        }
+        #pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int col = 16 * (4 * wave + cb) + lr;
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) Hs[16 * rb + lk + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b1[col]));
+            }
+        __syncthreads();
+        // hidden layer 2: K = 256
+        #pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < NB; ++kb) {
+            bf16x4 a[4], b[4];
+            #pragma unroll
+            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Hs[16 * rb + lr][16 * kb + lk];
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) b[cb] = *(const bf16x4 *)&w.w2[(((long)kb * NB + 4 * wave + cb) * 64 + lane) * 4];
+            #pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                #pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+        }
+        __syncthreads();   // every wave has read the first activation
+        #pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+            #pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int col = 16 * (4 * wave + cb) + lr;
+                #pragma unroll
+                for (int i = 0; i < 4; ++i) Hs[16 * rb + lk + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b2[col]));
+            }
+        __syncthreads();
+        // output layer: wave = 16-row block, one 16-column block
+        f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < NB; ++kb) {
+            const bf16x4 a = *(const bf16x4 *)&Hs[16 * wave + lr][16 * kb + lk];
+            const bf16x4 b = *(const bf16x4 *)&w.w3[((long)kb * 64 + lane) * 4];
+            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+        }
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + 16 * wave + lk + i;
+            if (m < M && lr < n_out) Y[(long)m * n_out + lr] = c[i] + w.b3[lr];
+        }
+        __syncthreads();   // the next tile overwrites Xs and Hs
+    }
+}
+
 }  // namespace cp
 
 using namespace cp;
@@ -207,6 +314,9 @@ struct cp_mlp {
     uint16_t *Xb = nullptr, *H1 = nullptr, *H2 = nullptr, *dY = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
     float *Z1 = nullptr, *Z2 = nullptr, *Yf = nullptr, *part = nullptr, *lossp = nullptr;
     long part_cap = 0;
+    uint16_t *fw = nullptr;      // weights packed for the fused inference kernel
+    float *fb = nullptr;
+    bool fused_stale = true;     // set whenever the parameters change
     std::vector<void *> allocs;
     std::string err;
 };
@@ -349,11 +459,34 @@ int weight_grad(cp_mlp *n, const uint16_t *Aact, int kin, const uint16_t *dZ, in
 }  // namespace
 
 namespace cp {
-int mlp_hidden(const cp_mlp *n) { return n->n_h; }
-int mlp_forward_into(cp_mlp *n, int max_rows, const int *rows_dev, const uint16_t *X, uint16_t *H1, uint16_t *H2,
-                     float *Y, hipStream_t s)
+bool mlp_fusable(const cp_mlp *n) { return n->n_in <= kFusedKin && n->n_h == kFusedNH && n->n_out <= 16; }
+
+int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
 {
-    return forward_rows(n, max_rows, rows_dev, FwdBufs{X, H1, H2, nullptr, nullptr, Y}, s);
+    if (!mlp_fusable(n)) return CP_EUNSUPPORTED;
+    // the network's own stream may still be updating the weights
+    if (s != n->stream && hipStreamSynchronize(n->stream) != hipSuccess) return mfail(n, CP_EHIP, "sync");
+    constexpr int NB = kFusedNH / 16;
+    hipLaunchKernelGGL(k_pack_frag, dim3(32), dim3(256), 0, s, n->pb + n->off[0], n->n_in, n->n_h, kFusedKin / 16, NB,
+                       w);
+    hipLaunchKernelGGL(k_pack_frag, dim3(256), dim3(256), 0, s, n->pb + n->off[2], n->n_h, n->n_h, NB, NB, w + kFusedW1);
+    hipLaunchKernelGGL(k_pack_frag, dim3(16), dim3(256), 0, s, n->pb + n->off[4], n->n_h, n->n_out, NB, 1,
+                       w + kFusedW1 + kFusedW2);
+    if (hipGetLastError() != hipSuccess) return mfail(n, CP_EHIP, "weight packing");
+    if (hipMemsetAsync(b, 0, 528 * sizeof(float), s) != hipSuccess ||
+        hipMemcpyAsync(b, n->p + n->off[1], 256 * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b + 256, n->p + n->off[3], 256 * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b + 512, n->p + n->off[5], n->n_out * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return mfail(n, CP_EHIP, "bias copy");
+    return CP_OK;
+}
+
+hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int n_out, const int *rows_dev,
+                             int max_rows, float *Y, hipStream_t s)
+{
+    const int blocks = std::max(1, std::min((max_rows + 63) / 64, 512));
+    hipLaunchKernelGGL(k_mlp_fused, dim3(blocks), dim3(256), 0, s, X, n_in, n_out, rows_dev, max_rows, w, Y);
+    return hipGetLastError();
 }
 void mlp_dims(const cp_mlp *n, int *n_in, int *n_out)
 {
@@ -416,6 +549,7 @@ int cp_mlp_set_params(cp_mlp *n, const float *host)
         hipMemsetAsync(n->v, 0, n->np * 4, n->stream) != hipSuccess)
         return mfail(n, CP_EHIP, "adam reset");
     n->adam_t = 0;
+    n->fused_stale = true;
     return hipStreamSynchronize(n->stream) == hipSuccess ? CP_OK : mfail(n, CP_EHIP, "sync");
 }
 
@@ -435,6 +569,21 @@ int cp_mlp_forward(cp_mlp *n, const float *X, int rows, float *Y)
     if (r) return r;
     const long nx = (long)rows * n->n_in;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, n->stream, X, nx, n->Xb);
+    if (mlp_fusable(n)) {   // inference shape: all layers in one kernel
+        if (!n->fw) {
+            n->fw = malloc_dev<uint16_t>(n, kFusedW1 + kFusedW2 + kFusedW3);
+            n->fb = malloc_dev<float>(n, 528);
+            if (!n->fw || !n->fb) return mfail(n, CP_ENOMEM, "packed weights");
+        }
+        if (n->fused_stale) {
+            if ((r = mlp_snapshot(n, n->fw, n->fb, n->stream))) return r;
+            n->fused_stale = false;
+        }
+        const FusedNet w{n->fw, n->fw + kFusedW1, n->fw + kFusedW1 + kFusedW2, n->fb, n->fb + 256, n->fb + 512};
+        if (mlp_fused_forward(w, n->Xb, n->n_in, n->n_out, nullptr, rows, Y, n->stream) != hipSuccess)
+            return mfail(n, CP_EHIP, "fused forward");
+        return CP_OK;
+    }
     if ((r = forward_rows(n, rows, n->stream))) return r;
     if (hipMemcpyAsync(Y, n->Yf, (long)rows * n->n_out * 4, hipMemcpyDeviceToDevice, n->stream) != hipSuccess)
         return mfail(n, CP_EHIP, "output copy");
@@ -499,6 +648,7 @@ int cp_mlp_adam(cp_mlp *n, double lr, double beta1, double beta2, double eps)
     const float c2 = (float)(1.0 / (1.0 - pow(beta2, n->adam_t)));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->np + 255) / 256)), dim3(256), 0, n->stream, n->p, n->m, n->v, n->g,
                        n->np, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2, n->pb);
+    n->fused_stale = true;
     return hipGetLastError() == hipSuccess ? CP_OK : mfail(n, CP_EHIP, "adam launch");
 }
 

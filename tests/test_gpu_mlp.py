@@ -88,3 +88,25 @@ def test_adam_training_reduces_loss(B):
         net.adam(1e-3)
     L1 = net.loss_grad(Xd, Td)
     assert L1 < 0.1 * L0, (L0, L1)
+
+
+def test_fused_inference_matches_layerwise_forward(B):
+    """The fused three-layer inference kernel (forward) and the layer-by-layer MFMA
+    GEMMs of the training pass (loss_grad) see the same bf16 operands in the same
+    accumulation order: their losses on the same batch agree to FP32 rounding."""
+    dims = (17, 256, 15)
+    theta, _, X, T = _setup(dims, 2500, 4)
+    net = B.MLP(*dims)
+    net.set_params(theta)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Td = torch.tensor(T, dtype=torch.float32, device="cuda")
+    Y = net.forward(Xd).double().cpu().numpy()
+    L_fused = float(np.mean((Y - T) ** 2))
+    L_layer = net.loss_grad(Xd, Td)
+    assert L_fused == pytest.approx(L_layer, rel=1e-5), (L_fused, L_layer)
+    # after an Adam step the packed weights are refreshed
+    net.adam(1e-3)
+    Y2 = net.forward(Xd).double().cpu().numpy()
+    assert np.abs(Y2 - Y).max() > 0
+    L2 = net.loss_grad(Xd, Td)
+    assert float(np.mean((Y2 - T) ** 2)) == pytest.approx(L2, rel=1e-5)
