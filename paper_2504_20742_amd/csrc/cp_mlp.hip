@@ -260,12 +260,22 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, 
         for (int rb = 0; rb < 4; ++rb)
             #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the B fragments of the next k block are requested before this block's MFMAs
+        bf16x4 bn[4];
+        #pragma unroll
+        for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const bf16x4 *)&w.w2[((long)(4 * wave + cb) * 64 + lane) * 4];
+        #pragma unroll 1
         for (int kb = 0; kb < NB; ++kb) {
             bf16x4 a[4], b[4];
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Hs[16 * rb + lr][16 * kb + lk];
+            for (int cb = 0; cb < 4; ++cb) b[cb] = bn[cb];
+            if (kb + 1 < NB) {
+                #pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    bn[cb] = *(const bf16x4 *)&w.w2[(((long)(kb + 1) * NB + 4 * wave + cb) * 64 + lane) * 4];
+            }
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b[cb] = *(const bf16x4 *)&w.w2[(((long)kb * NB + 4 * wave + cb) * 64 + lane) * 4];
+            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Hs[16 * rb + lr][16 * kb + lk];
             #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
                 #pragma unroll
@@ -283,6 +293,7 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, 
         __syncthreads();
         // output layer: wave = 16-row block, one 16-column block
         f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+        #pragma unroll 4
         for (int kb = 0; kb < NB; ++kb) {
             const bf16x4 a = *(const bf16x4 *)&Hs[16 * wave + lr][16 * kb + lk];
             const bf16x4 b = *(const bf16x4 *)&w.w3[((long)kb * 64 + lane) * 4];
@@ -484,7 +495,7 @@ int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
 hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int n_out, const int *rows_dev,
                              int max_rows, float *Y, hipStream_t s)
 {
-    const int blocks = std::max(1, std::min((max_rows + 63) / 64, 512));
+    const int blocks = std::max(1, std::min((max_rows + 63) / 64, 1024));
     hipLaunchKernelGGL(k_mlp_fused, dim3(blocks), dim3(256), 0, s, X, n_in, n_out, rows_dev, max_rows, w, Y);
     return hipGetLastError();
 }
