@@ -126,6 +126,7 @@ int cp_step(cp_ctx *ctx, void *U, double dt);
 
 /* Global CFL time step (Sec. 3.2 "globally controlled CFL number"):
  *   dt = CFL min_cells 1 / ((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)).
+ * Evaluated in IEEE FP64 for CP_FP64 contexts and in FP32 for CP_MIXED contexts.
  * Synchronises the stream and writes *dt_host.                                   */
 int cp_cfl_dt(cp_ctx *ctx, const void *U, double *dt_host);
 

@@ -35,6 +35,8 @@ struct cp_ctx {
     void *Ua = nullptr, *Ub = nullptr;
     double *dt_d = nullptr, *t_d = nullptr, *diag_d = nullptr, *Qsur = nullptr;
     unsigned long long *acc_d = nullptr, *nsub_d = nullptr;
+    double *cfl_bm = nullptr;   // per-workgroup minima of the CFL kernel
+    int cfl_nb = 0;
     int *flag_d = nullptr;
     int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
     bool sur_ready = false;                         // a network snapshot is attached
@@ -409,6 +411,7 @@ int cfl_any(cp_ctx *c, const void *U, hipStream_t s)
         a.delta0 = c->cs.delta0_frac * c->cs.R_core;
         a.s_delta = c->cs.s_delta;
         a.acc = c->acc_d;
+        a.block_min = c->cfl_bm;
         return launch_cfl<R>(a, s);
     };
     e = c->precision == CP_FP64 ? fill((double *)nullptr) : fill((float *)nullptr);
@@ -547,11 +550,13 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
     c->t_d = dalloc<double>(c, 1);
     c->diag_d = dalloc<double>(c, 8);
     c->acc_d = dalloc<unsigned long long>(c, 1);
+    c->cfl_nb = ((c->nx + kCflBX - 1) / kCflBX) * ((c->nr + kCflBY - 1) / kCflBY);
+    c->cfl_bm = dalloc<double>(c, c->cfl_nb);
     c->nsub_d = dalloc<unsigned long long>(c, 1);
     c->flag_d = dalloc<int>(c, 1);
     c->act_count = dalloc<int>(c, 4);
     c->act_list = dalloc<int>(c, c->plane);
-    if (!c->act_count || !c->act_list ||!c->inflow || !c->ambient || !c->Ua || !c->Ub || !c->dt_d || !c->t_d || !c->diag_d || !c->acc_d ||
+    if (!c->act_count || !c->act_list ||!c->inflow || !c->ambient || !c->Ua || !c->Ub || !c->dt_d || !c->t_d || !c->diag_d || !c->acc_d || !c->cfl_bm ||
         !c->nsub_d || !c->flag_d)
         return bail(CP_ENOMEM);
     if (hipMemcpy(c->inflow, inflow.data(), inflow.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -633,7 +638,7 @@ int cp_cfl_dt(cp_ctx *c, const void *U, double *dt_host)
     if (!c || !U || !dt_host) return fail(c, CP_EINVAL, "null argument");
     int r = cfl_any(c, U, c->stream);
     if (r) return r;
-    hipError_t e = launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, nullptr, c->stream);
+    hipError_t e = launch_cfl_finalize_blocks(c->cfl_bm, c->cfl_nb, c->cs.cfl, c->dt_d, nullptr, c->stream);
     if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
     HIPCHK(c, hipMemcpyAsync(dt_host, c->dt_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if ((r = check_flag(c))) return r;
@@ -650,7 +655,8 @@ int capture_steps(cp_ctx *c, void *U, int steps, hipGraphExec_t *out)
     int r = 0;
     for (int k = 0; k < steps && !r; ++k) {
         r = cfl_any(c, U, c->cap_stream);
-        if (!r && launch_cfl_finalize(c->acc_d, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) != hipSuccess)
+        if (!r && launch_cfl_finalize_blocks(c->cfl_bm, c->cfl_nb, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) !=
+                      hipSuccess)
             r = fail(c, CP_EHIP, "finalize launch");
         if (!r) r = enqueue_step(c, U, 0.0, c->dt_d, c->cap_stream);
     }
@@ -922,6 +928,7 @@ template <class R> int batch_upload_args(cp_batch *b, void *const *U)
         a.delta0 = c->cs.delta0_frac * c->cs.R_core;
         a.s_delta = c->cs.s_delta;
         a.acc = b->acc + p;
+        a.block_min = nullptr;   // the batch merges into per-plume running minima
     }
     for (int s = 0; s < 3; ++s) {
         if (!b->stage_args[s]) b->stage_args[s] = balloc<StageArgs<R>>(b, n);

@@ -73,7 +73,9 @@ template <class R> struct CflArgs {
     const double *inv_dx, *inv_dr;
     double kappa_m, delta0, s_delta;
     unsigned long long *acc;   // running min of the per-cell limit (bits of a positive double)
+    double *block_min;         // tiled kernels: one minimum per workgroup (or null: use acc)
 };
+constexpr int kCflBX = 64, kCflBY = 4;   // tile of the CFL kernels
 
 struct Ctx;   // host context (cp_api.hip)
 }  // namespace cp
@@ -102,6 +104,8 @@ template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s);
 hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
+// dt = cfl * min(block_min[0..n)), t += dt (t nullable)
+hipError_t launch_cfl_finalize_blocks(const double *block_min, int n, double cfl, double *dt, double *t, hipStream_t s);
 template <class R>
 hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int *wt, int nwork, int tx, int ty,
                               hipStream_t s);

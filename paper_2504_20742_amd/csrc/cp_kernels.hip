@@ -803,12 +803,13 @@ __device__ __forceinline__ double cfl_limit(const CflArgs<R> &a, int i, int j, c
     return 1.0 / rate;
 }
 
-// Block minimum (wavefront shuffles, then LDS) merged into the running minimum.
-// The running minimum only decreases, so a block whose minimum is not below the
-// value it reads (possibly an older, larger one) has nothing to merge: this keeps
-// the atomics on the single reduction word to a few per launch instead of one per
-// workgroup, which would serialise.
-__device__ __forceinline__ void cfl_block_min(double best, unsigned long long *acc)
+// Block minimum (wavefront shuffles, then LDS).  With a per-workgroup array the
+// block writes its minimum there and the finalize kernel reduces the array (no
+// atomics on one word, which serialise across thousands of workgroups); otherwise
+// it is merged into the running minimum with a 64-bit atomic min, issued only when
+// it is below the value the block reads (the minimum only decreases).  A
+// non-positive limit is recorded as 0, so dt collapses to 0 (reported as CP_EDT).
+__device__ __forceinline__ void cfl_block_min(double best, unsigned long long *acc, double *block_min)
 {
     for (int o = 32; o > 0; o >>= 1) best = fmin(best, __shfl_xor(best, o, 64));
     __shared__ double part[16];
@@ -817,10 +818,93 @@ __device__ __forceinline__ void cfl_block_min(double best, unsigned long long *a
     if (threadIdx.x == 0) {
         double b = part[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmin(b, part[k]);
-        // non-positive limit: dt collapses to 0 (reported as CP_EDT)
-        const unsigned long long key = b > 0.0 ? (unsigned long long)__double_as_longlong(b) : 0ull;
-        if (key < __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(acc, key);
+        if (block_min) {
+            block_min[blockIdx.y * gridDim.x + blockIdx.x] = b > 0.0 ? b : 0.0;
+        } else {
+            const unsigned long long key = b > 0.0 ? (unsigned long long)__double_as_longlong(b) : 0ull;
+            if (key < __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(acc, key);
+        }
     }
+}
+
+// The same limit in the storage precision of the mixed path: FP32 arithmetic with the
+// hardware reciprocal and square root (the time step needs no more than the state it
+// advances); the minimum is merged as a double.
+struct PrimF {
+    float rho, u, v, T, Y;
+};
+
+__device__ __forceinline__ PrimF cfl_prim_f32(const float *U, long plane, const BcInfo &bc, int i, int j)
+{
+#pragma clang fp contract(off)   // the same operations wherever it is inlined
+    const CellSrc cs = map_cell(i, j, bc);
+    const float U0 = fetch(U, plane, bc, cs.code, 0);
+    float U1 = fetch(U, plane, bc, cs.code, 1);
+    float U2 = fetch(U, plane, bc, cs.code, 2);
+    const float U3 = fetch(U, plane, bc, cs.code, 3);
+    const float U4 = fetch(U, plane, bc, cs.code, 4);
+    if (cs.fu) U1 = -U1;
+    if (cs.fv) U2 = -U2;
+    const float ir = __builtin_amdgcn_rcpf(U0);
+    PrimF w;
+    w.rho = U0;
+    w.u = U1 * ir;
+    w.v = U2 * ir;
+    w.Y = U4 * ir;
+    const float e = U3 * ir - 0.5f * (w.u * w.u + w.v * w.v);
+    const float cv = (1.0f - w.Y) * float(kCva) + w.Y * float(kCvv);
+    w.T = (e + (1.0f - w.Y) * float(kCpa * kTref) - w.Y * float(kLv0 - kCpv * kTref)) * __builtin_amdgcn_rcpf(cv);
+    return w;
+}
+
+__device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, int j, const PrimF &w, float uN,
+                                               float uS, float vE, float vW)
+{
+#pragma clang fp contract(off)
+    const float dudr = (uN - uS) * __builtin_amdgcn_rcpf((float)(a.rc[j + 3] - a.rc[j + 1]));
+    const float dvdx = (vE - vW) * __builtin_amdgcn_rcpf((float)(a.xc[i + 3] - a.xc[i + 1]));
+    const float lm = (float)(a.kappa_m * (a.delta0 + a.s_delta * a.xc[i + 2]));
+    const float mut = w.rho * lm * lm * fabsf(dudr + dvdx);
+    const float Rm = (1.0f - w.Y) * float(kRa) + w.Y * float(kRv);
+    const float cpm = (1.0f - w.Y) * float(kCpa) + w.Y * float(kCpv);
+    const float cvm = (1.0f - w.Y) * float(kCva) + w.Y * float(kCvv);
+    const float gam = cpm * __builtin_amdgcn_rcpf(cvm);
+    const float snd = __builtin_amdgcn_sqrtf(gam * Rm * w.T);
+    const float t = w.T * float(1.0 / kTref);
+    const float mu = float(kMu0) * t * __builtin_amdgcn_sqrtf(t) * float(kTref + kSuth) * __builtin_amdgcn_rcpf(w.T + float(kSuth));
+    const float fac = fmaxf(gam * float(1.0 / kPr), 4.0f / 3.0f);
+    const float nu = (mu + mut) * __builtin_amdgcn_rcpf(w.rho) * fac;
+    const float idx = (float)a.inv_dx[i], idr = (float)a.inv_dr[j];
+    const float rate = (fabsf(w.u) + snd) * idx + (fabsf(w.v) + snd) * idr + 2.0f * nu * (idx * idx + idr * idr);
+    return __builtin_amdgcn_rcpf(rate);
+}
+
+template <int BX, int BY> __global__ void __launch_bounds__(BX *BY) k_cfl_tile_f32(CflArgs<float> a)
+{
+    constexpr int EXC = BX + 2, NEC = EXC * (BY + 2);
+    __shared__ float pr[5][NEC];
+    const BcInfo &bc = a.bc;
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    for (int e = threadIdx.x; e < NEC; e += BX * BY) {
+        const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
+        const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
+        pr[0][e] = w.rho;
+        pr[1][e] = w.u;
+        pr[2][e] = w.v;
+        pr[3][e] = w.T;
+        pr[4][e] = w.Y;
+    }
+    __syncthreads();
+    double best = __builtin_huge_val();
+    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i < bc.nx && j < bc.nr) {
+        const int l = (ty + 1) * EXC + tx + 1;
+        const PrimF w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
+        const double d = (double)cfl_limit_f32(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
+        if (d < best) best = d;
+    }
+    cfl_block_min(best, a.acc, a.block_min);
 }
 
 template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a, int bx, int nbx)
@@ -830,13 +914,21 @@ template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a,
     double best = __builtin_huge_val();
     for (int c = bx * blockDim.x + threadIdx.x; c < n; c += nbx * blockDim.x) {
         const int i = c % bc.nx, j = c / bc.nx;
-        const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
-        const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
-        const double vE = cfl_prim(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim(a.U, a.plane, bc, i - 1, j).v;
-        const double d = cfl_limit(a, i, j, w, uN, uS, vE, vW);
+        double d;
+        if constexpr (sizeof(R) == 4) {   // same arithmetic as k_cfl_tile_f32
+            const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
+            const float uN = cfl_prim_f32(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim_f32(a.U, a.plane, bc, i, j - 1).u;
+            const float vE = cfl_prim_f32(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim_f32(a.U, a.plane, bc, i - 1, j).v;
+            d = (double)cfl_limit_f32(a, i, j, w, uN, uS, vE, vW);
+        } else {
+            const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
+            const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
+            const double vE = cfl_prim(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim(a.U, a.plane, bc, i - 1, j).v;
+            d = cfl_limit(a, i, j, w, uN, uS, vE, vW);
+        }
         if (d < best) best = d;
     }
-    cfl_block_min(best, a.acc);
+    cfl_block_min(best, a.acc, nullptr);
 }
 
 // Tiled form: the primitives of a BX x BY tile and its 1-cell ring are computed
@@ -867,7 +959,7 @@ template <class R, int BX, int BY> __global__ void __launch_bounds__(BX *BY) k_c
         const double d = cfl_limit(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
         if (d < best) best = d;
     }
-    cfl_block_min(best, a.acc);
+    cfl_block_min(best, a.acc, a.block_min);
 }
 
 // batched: blockIdx.y selects the plume, each plume reduces into its own slot
@@ -895,6 +987,24 @@ __global__ void k_cfl_finalize(unsigned long long *acc, double cfl, double *dt, 
     *dt = d;
     if (t) *t = *t + d;
     *acc = 0x7FF0000000000000ull;   // +inf for the next reduction
+}
+
+// dt = cfl * (minimum of the per-workgroup minima), one workgroup.
+__global__ void __launch_bounds__(256) k_cfl_finalize_blocks(const double *bm, int n, double cfl, double *dt, double *t)
+{
+#pragma clang fp contract(off)
+    double m = __builtin_huge_val();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmin(m, bm[k]);
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmin(fmin(part[0], part[1]), fmin(part[2], part[3]));
+        const double d = cfl * m;
+        *dt = d;
+        if (t) *t = *t + d;
+    }
 }
 
 __global__ void k_acc_reset(unsigned long long *acc) { *acc = 0x7FF0000000000000ull; }
@@ -1092,9 +1202,18 @@ hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s)
 
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s)
 {
-    constexpr int BX = 64, BY = 4;
+    constexpr int BX = kCflBX, BY = kCflBY;
     dim3 grid((a.bc.nx + BX - 1) / BX, (a.bc.nr + BY - 1) / BY);
-    hipLaunchKernelGGL((k_cfl_tile<R, BX, BY>), grid, dim3(BX * BY), 0, s, a);
+    if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL((k_cfl_tile_f32<BX, BY>), grid, dim3(BX * BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_cfl_tile<R, BX, BY>), grid, dim3(BX * BY), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize_blocks(const double *block_min, int n, double cfl, double *dt, double *t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cfl_finalize_blocks, dim3(1), dim3(256), 0, s, block_min, n, cfl, dt, t);
     return hipGetLastError();
 }
 
