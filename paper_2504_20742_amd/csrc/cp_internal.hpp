@@ -82,14 +82,14 @@ struct Ctx;   // host context (cp_api.hip)
 
 struct cp_mlp;
 namespace cp {
-// Network weights for the fused inference kernel: bf16 weights in MFMA fragment
-// order (w1: 2 x 16 fragments, w2: 16 x 16, w3: 16 x 1; 256 bf16 each) and FP32
-// biases (b1, b2: 256, b3: 16, zero-padded).
+// Network weights for the fused inference kernel: bf16 weights in MFMA B-fragment
+// order for 32-deep k blocks (w1: 1 x 16 fragments, w2: 8 x 16, w3: 8 x 1; 512 bf16
+// each) and FP32 biases (b1, b2: 256, b3: 16, zero-padded).
 struct FusedNet {
     const uint16_t *w1, *w2, *w3;
     const float *b1, *b2, *b3;
 };
-constexpr long kFusedW1 = 2L * 16 * 256, kFusedW2 = 16L * 16 * 256, kFusedW3 = 16L * 1 * 256;
+constexpr long kFusedW1 = 1L * 16 * 512, kFusedW2 = 8L * 16 * 512, kFusedW3 = 8L * 1 * 512;
 
 // network hooks used by the solver (cp_mlp.hip).  The solver keeps its own packed
 // snapshot of the weights (taken by mlp_snapshot) and its own input/output rows.

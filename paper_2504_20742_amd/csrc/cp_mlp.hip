@@ -28,23 +28,27 @@ namespace cp {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t b = __float_as_uint(f);
-    b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
-    return (uint16_t)(b >> 16);
-}
+// round to nearest even (the hardware conversion on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
-__device__ __forceinline__ float gelu_f(float z)
+// GELU in tanh form, evaluated through 0.5 (1 + tanh u) = 1 / (1 + e^{-2u}) with the
+// hardware exp2 and reciprocal: z / (1 + e^{-2u}), u = sqrt(2/pi) (z + 0.044715 z^3).
+// The error is a few 1e-7 relative, far below the bf16 rounding of the activations;
+// e^{-2u} = inf gives 0 and e^{-2u} = 0 gives z, so it saturates cleanly.
+constexpr float kGeluE = -2.0f * kGeluC * 1.4426950408889634f;   // -2 sqrt(2/pi) log2(e)
+__device__ __forceinline__ float gelu_sig(float z)   // 1 / (1 + e^{-2u})
 {
-    return 0.5f * z * (1.0f + tanhf(kGeluC * (z + 0.044715f * z * z * z)));
+    const float u2 = z * fmaf(0.044715f, z * z, 1.0f);   // z + 0.044715 z^3
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(kGeluE * u2));
 }
+__device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
 __device__ __forceinline__ float gelu_grad_f(float z)
 {
-    const float t = tanhf(kGeluC * (z + 0.044715f * z * z * z));
-    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * 0.044715f * z * z);
+    // d/dz [z s(2u)] = s + 2 z s (1 - s) u'(z),  u' = sqrt(2/pi) (1 + 3 * 0.044715 z^2)
+    const float sg = gelu_sig(z);
+    return sg + 2.0f * z * sg * (1.0f - sg) * kGeluC * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
 enum { EPI_BIAS = 0, EPI_BIAS_GELU = 1, EPI_DGELU = 2, EPI_PARTIAL = 3 };
@@ -191,18 +195,25 @@ __global__ void __launch_bounds__(256) k_adam(float *p, float *m, float *v, cons
 }
 
 // ---------------------------------------------------------------- fused inference
-// Weights repacked in MFMA B-fragment order: fragment (kb, nb) of W[K][N] holds, for
-// lane l and i = 0..3, W[16 kb + 4 (l / 16) + i][16 nb + l % 16] (zero beyond K, N),
-// 256 bf16 in a row, fragments ordered kb-major.  Each lane then fetches its B
-// operand with one 8-byte load, and a wavefront reads 512 contiguous bytes.
+// gfx950 v_mfma_f32_16x16x32_bf16 (lane layout checked on the device): A operand of
+// lane l holds row l % 16, k = 8 (l / 16) + i; B operand k = 8 (l / 16) + i, column
+// l % 16; the 4 results are rows 4 (l / 16) + i, column l % 16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
+
+// Weights repacked in B-fragment order: fragment (kb, nb) of W[K][N] holds, for lane l
+// and i = 0..7, W[32 kb + 8 (l / 16) + i][16 nb + l % 16] (zero beyond K, N), 512 bf16
+// in a row, fragments ordered kb-major.  Each lane fetches its B operand with one
+// 16-byte load and a wavefront reads 1 KB contiguous.
 __global__ void __launch_bounds__(256) k_pack_frag(const uint16_t *W, int K, int N, int KB, int NB, uint16_t *dst)
 {
-    const long total = (long)KB * NB * 256;   // KB x NB fragments, zero beyond K, N
+    const long total = (long)KB * NB * 512;   // KB x NB fragments, zero beyond K, N
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-        const long f = e >> 8;
-        const int r = (int)(e & 255), lane = r >> 2, i = r & 3;
+        const long f = e >> 9;
+        const int r = (int)(e & 511), lane = r >> 3, i = r & 7;
         const int kb = (int)(f / NB), nb = (int)(f % NB);
-        const int k = 16 * kb + 4 * (lane >> 4) + i, n = 16 * nb + (lane & 15);
+        const int k = 32 * kb + 8 * (lane >> 4) + i, n = 16 * nb + (lane & 15);
         dst[e] = (k < K && n < N) ? W[(long)k * N + n] : (uint16_t)0;
     }
 }
@@ -210,18 +221,20 @@ __global__ void __launch_bounds__(256) k_pack_frag(const uint16_t *W, int K, int
 // All three layers for 64-row tiles in one launch (n_in <= 32, n_h = 256,
 // n_out <= 16): the input tile and each hidden activation stay in LDS, every wave
 // owns 64 output columns of a hidden layer (4 x 4 MFMA tiles of 16 x 16) and one
-// 16-row block of the output layer.  Rows past the device-side count are skipped;
-// the workgroups stride over the row tiles.
+// 16-row block of the output layer.  The B fragments of the next k block are
+// requested before the current block's MFMAs.  Rows past the device-side count are
+// skipped; the workgroups stride over the row tiles.
 constexpr int kFusedNH = 256, kFusedKin = 32, kFusedPad = 8;
-__global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, int n_out, const int *M_dev, int M_max,
+__global__ void __launch_bounds__(256, 2) k_mlp_fused(const uint16_t *X, int n_in, int n_out, const int *M_dev, int M_max,
                                                    FusedNet w, float *Y)
 {
     __shared__ uint16_t Xs[64][kFusedKin + kFusedPad];
     __shared__ uint16_t Hs[64][kFusedNH + kFusedPad];
     const int M = M_dev ? min(*M_dev, M_max) : M_max;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = 4 * (lane >> 4);   // A: row in block, first k; B/D: column
-    constexpr int NB = kFusedNH / 16;
+    const int lr = lane & 15, lk = 8 * (lane >> 4);   // A: row in block, first k; B/D: column
+    const int ld = 4 * (lane >> 4);                     // D: first row
+    constexpr int NB = kFusedNH / 16, KB = kFusedNH / 32;
     for (int m0 = blockIdx.x * 64; m0 < M; m0 += gridDim.x * 64) {
         for (int e = threadIdx.x; e < 64 * kFusedKin; e += 256) {
             const int r = e / kFusedKin, k = e % kFusedKin, m = m0 + r;
@@ -229,22 +242,18 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, 
         }
         __syncthreads();
         f32x4 acc[4][4];
-        // hidden layer 1: K = 32 (two k blocks)
-        #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        // hidden layer 1: K = 32, one k block
+        {
+            bf16x8 a[4], b[4];
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        #pragma unroll
-        for (int kb = 0; kb < kFusedKin / 16; ++kb) {
-            bf16x4 a[4], b[4];
+            for (int rb = 0; rb < 4; ++rb) a[rb] = ld_bf16x8(&Xs[16 * rb + lr][lk]);
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Xs[16 * rb + lr][16 * kb + lk];
-            #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b[cb] = *(const bf16x4 *)&w.w1[(((long)kb * NB + 4 * wave + cb) * 64 + lane) * 4];
+            for (int cb = 0; cb < 4; ++cb) b[cb] = ld_bf16x8(&w.w1[((long)(4 * wave + cb) * 64 + lane) * 8]);
             #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         }
         #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
@@ -252,34 +261,33 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, 
             for (int cb = 0; cb < 4; ++cb) {
                 const int col = 16 * (4 * wave + cb) + lr;
                 #pragma unroll
-                for (int i = 0; i < 4; ++i) Hs[16 * rb + lk + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b1[col]));
+                for (int i = 0; i < 4; ++i) Hs[16 * rb + ld + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b1[col]));
             }
         __syncthreads();
-        // hidden layer 2: K = 256
+        // hidden layer 2: K = 256, eight k blocks
         #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
             #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // the B fragments of the next k block are requested before this block's MFMAs
-        bf16x4 bn[4];
+        bf16x8 bn[4];
         #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const bf16x4 *)&w.w2[((long)(4 * wave + cb) * 64 + lane) * 4];
+        for (int cb = 0; cb < 4; ++cb) bn[cb] = ld_bf16x8(&w.w2[((long)(4 * wave + cb) * 64 + lane) * 8]);
         #pragma unroll 1
-        for (int kb = 0; kb < NB; ++kb) {
-            bf16x4 a[4], b[4];
+        for (int kb = 0; kb < KB; ++kb) {
+            bf16x8 a[4], b[4];
             #pragma unroll
             for (int cb = 0; cb < 4; ++cb) b[cb] = bn[cb];
-            if (kb + 1 < NB) {
+            if (kb + 1 < KB) {
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    bn[cb] = *(const bf16x4 *)&w.w2[(((long)(kb + 1) * NB + 4 * wave + cb) * 64 + lane) * 4];
+                for (int cb = 0; cb < 4; ++cb) bn[cb] = ld_bf16x8(&w.w2[(((long)(kb + 1) * NB + 4 * wave + cb) * 64 + lane) * 8]);
             }
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x4 *)&Hs[16 * rb + lr][16 * kb + lk];
+            for (int rb = 0; rb < 4; ++rb) a[rb] = ld_bf16x8(&Hs[16 * rb + lr][32 * kb + lk]);
             #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
         }
         __syncthreads();   // every wave has read the first activation
         #pragma unroll
@@ -288,20 +296,20 @@ __global__ void __launch_bounds__(256) k_mlp_fused(const uint16_t *X, int n_in, 
             for (int cb = 0; cb < 4; ++cb) {
                 const int col = 16 * (4 * wave + cb) + lr;
                 #pragma unroll
-                for (int i = 0; i < 4; ++i) Hs[16 * rb + lk + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b2[col]));
+                for (int i = 0; i < 4; ++i) Hs[16 * rb + ld + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b2[col]));
             }
         __syncthreads();
-        // output layer: wave = 16-row block, one 16-column block
+        // output layer: wave = 16-row block, one 16-column block, eight k blocks
         f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
         #pragma unroll 4
-        for (int kb = 0; kb < NB; ++kb) {
-            const bf16x4 a = *(const bf16x4 *)&Hs[16 * wave + lr][16 * kb + lk];
-            const bf16x4 b = *(const bf16x4 *)&w.w3[((long)kb * 64 + lane) * 4];
-            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+        for (int kb = 0; kb < KB; ++kb) {
+            const bf16x8 a = ld_bf16x8(&Hs[16 * wave + lr][32 * kb + lk]);
+            const bf16x8 b = ld_bf16x8(&w.w3[((long)kb * 64 + lane) * 8]);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
         }
         #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int m = m0 + 16 * wave + lk + i;
+            const int m = m0 + 16 * wave + ld + i;
             if (m < M && lr < n_out) Y[(long)m * n_out + lr] = c[i] + w.b3[lr];
         }
         __syncthreads();   // the next tile overwrites Xs and Hs
@@ -477,11 +485,11 @@ int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
     if (!mlp_fusable(n)) return CP_EUNSUPPORTED;
     // the network's own stream may still be updating the weights
     if (s != n->stream && hipStreamSynchronize(n->stream) != hipSuccess) return mfail(n, CP_EHIP, "sync");
-    constexpr int NB = kFusedNH / 16;
-    hipLaunchKernelGGL(k_pack_frag, dim3(32), dim3(256), 0, s, n->pb + n->off[0], n->n_in, n->n_h, kFusedKin / 16, NB,
+    constexpr int NB = kFusedNH / 16, KB = kFusedNH / 32;
+    hipLaunchKernelGGL(k_pack_frag, dim3(32), dim3(256), 0, s, n->pb + n->off[0], n->n_in, n->n_h, kFusedKin / 32, NB,
                        w);
-    hipLaunchKernelGGL(k_pack_frag, dim3(256), dim3(256), 0, s, n->pb + n->off[2], n->n_h, n->n_h, NB, NB, w + kFusedW1);
-    hipLaunchKernelGGL(k_pack_frag, dim3(16), dim3(256), 0, s, n->pb + n->off[4], n->n_h, n->n_out, NB, 1,
+    hipLaunchKernelGGL(k_pack_frag, dim3(256), dim3(256), 0, s, n->pb + n->off[2], n->n_h, n->n_h, KB, NB, w + kFusedW1);
+    hipLaunchKernelGGL(k_pack_frag, dim3(16), dim3(256), 0, s, n->pb + n->off[4], n->n_h, n->n_out, KB, 1,
                        w + kFusedW1 + kFusedW2);
     if (hipGetLastError() != hipSuccess) return mfail(n, CP_EHIP, "weight packing");
     if (hipMemsetAsync(b, 0, 528 * sizeof(float), s) != hipSuccess ||
