@@ -163,6 +163,28 @@ def run_source_active(binding, inputs, steps, warmup, trained):
     return out
 
 
+def run_mlp_inference(binding, net, rows, reps=5):
+    """The learned source's network on `rows` synthetic feature rows: the fused MFMA
+    inference kernel (all three layers in one launch), timed with HIP events."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(0)
+    X = torch.randn((rows, 17), generator=g).cuda()
+    for _ in range(3):
+        net.forward(X)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        net.forward(X)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    flop = rows * 2.0 * (17 * 256 + 256 * 256 + 256 * 15)
+    del X
+    torch.cuda.empty_cache()
+    return {"rows": rows, "ms": ms, "tflops": flop / ms / 1e9, "frac_of_bf16_dense_peak": flop / ms / 1e9 / 2500.0}
+
+
 def run_batch(binding, inputs, steps):
     """64 plumes on meshes drawn from {256x64, 512x128, 1024x256}, mixed precision,
     one graph replay per step covering every plume."""
@@ -218,6 +240,7 @@ def main():
     ap.add_argument("--active-steps", type=int, default=100, help="timed steps of the source-active jet (0: skip)")
     ap.add_argument("--active-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
+    ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -238,7 +261,7 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy calibration done (3 x 512 MiB)")
         del src, dst
-    paths = a.paths.split(",")
+    paths = [p for p in a.paths.split(",") if p]
     active = None
     trained = None
     if a.active_steps > 0 or "mixed_surrogate" in paths:
@@ -254,6 +277,20 @@ def main():
         log("bench: production jet, path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps))
         attach = (trained[0], trained[1].pack()) if p == "mixed_surrogate" else None
         res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach)
+    if a.mlp_rows > 0:
+        from paper_2504_20742_amd import surrogate
+        if trained is None:
+            net = binding.MLP(17, 256, 15)
+            net.set_params(surrogate.init_params(0))
+        else:
+            net = trained[0]
+        log("bench: network inference on %d rows" % a.mlp_rows)
+        mlp = run_mlp_inference(binding, net, a.mlp_rows)
+    else:
+        mlp = None
+    if not res:
+        print(json.dumps({"surrogate_inference": mlp}), flush=True)
+        return
     head_name = "mixed_surrogate" if "mixed_surrogate" in res else ("mixed" if "mixed" in res else "fp64")
     head = res[head_name]
     achieved = head["stage_bytes"] / (head["stage_ms"] / 1e3) / 1e9
@@ -286,6 +323,8 @@ def main():
                              for k, v in res.items() if k != "fp64"}
     if active is not None:
         line["source_active_2048x512"] = active
+    if mlp is not None:
+        line["surrogate_inference"] = mlp
     if a.batch_steps > 0:
         log("bench: 64-plume batch, %d steps" % a.batch_steps)
         line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)
