@@ -94,6 +94,11 @@ def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, ke
     out = dict(cell_updates_per_s=cells * steps / (ms / 1e3), ms_per_step=ms / steps, wall_s=wall,
                sim_time_s=sim_t, tile=list(s.get_tile()), max_lnS_l=d["max_lnS_l"],
                active_cells=d["active_cells"], esz=8 if precision == binding.CP_FP64 else 4, cells=cells)
+    if d["active_cells"] > 0:
+        # exact-source sub-steps over the timed steps, per cell-stage of the active set
+        subs = d["nsub_total"] - d0["nsub_total"]
+        out["source_substeps_per_step"] = subs / steps
+        out["mean_nsub_per_active_cell_stage"] = subs / (3.0 * steps * d["active_cells"])
     if sur is not None:
         n_net = d["surrogate_cells"] - d0["surrogate_cells"]
         n_fb = d["fallback_cells"] - d0["fallback_cells"]
@@ -183,6 +188,27 @@ def run_mlp_inference(binding, net, rows, reps=5):
     del X
     torch.cuda.empty_cache()
     return {"rows": rows, "ms": ms, "tflops": flop / ms / 1e9, "frac_of_bf16_dense_peak": flop / ms / 1e9 / 2500.0}
+
+
+def copy_bandwidth(gib=1.0, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `gib` GiB (bytes read
+    + written per second), beside the 8 TB/s peak."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    src = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 4, "ms": ms, "GBps": 2 * n * 4 / ms / 1e6, "frac_of_peak": 2 * n * 4 / ms / 1e6 / HBM_PEAK_GBS}
 
 
 def run_batch(binding, inputs, steps):
@@ -325,6 +351,8 @@ def main():
         line["source_active_2048x512"] = active
     if mlp is not None:
         line["surrogate_inference"] = mlp
+    log("bench: 1 GiB device copy (achievable HBM bandwidth)")
+    line["hbm_copy"] = copy_bandwidth()
     if a.batch_steps > 0:
         log("bench: 64-plume batch, %d steps" % a.batch_steps)
         line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)

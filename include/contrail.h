@@ -141,7 +141,8 @@ int cp_set_qmode(cp_ctx *ctx, int qmode);
 /* Diagnostics (synchronises): out[0] total water mass per radian
  * (vapour + 4pi/3 (rho_l M3 + rho_s N3), Eq. 25-26), out[1] max ln S_l (Eq. 1),
  * out[2] total ice number, out[3] gas mass, out[4] cells with an active source,
- * out[5] source sub-steps of the last cp_source call, out[6] and out[7] running
+ * out[5] sub-steps of the exact source since the last cp_source call (that call
+ * and every later step included), out[6] and out[7] running
  * totals of the active cells the surrogate (CP_Q_SURROGATE) sent to the network and
  * to the exact fallback, summed over every stage since cp_sur_set.              */
 int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
