@@ -96,6 +96,7 @@ template <class R, int TX, int TY> struct Tile {
     R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn;
                                  // the scalars' r slopes during the scalar phase
     int code[N];
+    int nonzero[2];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
     static_assert(7 * NF >= 5 * NR, "face buffer must hold five ring arrays");
 };
 
@@ -247,6 +248,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // directly; only boundary tiles go through the ghost-cell mapping.
     const bool inner = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= nx && j0 + TY + 2 <= nr;
 
+    if (tid == 0) t.nonzero[0] = t.nonzero[1] = 0;
     // phase 1: gas primitives of tile + halo
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
@@ -366,34 +368,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         }
     }
     // phase 5: passive scalars, five at a time in the freed primitive arrays, slopes
-    // once per cell.  T of the cell is kept for the source-activity test.
+    // once per cell.  T of the cell is kept for the source-activity test.  A scalar
+    // that is zero on the whole tile and halo (no particles there) has zero slopes
+    // and zero fluxes, so its slope and flux work is skipped: the result is the same
+    // zero (the stage output is bit-identical).
     const R Tcell = valid ? t.T[l] : R(0);
     #pragma unroll
     for (int g = 0; g < 2; ++g) {
         const int s0 = 5 + 5 * g;
         __syncthreads();
+        int nz = 0;
         if (inner) {
             for (int e = tid; e < NE; e += NT) {
                 const R *src = a.Uin + (long)s0 * a.plane + t.code[e];
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
-                for (int k = 0; k < 5; ++k) scalar_slot(t, k)[e] = per_mass(src[k * a.plane], rho, ir);
+                for (int k = 0; k < 5; ++k) {
+                    const R u = src[k * a.plane];
+                    nz |= (u != R(0)) << k;
+                    scalar_slot(t, k)[e] = per_mass(u, rho, ir);
+                }
             }
         } else {
             for (int e = tid; e < NE; e += NT) {
                 const int code = t.code[e];
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
-                for (int k = 0; k < 5; ++k)
-                    scalar_slot(t, k)[e] = per_mass(fetch(a.Uin, a.plane, bc, code, s0 + k), rho, ir);
+                for (int k = 0; k < 5; ++k) {
+                    const R u = fetch(a.Uin, a.plane, bc, code, s0 + k);
+                    nz |= (u != R(0)) << k;
+                    scalar_slot(t, k)[e] = per_mass(u, rho, ir);
+                }
             }
         }
+        if (nz) atomicOr(&t.nonzero[g], nz);
         __syncthreads();
+        const int live = t.nonzero[g];   // block-uniform
         R(*srs)[NRG] = reinterpret_cast<R(*)[NRG]>(&t.face[0][0]);   // r slopes in the free face buffer
         for (int r = tid; r < NRG; r += NT) {
             const int le = ext_of_ring<TX, TY>(r);
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
+                if (!(live & (1 << k))) continue;
                 const R *ph = scalar_slot(t, k);
                 t.sl[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
                 srs[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
@@ -403,6 +419,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         if (valid) {
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
+                if (!(live & (1 << k))) {
+                    res[s0 + k] = R(0);
+                    continue;
+                }
                 const R *ph = scalar_slot(t, k);
                 const R fw = scalar_face(ph, t.sl[k], l - 1, l, rl - 1, rl, Fm0, kd0);
                 const R fe = scalar_face(ph, t.sl[k], l, l + 1, rl, rl + 1, Fm1, kd1);
