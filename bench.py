@@ -71,10 +71,12 @@ def measured_traffic(tile):
         return None
 
 
-def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False):
+def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None):
     import torch
     s = binding.Solver(m, c, precision)
     U = s.init()
+    if tile:
+        s.set_tile(*tile)
     if sur is not None:
         s.sur_set(sur[0], sur[1])
         s.set_qmode(binding.CP_Q_SURROGATE)
@@ -267,6 +269,8 @@ def main():
     ap.add_argument("--active-warmup", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
     ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
+    ap.add_argument("--tile", default="", help="stage tile of the production-jet paths, e.g. 32x8 (default: autotuned)")
+    ap.add_argument("--hbm-copy-gib", type=float, default=1.0, help="size of the achievable-bandwidth copy (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -302,7 +306,8 @@ def main():
         prec = binding.CP_FP64 if p == "fp64" else binding.CP_MIXED
         log("bench: production jet, path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps))
         attach = (trained[0], trained[1].pack()) if p == "mixed_surrogate" else None
-        res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach)
+        tile = tuple(int(x) for x in a.tile.split("x")) if a.tile else None
+        res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach, tile=tile)
     if a.mlp_rows > 0:
         from paper_2504_20742_amd import surrogate
         if trained is None:
@@ -351,8 +356,9 @@ def main():
         line["source_active_2048x512"] = active
     if mlp is not None:
         line["surrogate_inference"] = mlp
-    log("bench: 1 GiB device copy (achievable HBM bandwidth)")
-    line["hbm_copy"] = copy_bandwidth()
+    if a.hbm_copy_gib > 0:
+        log("bench: %.1f GiB device copy (achievable HBM bandwidth)" % a.hbm_copy_gib)
+        line["hbm_copy"] = copy_bandwidth(a.hbm_copy_gib)
     if a.batch_steps > 0:
         log("bench: 64-plume batch, %d steps" % a.batch_steps)
         line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)

@@ -438,7 +438,7 @@ int autotune(cp_ctx *c, const void *U)
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     // Shapes are tried in the built order; a later shape must beat the best so far by
-    // more than 3% to replace it, so that run-to-run noise does not flip the choice.
+    // more than 5% to replace it, so that run-to-run noise does not flip the choice.
     float best = 1e30f;
     int btx = 32, bty = 8;
     for (auto &sh : tile_list()) {
@@ -455,7 +455,7 @@ int autotune(cp_ctx *c, const void *U)
         HIPCHK(c, hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < 0.97f * best) {
+        if (ms < 0.95f * best) {
             best = ms;
             btx = sh.first;
             bty = sh.second;
