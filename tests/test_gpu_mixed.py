@@ -82,3 +82,16 @@ def test_mixed_full_size_runs(B):
     assert abs(t32 - t64) / t64 < 1e-5
     d = (U32.double() - U64).abs().amax(dim=(1, 2)) / U64.abs().amax(dim=(1, 2)).clamp_min(1e-300)
     assert float(d[:5].max()) < 1e-4
+
+
+def test_mixed_cfl_matches_fp64(B):
+    """The mixed path evaluates the CFL limit in FP32: on the same state it agrees
+    with the FP64 limit to FP32 accuracy."""
+    for m, c in (inputs.config1(2), inputs.sa1(2), inputs.config2(0, 256, 64)):
+        s64 = B.Solver(m, c, B.CP_FP64)
+        U64 = s64.init()
+        s64.step_n(U64, 30)
+        s32 = B.Solver(m, c, B.CP_MIXED)
+        dt64 = s64.cfl_dt(U64)
+        dt32 = s32.cfl_dt(U64.float().contiguous())
+        assert abs(dt32 - dt64) / dt64 < 2e-6, (dt32, dt64)

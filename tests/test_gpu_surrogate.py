@@ -190,3 +190,48 @@ def test_surrogate_gain(B, S):
     print("gain %.3f (exact %.3f ms/step, surrogate %.3f ms/step, network/fallback cells %s, train %s)"
           % (gain, 1e3 * times["exact"], 1e3 * times["surrogate"], fr, rep["final_val_loss"]))
     assert gain > 0
+
+
+def test_attach_snapshots_the_weights(B, trained):
+    """cp_sur_set copies the weights: training the network afterwards leaves the
+    context's source unchanged until it is attached again."""
+    net, norm, _ = trained
+    s, U = _state(B, 2, 300)   # a state with network cells (see the closure test)
+    dt = s.cfl_dt(U)
+    s.sur_set(net, norm.pack())
+    s.set_qmode(B.CP_Q_SURROGATE)
+    Q1 = s.source(U, dt).cpu().numpy()
+    assert s.diag(U)["surrogate_cells"] > 0
+    theta = net.get_params()
+    X = torch.zeros((64, 17), device="cuda")
+    net.loss_grad(X, torch.ones((64, 15), device="cuda"))
+    net.adam(1e-2)                       # the network changes ...
+    Q2 = s.source(U, dt).cpu().numpy()   # ... the attached copy does not
+    assert np.array_equal(Q1, Q2)
+    s.sur_set(net, norm.pack())          # re-attaching takes the new weights
+    s.set_qmode(B.CP_Q_SURROGATE)
+    Q3 = s.source(U, dt).cpu().numpy()
+    assert not np.array_equal(Q1, Q3)
+    net.set_params(theta)                # restore for the other tests
+    s.close()
+
+
+def test_attach_errors(B, trained, S):
+    net, norm, _ = trained
+    m, c = inputs.sa1(1)
+    s = B.Solver(m, c, B.CP_MIXED)
+    with pytest.raises(B.ContrailError) as e:
+        s.set_qmode(B.CP_Q_SURROGATE)          # nothing attached
+    assert e.value.code == B.CP_ESTATE
+    with pytest.raises(B.ContrailError) as e:
+        s.sur_set(net, norm.pack()[:-1])       # wrong block size
+    assert e.value.code == B.CP_EINVAL
+    small = B.MLP(17, 64, 15)
+    with pytest.raises(B.ContrailError) as e:
+        s.sur_set(small, norm.pack())          # the in-step kernel needs 256 hidden units
+    assert e.value.code == B.CP_EUNSUPPORTED
+    other = B.MLP(17, 256, 14)
+    with pytest.raises(B.ContrailError) as e:
+        s.sur_set(other, norm.pack())          # must map 17 features to 15 sources
+    assert e.value.code == B.CP_EINVAL
+    s.close()
