@@ -42,11 +42,17 @@ def stage_bytes_per_cell(esz):
     return (2 * 15 * esz + 3 * 15 * esz + 3 * 15 * esz) / 3.0
 
 
-def kernel_source_hash():
+def kernel_source_hash(root=ROOT):
+    """Hash of the stage-kernel sources with comments and white space removed (a
+    comment edit does not change the kernel the counters were taken on)."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root, p)) as f:
+            txt = f.read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(" ".join(txt.split()).encode())
     return h.hexdigest()[:16]
 
 
