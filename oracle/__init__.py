@@ -93,6 +93,8 @@ def lib():
         L.or_run.argtypes = [_V, _P, ctypes.c_int]
         L.or_diag.argtypes = [_V, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
+        L.or_set_area.restype = ctypes.c_int
+        L.or_set_area.argtypes = [_V, _P]
         L.or_case_derived.argtypes = [_V, _P]
         L.or_source_cell.restype = ctypes.c_int
         L.or_source_cell.argtypes = [_V, _P, _D, _P]
@@ -172,6 +174,13 @@ class Oracle:
         out = np.zeros(4)
         self.L.or_diag(self.h, _ptr(U), _ptr(out))
         return {"water": out[0], "max_lnS_l": out[1], "ice_number": out[2], "gas_mass": out[3]}
+
+    def set_area(self, area):
+        """Quasi-1D duct only: cross-section areas at the nx+1 x faces."""
+        a = np.ascontiguousarray(area, dtype=np.float64)
+        assert a.shape == (self.nx + 1,)
+        if self.L.or_set_area(self.h, _ptr(a)) != 0:
+            raise ValueError("or_set_area: needs the quasi-1D geometry, nr = 1 and positive areas")
 
     def faces(self):
         xf = np.zeros(self.nx + 1)

@@ -68,7 +68,7 @@ typedef struct {
     double sx_ratio;     /* ratio of successive axial widths (1 = uniform)        */
     double r_cluster;    /* radius the radial cells cluster about (<=0: uniform)  */
     double beta_r;       /* clustering strength                                   */
-    int geom;            /* 0 axisymmetric, 1 planar                              */
+    int geom;            /* 0 axisymmetric, 1 planar, 2 quasi-1D duct (nr = 1)    */
     int bc_xlo, bc_xhi, bc_rlo, bc_rhi;  /* 0 inflow,1 copy,2 wall,3 far field    */
 } or_mesh;
 
@@ -88,12 +88,14 @@ typedef struct {
 } or_case;
 
 enum { BC_INFLOW = 0, BC_COPY = 1, BC_WALL = 2, BC_FARFIELD = 3 };
+enum { GEOM_AXI = 0, GEOM_PLANAR = 1, GEOM_Q1D = 2 };
 
 typedef struct {
     or_mesh m;
     or_case c;
     int nx, nr;
     double *xf, *rf, *xc, *rc, *dx, *dr;
+    double *ax;                 /* quasi-1D: duct area at the nx+1 x faces         */
     double *inflow;             /* nr x NV: Dirichlet inflow state by row          */
     double ambient[NV];
     double Y_amb, u_amb;
@@ -605,6 +607,10 @@ or_ctx *or_create(const or_mesh *m, const or_case *c)
     cx->nx = m->nx;
     cx->nr = m->nr;
     build_mesh(cx);
+    if (m->geom == GEOM_Q1D) {
+        cx->ax = malloc(sizeof(double) * (m->nx + 1));
+        for (int i = 0; i <= m->nx; ++i) cx->ax[i] = 1.0;   /* a straight duct until set */
+    }
     /* ambient: vapour partial pressure from the ice relative humidity */
     double pv = c->RH_ice * exp(or_ln_psat_ice(c->T_amb));
     double rho_v = pv / (RGAS_VAP * c->T_amb);
@@ -634,7 +640,20 @@ void or_destroy(or_ctx *cx)
     if (!cx) return;
     free(cx->xf); free(cx->rf); free(cx->xc); free(cx->rc); free(cx->dx); free(cx->dr);
     free(cx->inflow);
+    free(cx->ax);
     free(cx);
+}
+
+/* Quasi-1D duct: the cross-section area at the nx+1 x faces (all > 0).  The
+ * duct has one row of cells; walls close it in r.  Returns -1 for other
+ * geometries or a non-positive area.                                            */
+int or_set_area(or_ctx *cx, const double *area)
+{
+    if (cx->m.geom != GEOM_Q1D || cx->nr != 1) return -1;
+    for (int i = 0; i <= cx->nx; ++i)
+        if (!(area[i] > 0.0)) return -1;
+    memcpy(cx->ax, area, sizeof(double) * (cx->nx + 1));
+    return 0;
 }
 
 void or_mesh_faces(const or_ctx *cx, double *xf, double *rf)
@@ -897,8 +916,21 @@ static void face_flux(const or_ctx *cx, const field_t *f, int dir, int i, int j,
     for (int m = 0; m < NV; ++m) Fout[m] = Fg[m] - Fv[m];
 }
 
+/* Cell volume: per radian (axisymmetric), per unit depth (planar), or the
+ * trapezoidal duct volume 0.5 (A_w + A_e) dx (quasi-1D).                        */
+static double cell_volume(const or_ctx *cx, int i, int j)
+{
+    if (cx->m.geom == GEOM_Q1D) return 0.5 * (cx->ax[i] + cx->ax[i + 1]) * cx->dx[i];
+    if (cx->m.geom == GEOM_AXI) return RC(j) * cx->dr[j] * cx->dx[i];
+    return cx->dr[j] * cx->dx[i];
+}
+
 /* Transport residual per unit volume: -(1/V) sum_faces (Fc - Fv).A plus the
- * axisymmetric pressure / hoop-stress source on radial momentum.                */
+ * axisymmetric pressure / hoop-stress source on radial momentum.  In the
+ * quasi-1D duct the x faces carry the duct areas, there are no r faces, and the
+ * walls push on the gas with p (A_e - A_w) along x: the textbook quasi-1D Euler
+ * equations, d(rho u A)/dx = 0, d((rho u^2 + p) A)/dx = p dA/dx, in finite-volume
+ * form.                                                                         */
 static void transport_residual(const or_ctx *cx, const double *U, double *Rout)
 {
     const int nx = cx->nx, nr = cx->nr;
@@ -915,9 +947,11 @@ static void transport_residual(const or_ctx *cx, const double *U, double *Rout)
         for (int i = 0; i < nx; ++i) {
             double *F = Fr + NV * ((size_t)(j + 1) * nx + i);
             if (cx->m.geom == 0 && j == -1) continue;       /* axis face: zero area */
+            if (cx->m.geom == GEOM_Q1D) continue;           /* duct: no r faces     */
             face_flux(cx, &f, 1, i, j, F);
         }
     const int axi = cx->m.geom == 0;
+    const int q1d = cx->m.geom == GEOM_Q1D;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -939,6 +973,16 @@ static void transport_residual(const or_ctx *cx, const double *U, double *Rout)
                 double mue = FS(&f, mu, i, j) + FS(&f, mut, i, j);
                 double tau_tt = mue * (2.0 * vr - 2.0 / 3.0 * div);
                 Sax = (w->p - tau_tt) * cx->dx[i] * cx->dr[j];
+            }
+            if (q1d) {
+                double Aw = cx->ax[i], Ae = cx->ax[i + 1];
+                double Vq = cell_volume(cx, i, j);
+                for (int v = 0; v < NV; ++v) {
+                    double Rv = -(Fe[v] * Ae - Fw[v] * Aw);
+                    if (v == 1) Rv += FW(&f, i, j).p * (Ae - Aw);
+                    Rout[v * plane + (size_t)j * nx + i] = Rv / Vq;
+                }
+                continue;
             }
             for (int v = 0; v < NV; ++v) {
                 double net = (Fe[v] - Fw[v]) * Ax + (Fn[v] * An - Fs[v] * As);
@@ -992,6 +1036,8 @@ int or_cfl_dt(const or_ctx *cx, const double *U, double *dt_out)
             double nu = (FS(&f, mu, i, j) + FS(&f, mut, i, j)) / w->rho * fac;
             double rate = (fabs(w->u) + w->c) * idx + (fabs(w->v) + w->c) * idr
                           + 2.0 * nu * (idx * idx + idr * idr);
+            if (cx->m.geom == GEOM_Q1D)      /* the duct has no r direction */
+                rate = (fabs(w->u) + w->c) * idx + 2.0 * nu * idx * idx;
             double d = 1.0 / rate;
             if (d < best) best = d;
         }
@@ -1037,12 +1083,11 @@ void or_diag(const or_ctx *cx, const double *U, double *out)
 {
     const int nx = cx->nx, nr = cx->nr;
     const size_t plane = (size_t)nx * nr;
-    const int axi = cx->m.geom == 0;
     double water = 0.0, lnS = -HUGE_VAL, nice = 0.0, gas = 0.0;
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t k = (size_t)j * nx + i;
-            double V = axi ? RC(j) * cx->dr[j] * cx->dx[i] : cx->dr[j] * cx->dx[i];
+            double V = cell_volume(cx, i, j);
             water += V * (U[4 * plane + k] + 4.0 / 3.0 * PI * (RHO_LIQ * U[8 * plane + k] + RHO_ICE * U[12 * plane + k]));
             nice += V * U[9 * plane + k];
             gas += V * U[k];

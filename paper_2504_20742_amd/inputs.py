@@ -14,7 +14,7 @@ activates the phase-change source.
 import numpy as np
 
 BC_INFLOW, BC_COPY, BC_WALL, BC_FARFIELD = 0, 1, 2, 3
-GEOM_AXI, GEOM_PLANAR = 0, 1
+GEOM_AXI, GEOM_PLANAR, GEOM_QUASI1D = 0, 1, 2
 
 _CASE_DEFAULTS = dict(
     p_amb=23800.0, T_amb=218.0, RH_ice=1.1, mach_amb=0.8,

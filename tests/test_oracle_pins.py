@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2504_20742_amd import inputs
+from tests import exact_nozzle
 from tests.exact_riemann import sample as riemann_sample
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -391,6 +392,84 @@ def test_sod_shock_tube_against_exact_riemann(orc):
     p_star = W[(xc > 0.55) & (xc < 0.62), 3]
     ex_p = ex[2][(xc > 0.55) & (xc < 0.62)]
     assert np.allclose(p_star, ex_p, rtol=1e-2)
+
+
+def _gas_constants(orc):
+    """Isentropic exponent and gas constant of dry air in the oracle's gas model."""
+    W = np.zeros(15)
+    W[0], W[3] = 1.0, 1.0e5
+    P = orc.cons_to_prim(orc.prim_to_cons(W))
+    return P[16] ** 2 * P[0] / P[3], P[3] / (P[0] * P[15])
+
+
+def _nozzle_steady(orc, nx, tol=1e-12, chunk=100, max_steps=40000):
+    """March the quasi-1D test duct from the exact cell-centre state to the
+    scheme's own steady state (relative change per chunk of steps below tol)."""
+    g, R = _gas_constants(orc)
+    m, c, area, xc, Mex, Wex = exact_nozzle.nozzle_setup(nx, g, R)
+    o = orc.Oracle(m, c)
+    o.set_area(area)
+    U = o.empty()
+    for i in range(nx):
+        W = np.zeros(15)
+        W[0], W[1], W[3] = Wex[i]
+        U[:, 0, i] = orc.prim_to_cons(W)
+    steps = 0
+    while True:
+        U0 = U.copy()
+        o.run(U, chunk)
+        steps += chunk
+        d = max(np.abs(U[v] - U0[v]).max() / np.abs(U0[v]).max() for v in (0, 1, 3))
+        assert np.isfinite(d), (nx, steps)
+        if d < tol:
+            break
+        assert steps < max_steps, (nx, d)
+    P = np.array([orc.cons_to_prim(U[:, 0, i].copy()) for i in range(nx)])
+    return o, U, area, xc, Mex, P, g, R
+
+
+def test_quasi1d_nozzle_against_area_mach_relation(orc):
+    """P10 (Sec. 3.2 convective flux, MUSCL / van Leer, SSP-RK3): phase change off,
+    the steady flow through a choked converging-diverging duct (subsonic inflow,
+    supersonic exit) matches the exact isentropic area-Mach relation with observed
+    order about 2 under refinement, and the entropy stays constant to truncation
+    (its deviation also falls at second order).  Errors in the L1 norm over cells:
+    the zero-gradient exit cell is first order by construction, which the L1 norm
+    sees at O(dx^2)."""
+    eM, es = [], []
+    for nx in (50, 100, 200):
+        o, U, area, xc, Mex, P, g, R = _nozzle_steady(orc, nx)
+        M = P[:, 1] / P[:, 16]
+        assert np.all(M[xc < 0.45] < 1.0) and np.all(M[xc > 0.55] > 1.0)
+        # entropy relative to the stagnation state: ds/R = ln((p/p0) (rho0/rho)^g) / (g - 1)
+        rho0 = exact_nozzle.P0 / (R * exact_nozzle.T0)
+        ds = np.log(P[:, 3] / exact_nozzle.P0 * (rho0 / P[:, 0]) ** g) / (g - 1.0)
+        eM.append(np.mean(np.abs(M - Mex)))
+        es.append(np.mean(np.abs(ds)))
+        # the mass flux rho u A is one constant at steady state (conservative faces):
+        # the exit face carries the exit cell's own flux, the exact value is rho* c* A*
+        mdot_exit = P[-1, 0] * P[-1, 1] * area[-1]
+        rs, us, ps, Ts = exact_nozzle.static_state(1.0, exact_nozzle.P0, exact_nozzle.T0, g, R)
+        assert abs(mdot_exit / (rs * us * 1.0) - 1.0) < 40.0 / nx ** 2
+    orders_M = np.log2(np.array(eM[:-1]) / np.array(eM[1:]))
+    orders_s = np.log2(np.array(es[:-1]) / np.array(es[1:]))
+    print("L1 Mach errors", eM, "orders", orders_M, "entropy", es, "orders", orders_s)
+    assert np.all(orders_M > 1.85) and np.all(orders_M < 2.2)
+    assert np.all(orders_s > 1.85)
+    assert eM[-1] < 1e-4 and es[-1] < 2e-5
+
+    # the cell volume is the trapezoid 0.5 (A_w + A_e) dx: the volume-weighted sum of
+    # the mass residual telescopes to the two boundary face fluxes, which a
+    # perturbation of interior cells leaves unchanged
+    nx = o.nx
+    V = 0.5 * (area[1:] + area[:-1]) / nx
+    R0 = o.residual(U)
+    Up = U.copy()
+    Up[:, 0, 20:30] *= 1.0 + 0.01 * np.sin(np.arange(10))[None, :]
+    R1 = o.residual(Up)
+    mdot = P[-1, 0] * P[-1, 1] * area[-1]
+    assert np.abs(R1[0, 0, 20:30]).max() * V[20] > 1e-4 * mdot       # the perturbation is seen
+    assert abs(np.sum(V * R1[0, 0]) - np.sum(V * R0[0, 0])) < 1e-12 * mdot
 
 
 def test_viscous_stress_quadratic_shear(orc):
