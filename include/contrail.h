@@ -66,7 +66,12 @@ enum cp_qmode {
     CP_Q_OFF = 2           /* no phase change                                       */
 };
 
-enum cp_geom { CP_GEOM_AXI = 0, CP_GEOM_PLANAR = 1 };
+/* AXI: r-weighted axisymmetric cells (Sec. 4.1).  PLANAR: unit-depth cells.
+ * QUASI1D: a duct of one cell row (nr = 1) whose x faces have the areas area_x;
+ * the cell volume is 0.5 (A_w + A_e) dx, there are no r faces, and the walls push
+ * on the gas with p (A_e - A_w) along x (the quasi-1D Euler equations in
+ * finite-volume form; a verification geometry for the transport scheme).       */
+enum cp_geom { CP_GEOM_AXI = 0, CP_GEOM_PLANAR = 1, CP_GEOM_QUASI1D = 2 };
 
 /* Boundary treatment per side (Sec. 4.1: inflow streams, far field).
  *  INFLOW   (x = 0 only): Dirichlet core / bypass / ambient state by radius
@@ -76,13 +81,16 @@ enum cp_geom { CP_GEOM_AXI = 0, CP_GEOM_PLANAR = 1 };
 enum cp_bc { CP_BC_INFLOW = 0, CP_BC_COPY = 1, CP_BC_WALL = 2, CP_BC_FARFIELD = 3 };
 
 typedef struct {
-    int nx, nr;            /* cells, both >= 2                                      */
+    int nx, nr;            /* cells: both >= 2; nr = 1 for CP_GEOM_QUASI1D          */
     double Lx, Lr;         /* domain [0, Lx] x [0, Lr] in metres                    */
     double sx_ratio;       /* ratio of successive axial widths (1 = uniform)        */
     double r_cluster;      /* radius the radial cells cluster about (<= 0: uniform) */
     double beta_r;         /* sinh clustering strength                              */
     int geom;              /* cp_geom                                               */
     int bc_xlo, bc_xhi, bc_rlo, bc_rhi;   /* cp_bc per side                         */
+    const double *area_x;  /* CP_GEOM_QUASI1D: host array of the nx+1 duct areas at
+                              the x faces, each finite and > 0; copied by cp_create
+                              (the caller keeps ownership).  Ignored otherwise.    */
 } cp_mesh;
 
 typedef struct {
@@ -102,7 +110,10 @@ typedef struct {
 
 /* Create a context for one mesh + operating point.  precision: cp_precision.
  * hip_stream: a hipStream_t (NULL = default stream).  On success *out owns the
- * workspace; release with cp_destroy.  Errors: CP_EINVAL, CP_ENOMEM, CP_EHIP.    */
+ * workspace; release with cp_destroy.  Errors: CP_EINVAL (sizes, an unknown
+ * geometry or boundary, bc_rlo other than WALL, INFLOW at x = Lx or r = Lr; for
+ * CP_GEOM_QUASI1D also nr != 1, bc_rhi other than WALL, a null area_x or an area
+ * that is not finite and > 0), CP_ENOMEM, CP_EHIP.                              */
 int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_stream, cp_ctx **out);
 void cp_destroy(cp_ctx *ctx);
 
@@ -111,7 +122,8 @@ void cp_destroy(cp_ctx *ctx);
 int cp_init(cp_ctx *ctx, void *U);
 
 /* Transport residual per unit volume (Eq. 22 without Q):
- *   R = -(1/V) sum_faces (F^c - F^v) . A  +  (p - tau_thetatheta) dx dr / V  on rho v.  */
+ *   R = -(1/V) sum_faces (F^c - F^v) . A  +  (p - tau_thetatheta) dx dr / V  on rho v
+ * (axisymmetric), or + p (A_e - A_w) / V on rho u (quasi-1D duct).              */
 int cp_residual(cp_ctx *ctx, const void *U, void *R);
 
 /* Phase-change source integrated over dt (Sec. 2.2 rates, evaluated explicitly per
@@ -125,7 +137,8 @@ int cp_source(cp_ctx *ctx, const void *U, double dt, void *Q);
 int cp_step(cp_ctx *ctx, void *U, double dt);
 
 /* Global CFL time step (Sec. 3.2 "globally controlled CFL number"):
- *   dt = CFL min_cells 1 / ((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)).
+ *   dt = CFL min_cells 1 / ((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)),
+ * without the 1/dr terms in the quasi-1D duct.
  * Evaluated in IEEE FP64 for CP_FP64 contexts and in FP32 for CP_MIXED contexts.
  * Synchronises the stream and writes *dt_host.                                   */
 int cp_cfl_dt(cp_ctx *ctx, const void *U, double *dt_host);
@@ -173,7 +186,8 @@ const char *cp_error_string(const cp_ctx *ctx);
 typedef struct cp_batch cp_batch;
 
 /* n plumes with meshes[p], cases[p] (host arrays of n structs), all in one precision,
- * launched on hip_stream.  Errors as cp_create.                                     */
+ * launched on hip_stream.  Errors as cp_create; CP_EUNSUPPORTED for a quasi-1D duct
+ * (the batch runs axisymmetric and planar plumes).                                */
 int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int precision, void *hip_stream,
                     cp_batch **out);
 void cp_batch_destroy(cp_batch *b);

@@ -131,6 +131,8 @@ class Oracle:
         self._c = make_case(case)
         self.nx, self.nr = int(mesh["nx"]), int(mesh["nr"])
         self.h = self.L.or_create(ctypes.byref(self._m), ctypes.byref(self._c))
+        if mesh.get("area_x") is not None:
+            self.set_area(mesh["area_x"])
 
     def __del__(self):
         try:

@@ -1030,14 +1030,13 @@ int or_cfl_dt(const or_ctx *cx, const double *U, double *dt_out)
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < nx; ++i) {
             const prim_t *w = &FW(&f, i, j);
-            double idx = 1.0 / cx->dx[i], idr = 1.0 / cx->dr[j];
+            /* the quasi-1D duct has no r direction: its r terms vanish */
+            double idx = 1.0 / cx->dx[i], idr = cx->m.geom == GEOM_Q1D ? 0.0 : 1.0 / cx->dr[j];
             double fac = w->gam / PRANDTL;
             if (fac < 4.0 / 3.0) fac = 4.0 / 3.0;
             double nu = (FS(&f, mu, i, j) + FS(&f, mut, i, j)) / w->rho * fac;
             double rate = (fabs(w->u) + w->c) * idx + (fabs(w->v) + w->c) * idr
                           + 2.0 * nu * (idx * idx + idr * idr);
-            if (cx->m.geom == GEOM_Q1D)      /* the duct has no r direction */
-                rate = (fabs(w->u) + w->c) * idx + 2.0 * nu * idx * idx;
             double d = 1.0 / rate;
             if (d < best) best = d;
         }

@@ -34,7 +34,8 @@ class CpMesh(ctypes.Structure):
                 ("sx_ratio", ctypes.c_double), ("r_cluster", ctypes.c_double),
                 ("beta_r", ctypes.c_double), ("geom", ctypes.c_int),
                 ("bc_xlo", ctypes.c_int), ("bc_xhi", ctypes.c_int),
-                ("bc_rlo", ctypes.c_int), ("bc_rhi", ctypes.c_int)]
+                ("bc_rlo", ctypes.c_int), ("bc_rhi", ctypes.c_int),
+                ("area_x", ctypes.POINTER(ctypes.c_double))]
 
 
 _CASE_D = ["p_amb", "T_amb", "RH_ice", "mach_amb", "R_core", "u_core", "T_core", "Y_core",
@@ -122,7 +123,19 @@ def _ptr(x):
 
 
 def make_mesh(m):
-    return CpMesh(**{k: m[k] for k, _ in CpMesh._fields_})
+    """cp_mesh from a mesh dict; a quasi-1D mesh carries its nx+1 face areas as
+    'area_x'.  The returned struct keeps the area array alive (cp_create copies it)."""
+    d = {k: m[k] for k, _ in CpMesh._fields_ if k != "area_x"}
+    cm = CpMesh(**d)
+    a = m.get("area_x")
+    if a is not None:
+        import numpy as np
+        arr = np.ascontiguousarray(a, dtype=np.float64)
+        if arr.shape != (int(m["nx"]) + 1,):
+            raise ValueError("area_x needs nx+1 values")
+        cm.area_x = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cm._area_keep = arr
+    return cm
 
 
 def make_case(c):
@@ -281,7 +294,8 @@ class Batch:
         self.L = load()
         self.n = len(meshes)
         self.precision = precision
-        self._m = (CpMesh * self.n)(*[make_mesh(m) for m in meshes])
+        self._mesh_structs = [make_mesh(m) for m in meshes]   # keep any area arrays alive
+        self._m = (CpMesh * self.n)(*self._mesh_structs)
         self._c = (CpCase * self.n)(*[make_case(c) for c in cases])
         self.shapes = [(int(m["nr"]), int(m["nx"])) for m in meshes]
         h = _P()

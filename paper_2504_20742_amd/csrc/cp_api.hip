@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -17,7 +18,7 @@
 using namespace cp;
 
 enum { M_XC, M_RC, M_INV_DXF, M_INV_DRF, M_INV_D2X, M_INV_D2R, M_LM2, M_INV_DX, M_RFA, M_INVV_R, M_INV_RC,
-       M_INV_RF, M_COUNT };
+       M_INV_RF, M_AXF, M_INVVX, M_COUNT };
 
 struct cp_ctx {
     int precision = CP_FP64;
@@ -28,6 +29,7 @@ struct cp_ctx {
     int nx = 0, nr = 0;
     long plane = 0;
     std::vector<double> xf, rf, xc, rc, dx, dr;     // host mesh
+    std::vector<double> ax;                         // quasi-1D duct areas at the x faces
     std::vector<void *> allocs;                     // device memory owned by the context
     double *inflow = nullptr, *ambient = nullptr, *vol = nullptr;
     double *xc_d = nullptr, *rc_d = nullptr, *inv_dx_d = nullptr, *inv_dr_d = nullptr;
@@ -170,6 +172,7 @@ template <class R> int upload_metrics(cp_ctx *c)
 {
     const int nx = c->nx, nr = c->nr;
     const bool axi = c->mesh.geom == CP_GEOM_AXI;
+    const bool q1d = c->mesh.geom == CP_GEOM_QUASI1D;
     auto XC = [&](int i) { return c->xc[i + 2]; };
     auto RC = [&](int j) { return c->rc[j + 2]; };
     std::vector<double> inv_dxf(nx + 1), inv_drf(nr + 1), inv_d2x(nx + 2), inv_d2r(nr + 2), lm2(nx + 2),
@@ -188,12 +191,19 @@ template <class R> int upload_metrics(cp_ctx *c)
     }
     for (int i = 0; i < nx; ++i) inv_dx[i] = 1.0 / c->dx[i];
     for (int j = 0; j <= nr; ++j) {
-        rfa[j] = axi ? c->rf[j] : 1.0;
+        rfa[j] = axi ? c->rf[j] : (q1d ? 0.0 : 1.0);   // the duct has no r faces
         inv_rf[j] = (axi && c->rf[j] > 0.0) ? 1.0 / c->rf[j] : 0.0;
     }
     for (int j = 0; j < nr; ++j) invV_r[j] = axi ? 1.0 / (RC(j) * c->dr[j]) : 1.0 / c->dr[j];
+    // duct: x-face areas and 1 / V_i with V_i = 0.5 (A_w + A_e) dx (unit areas and
+    // 1/dx elsewhere; the stage kernel reads them only for the duct)
+    std::vector<double> axf(nx + 1, 1.0), invVx(inv_dx);
+    if (q1d) {
+        axf = c->ax;
+        for (int i = 0; i < nx; ++i) invVx[i] = 1.0 / (0.5 * (c->ax[i] + c->ax[i + 1]) * c->dx[i]);
+    }
     const std::vector<double> *src[M_COUNT] = {&c->xc, &c->rc, &inv_dxf, &inv_drf, &inv_d2x, &inv_d2r, &lm2,
-                                               &inv_dx, &rfa, &invV_r, &inv_rc, &inv_rf};
+                                               &inv_dx, &rfa, &invV_r, &inv_rc, &inv_rf, &axf, &invVx};
     for (int k = 0; k < M_COUNT; ++k) {
         int r = upload_as<R>(c, *src[k], &c->met[k]);
         if (r) return r;
@@ -207,9 +217,11 @@ template <class R> int upload_metrics(cp_ctx *c)
     c->rc_d = (double *)p;
     std::vector<double> idx(nx), idr(nr), vol((size_t)nx * nr);
     for (int i = 0; i < nx; ++i) idx[i] = 1.0 / c->dx[i];
-    for (int j = 0; j < nr; ++j) idr[j] = 1.0 / c->dr[j];
+    for (int j = 0; j < nr; ++j) idr[j] = q1d ? 0.0 : 1.0 / c->dr[j];   // the duct has no r direction
     for (int j = 0; j < nr; ++j)
-        for (int i = 0; i < nx; ++i) vol[(size_t)j * nx + i] = (axi ? RC(j) : 1.0) * c->dr[j] * c->dx[i];
+        for (int i = 0; i < nx; ++i)
+            vol[(size_t)j * nx + i] = q1d ? 0.5 * (c->ax[i] + c->ax[i + 1]) * c->dx[i]
+                                          : (axi ? RC(j) : 1.0) * c->dr[j] * c->dx[i];
     if ((r = upload_as<double>(c, idx, &p))) return r;
     c->inv_dx_d = (double *)p;
     if ((r = upload_as<double>(c, idr, &p))) return r;
@@ -234,6 +246,8 @@ template <class R> Metrics<R> metrics(const cp_ctx *c)
     m.invV_r = (const R *)c->met[M_INVV_R];
     m.inv_rc = (const R *)c->met[M_INV_RC];
     m.inv_rf = (const R *)c->met[M_INV_RF];
+    m.axf = (const R *)c->met[M_AXF];
+    m.invVx = (const R *)c->met[M_INVVX];
     return m;
 }
 
@@ -487,15 +501,24 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
 {
     if (!mesh || !cs || !out) return CP_EINVAL;
     *out = nullptr;
-    if (mesh->nx < 2 || mesh->nr < 2 || !(mesh->Lx > 0) || !(mesh->Lr > 0)) return CP_EINVAL;
+    const bool q1d = mesh->geom == CP_GEOM_QUASI1D;
+    if (mesh->nx < 2 || (q1d ? mesh->nr != 1 : mesh->nr < 2) || !(mesh->Lx > 0) || !(mesh->Lr > 0))
+        return CP_EINVAL;
     if (precision != CP_FP64 && precision != CP_MIXED) return CP_EINVAL;
-    if (mesh->geom != CP_GEOM_AXI && mesh->geom != CP_GEOM_PLANAR) return CP_EINVAL;
+    if (mesh->geom != CP_GEOM_AXI && mesh->geom != CP_GEOM_PLANAR && !q1d) return CP_EINVAL;
     if (mesh->bc_rhi == CP_BC_INFLOW || mesh->bc_xhi == CP_BC_INFLOW || mesh->bc_rlo != CP_BC_WALL) return CP_EINVAL;
+    if (q1d) {
+        if (!mesh->area_x || mesh->bc_rhi != CP_BC_WALL) return CP_EINVAL;
+        for (int i = 0; i <= mesh->nx; ++i)
+            if (!std::isfinite(mesh->area_x[i]) || !(mesh->area_x[i] > 0.0)) return CP_EINVAL;
+    }
     if (!(mesh->sx_ratio > 0) || cs->n_sub_max < 1 || !(cs->cfl > 0)) return CP_EINVAL;
     cp_ctx *c = new cp_ctx();
     c->precision = precision;
     c->stream = (hipStream_t)hip_stream;
     c->mesh = *mesh;
+    c->mesh.area_x = nullptr;   // the areas are copied; the caller's array is not kept
+    if (q1d) c->ax.assign(mesh->area_x, mesh->area_x + mesh->nx + 1);
     c->cs = *cs;
     c->nx = mesh->nx;
     c->nr = mesh->nr;
@@ -967,6 +990,8 @@ int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int prec
 {
     if (!out || n < 1 || !meshes || !cases) return CP_EINVAL;
     *out = nullptr;
+    for (int p = 0; p < n; ++p)
+        if (meshes[p].geom == CP_GEOM_QUASI1D) return CP_EUNSUPPORTED;   // the batch kernel is axisymmetric/planar
     cp_batch *b = new cp_batch();
     b->n = n;
     b->precision = precision;

@@ -23,7 +23,11 @@ template <class R> struct Metrics {
     const R *invV_r;           // nr: 1 / (r_c dr)  (1/dr planar)
     const R *inv_rc;           // nr+2: 1 / r_c for j = -1..nr (0 planar)  (index j+1)
     const R *inv_rf;           // nr+1: 1 / r_f (0 at the axis and for planar)
+    const R *axf;              // nx+1: duct area at the x faces (quasi-1D only)
+    const R *invVx;            // nx: 1 / (0.5 (A_w + A_e) dx) (quasi-1D only)
 };
+
+constexpr int kGeomAxi = 0, kGeomQuasi1D = 2;   // BcInfo::geom (cp_geom)
 
 struct BcInfo {
     int nx, nr, geom, bc_xlo, bc_xhi, bc_rlo, bc_rhi;

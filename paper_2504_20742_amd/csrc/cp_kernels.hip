@@ -189,6 +189,13 @@ template <class R> __device__ __forceinline__ R assemble_r(R rx, R fn, R an, R f
     return rx - (fn * an - fs * as) * ivr;
 }
 
+// Quasi-1D duct: x faces of areas aw, ae and cell volume 1/iv.
+template <class R> __device__ __forceinline__ R assemble_duct(R fe, R ae, R fw, R aw, R iv)
+{
+#pragma clang fp contract(off)
+    return -(fe * ae - fw * aw) * iv;
+}
+
 // Passive scalar flux through a face: upwind MUSCL value (from the cell slopes)
 // times the Roe mass flux, minus eddy diffusion.
 // Both one-sided states are formed and the upwind one selected, so the flux is
@@ -233,7 +240,10 @@ __device__ __forceinline__ int xcd_band(int b, int nb)
 }
 
 // One fused SSP-RK3 stage on the TX x TY tile whose first cell is (i0, j0).
-template <class R, int TX, int TY>
+// DUCT: the quasi-1D duct (one row, x faces of the duct areas, no r faces, wall
+// force on axial momentum), a separate instantiation so that the axisymmetric and
+// planar kernels carry none of its code.
+template <class R, int TX, int TY, bool DUCT = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0, Tile<R, TX, TY> &t)
 {
     using TileT = Tile<R, TX, TY>;
@@ -244,7 +254,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     const int nx = bc.nx, nr = bc.nr;
     const int tid = threadIdx.x;
     const R pref = (R)a.pref;
-    const bool axi = bc.geom == 0;
+    const bool axi = !DUCT && bc.geom == kGeomAxi;
+    constexpr bool q1d = DUCT;
 
     // A tile whose 2-cell halo lies inside the mesh (most tiles) addresses its cells
     // directly; only boundary tiles go through the ghost-cell mapping.
@@ -318,8 +329,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     const R idx = valid ? m.inv_dx[i] : R(0);
     if (valid) {
         const int fw = ty * (TX + 1) + tx;
-        #pragma unroll
-        for (int k = 0; k < 5; ++k) res[k] = assemble_x(t.face[k][fw + 1], t.face[k][fw], idx);
+        if (q1d) {
+            // duct: the walls push with (p - p_ref)(A_e - A_w) on axial momentum, the
+            // reference pressure having been taken out of the momentum fluxes as well
+            const R aw = m.axf[i], ae = m.axf[i + 1], iv = m.invVx[i];
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) res[k] = assemble_duct(t.face[k][fw + 1], ae, t.face[k][fw], aw, iv);
+            res[1] += ((t.p[l] - pref) * (ae - aw)) * iv;
+        } else {
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) res[k] = assemble_x(t.face[k][fw + 1], t.face[k][fw], idx);
+        }
         Fm0 = t.face[5][fw];
         kd0 = t.face[6][fw];
         Fm1 = t.face[5][fw + 1];
@@ -338,7 +358,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int fi = f % TX, fj = f / TX;
         const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
         R F[5] = {R(0), R(0), R(0), R(0), R(0)}, fm = R(0), kdv = R(0);
-        if (!(axi && jg == 0)) {
+        if (!(axi && jg == 0) && !q1d) {
             const int la = (fj + 1) * EX + fi + 2;
             const int ra = fj * RX + fi + 1;
             gas_face<R>(t, la, ra, ra + RX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1], m.inv_rf[jg], pref, F, fm,
@@ -419,6 +439,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         }
         __syncthreads();
         if (valid) {
+            R aw = R(0), ae = R(0), iv = R(0);
+            if (q1d) {
+                aw = m.axf[i];
+                ae = m.axf[i + 1];
+                iv = m.invVx[i];
+            }
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 if (!(live & (1 << k))) {
@@ -431,7 +457,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R fs_raw = scalar_face(ph, srs[k], l - EX, l, rl - RX, rl, Fm2, kd2);
                 const R fsv = (axi && j == 0) ? R(0) : fs_raw;   // zero-area axis face
                 const R fnv = scalar_face(ph, srs[k], l, l + EX, rl, rl + RX, Fm3, kd3);
-                res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+                res[s0 + k] = q1d ? assemble_duct(fe, ae, fw, aw, iv)
+                                  : assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
             }
         }
     }
@@ -499,7 +526,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     if (bad) atomicOr(a.flag, 1);
 }
 
-template <class R, int TX, int TY>
+template <class R, int TX, int TY, bool DUCT = false>
 __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
 {
     __shared__ Tile<R, TX, TY> t;
@@ -507,7 +534,7 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
     if (a.sur_cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sur_fold_counts(a.sur_cnt, a.sur_tot);
     const int gx = gridDim.x;
     const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
-    stage_tile<R, TX, TY>(a, (tb % gx) * TX, (tb / gx) * TY, t);
+    stage_tile<R, TX, TY, DUCT>(a, (tb % gx) * TX, (tb / gx) * TY, t);
 }
 
 // Batched operating points: workgroup b takes work item b (XCD-banded) of a list of
@@ -1113,16 +1140,18 @@ bool tile_supported(int tx, int ty)
     return false;
 }
 
-template <class R, int TX, int TY>
+template <class R, int TX, int TY, bool DUCT = false>
 static hipError_t stage_launch(const StageArgs<R> &a, hipStream_t s)
 {
     dim3 grid((a.bc.nx + TX - 1) / TX, (a.bc.nr + TY - 1) / TY);
-    hipLaunchKernelGGL((k_stage<R, TX, TY>), grid, dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_stage<R, TX, TY, DUCT>), grid, dim3(TX * TY), 0, s, a);
     return hipGetLastError();
 }
 
+// The duct (one row) always takes its own 64 x 4 instantiation.
 template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s)
 {
+    if (a.bc.geom == kGeomQuasi1D) return stage_launch<R, 64, 4, true>(a, s);
     if (tx == 32 && ty == 8) return stage_launch<R, 32, 8>(a, s);
     if (tx == 16 && ty == 16) return stage_launch<R, 16, 16>(a, s);
     if (tx == 64 && ty == 4) return stage_launch<R, 64, 4>(a, s);
