@@ -81,7 +81,8 @@ enum cp_geom { CP_GEOM_AXI = 0, CP_GEOM_PLANAR = 1, CP_GEOM_QUASI1D = 2 };
 enum cp_bc { CP_BC_INFLOW = 0, CP_BC_COPY = 1, CP_BC_WALL = 2, CP_BC_FARFIELD = 3 };
 
 typedef struct {
-    int nx, nr;            /* cells: both >= 2; nr = 1 for CP_GEOM_QUASI1D          */
+    int nx, nr;            /* cells: both >= 2 (nr = 1 for CP_GEOM_QUASI1D), and
+                              nx * nr <= 2^28                                       */
     double Lx, Lr;         /* domain [0, Lx] x [0, Lr] in metres                    */
     double sx_ratio;       /* ratio of successive axial widths (1 = uniform)        */
     double r_cluster;      /* radius the radial cells cluster about (<= 0: uniform) */

@@ -504,6 +504,7 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
     const bool q1d = mesh->geom == CP_GEOM_QUASI1D;
     if (mesh->nx < 2 || (q1d ? mesh->nr != 1 : mesh->nr < 2) || !(mesh->Lx > 0) || !(mesh->Lr > 0))
         return CP_EINVAL;
+    if ((long)mesh->nx * mesh->nr > kMaxCells) return CP_EINVAL;   // a state plane must stay below 2 GiB
     if (precision != CP_FP64 && precision != CP_MIXED) return CP_EINVAL;
     if (mesh->geom != CP_GEOM_AXI && mesh->geom != CP_GEOM_PLANAR && !q1d) return CP_EINVAL;
     if (mesh->bc_rhi == CP_BC_INFLOW || mesh->bc_xhi == CP_BC_INFLOW || mesh->bc_rlo != CP_BC_WALL) return CP_EINVAL;
@@ -573,7 +574,7 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
     c->t_d = dalloc<double>(c, 1);
     c->diag_d = dalloc<double>(c, 8);
     c->acc_d = dalloc<unsigned long long>(c, 1);
-    c->cfl_nb = ((c->nx + kCflBX - 1) / kCflBX) * ((c->nr + kCflBY - 1) / kCflBY);
+    c->cfl_nb = ((c->nx + kCflBX - 1) / kCflBX) * ((c->nr + kCflBY * kCflRows - 1) / (kCflBY * kCflRows));
     c->cfl_bm = dalloc<double>(c, c->cfl_nb);
     c->nsub_d = dalloc<unsigned long long>(c, 1);
     c->flag_d = dalloc<int>(c, 1);

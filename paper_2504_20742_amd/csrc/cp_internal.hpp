@@ -28,6 +28,7 @@ template <class R> struct Metrics {
 };
 
 constexpr int kGeomAxi = 0, kGeomQuasi1D = 2;   // BcInfo::geom (cp_geom)
+constexpr long kMaxCells = 1L << 28;             // cells per context: one FP64 plane below 2 GiB
 
 struct BcInfo {
     int nx, nr, geom, bc_xlo, bc_xhi, bc_rlo, bc_rhi;
@@ -79,7 +80,7 @@ template <class R> struct CflArgs {
     unsigned long long *acc;   // running min of the per-cell limit (bits of a positive double)
     double *block_min;         // tiled kernels: one minimum per workgroup (or null: use acc)
 };
-constexpr int kCflBX = 64, kCflBY = 4;   // tile of the CFL kernels
+constexpr int kCflBX = 64, kCflBY = 4, kCflRows = 4;   // CFL kernels: 64 x 4 threads, 4 rows each
 
 struct Ctx;   // host context (cp_api.hip)
 }  // namespace cp

@@ -68,6 +68,44 @@ __device__ __forceinline__ CellSrc map_cell(int i, int j, const BcInfo &b)
     return s;
 }
 
+// Raw buffer access to one plane of a state array: the plane's base and size sit
+// in a scalar resource descriptor and the cell offset in one vector register, so a
+// load or store needs no 64-bit vector address arithmetic (one shared offset serves
+// all planes).  The hardware range check reads 0 past the plane's end and drops
+// such stores; every access here is inside the plane.
+constexpr int kBufferWord3 = 0x00020000;   // resource word 3 of a raw buffer on gfx9-family GPUs
+template <class R> __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const R *base, long plane)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R *>(base), 0, (int)(plane * (long)sizeof(R)),
+                                             kBufferWord3);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, float)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, x), r,
+                                          (int)off, 0, 0);
+}
+// element k of plane v of the state array U
+template <class R> __device__ __forceinline__ R ld_plane(const R *U, long plane, int v, unsigned k)
+{
+    return buf_ld(plane_rsrc(U + v * plane, plane), k * (unsigned)sizeof(R), R(0));
+}
+template <class R> __device__ __forceinline__ void st_plane(R *U, long plane, int v, unsigned k, R x)
+{
+    buf_st(plane_rsrc(U + v * plane, plane), k * (unsigned)sizeof(R), x);
+}
+
 template <class R>
 __device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int code, int v)
 {
@@ -266,19 +304,31 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
         const int i = min(i0 + ex - 2, nx + 1), j = min(j0 + ey - 2, nr + 1);
-        const CellSrc cs = inner ? CellSrc{j * nx + i, false, false} : map_cell(i, j, bc);
-        const R U0 = fetch(a.Uin, a.plane, bc, cs.code, 0);
-        R U1 = fetch(a.Uin, a.plane, bc, cs.code, 1);
-        R U2 = fetch(a.Uin, a.plane, bc, cs.code, 2);
-        const R U3 = fetch(a.Uin, a.plane, bc, cs.code, 3);
-        const R U4 = fetch(a.Uin, a.plane, bc, cs.code, 4);
-        if (cs.fu) U1 = -U1;
-        if (cs.fv) U2 = -U2;
+        int code;
+        R U0, U1, U2, U3, U4;
+        if (inner) {
+            code = j * nx + i;
+            U0 = ld_plane(a.Uin, a.plane, 0, code);
+            U1 = ld_plane(a.Uin, a.plane, 1, code);
+            U2 = ld_plane(a.Uin, a.plane, 2, code);
+            U3 = ld_plane(a.Uin, a.plane, 3, code);
+            U4 = ld_plane(a.Uin, a.plane, 4, code);
+        } else {
+            const CellSrc cs = map_cell(i, j, bc);
+            code = cs.code;
+            U0 = fetch(a.Uin, a.plane, bc, code, 0);
+            U1 = fetch(a.Uin, a.plane, bc, code, 1);
+            U2 = fetch(a.Uin, a.plane, bc, code, 2);
+            U3 = fetch(a.Uin, a.plane, bc, code, 3);
+            U4 = fetch(a.Uin, a.plane, bc, code, 4);
+            if (cs.fu) U1 = -U1;
+            if (cs.fv) U2 = -U2;
+        }
         const R ir = trcp(U0);
         const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
         const R eint = U3 * ir - R(0.5) * (u * u + v * v);
         const R T = tdiv(eint + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
-        t.code[e] = cs.code;
+        t.code[e] = code;
         t.rho[e] = U0;
         t.u[e] = u;
         t.v[e] = v;
@@ -402,11 +452,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         int nz = 0;
         if (inner) {
             for (int e = tid; e < NE; e += NT) {
-                const R *src = a.Uin + (long)s0 * a.plane + t.code[e];
+                const unsigned code = t.code[e];
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    const R u = src[k * a.plane];
+                    const R u = ld_plane(a.Uin, a.plane, s0 + k, code);
                     nz |= (u != R(0)) << k;
                     scalar_slot(t, k)[e] = per_mass(u, rho, ir);
                 }
@@ -483,10 +533,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         // for each load in turn)
         R ui[NVAR], un[NVAR];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) ui[v] = a.Uin[v * a.plane + c];
+        for (int v = 0; v < NVAR; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
         if (a.stage > 0) {
             #pragma unroll
-            for (int v = 0; v < NVAR; ++v) un[v] = a.Un[v * a.plane + c];
+            for (int v = 0; v < NVAR; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
         }
         bool act = false;
         if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], ui[5], ui[9], Tcell))) {
@@ -519,7 +569,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 out = a.stage == 1 ? R(0.75) * un[v] + R(0.25) * (ui[v] + rdt * L)
                                    : R(1.0 / 3.0) * un[v] + R(2.0 / 3.0) * (ui[v] + rdt * L);
             }
-            a.Uout[v * a.plane + c] = out;
+            st_plane(a.Uout, a.plane, v, (unsigned)c, out);
             bad |= !isfinite(out);
         }
     }
@@ -585,8 +635,14 @@ template <class R> __device__ __forceinline__ void source_fix_body(const SourceF
 
 // One wavefront per workgroup: the active cells are a small, compact fraction of
 // the mesh, so they are spread over as many compute units as possible.
+// A workgroup with no listed cell leaves at once, before any of the source code
+// is fetched (most stages of a jet have no source-active cell at all).
 template <class R> __global__ void __launch_bounds__(64) k_source_fix(SourceFixArgs<R> a)
 {
+    if ((long)blockIdx.x * blockDim.x >= min((long)*a.count, a.plane)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
+        return;
+    }
     source_fix_body(a, blockIdx.x, gridDim.x);
 }
 
@@ -642,6 +698,7 @@ __global__ void __launch_bounds__(256) k_sur_features(const R *U, long plane, do
 template <class R> __global__ void __launch_bounds__(256) k_sur_gate(SurArgs<R> a)
 {
     const int n = (int)min((long)*a.count, a.plane);
+    if ((long)blockIdx.x * blockDim.x >= n) return;   // no listed cell for this workgroup
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const long c = a.list[k];
@@ -733,6 +790,10 @@ template <class R> __global__ void __launch_bounds__(64) k_sur_finish(SurArgs<R>
                                                                       int *next_count, unsigned long long *nsub)
 {
     const int n_net = min(a.cnt[0], (int)a.plane), n_fb = min(a.cnt[1], (int)a.plane);
+    if ((long)blockIdx.x * blockDim.x >= (long)n_net + n_fb) {   // no row for this workgroup
+        if (blockIdx.x == 0 && threadIdx.x == 0 && next_count) *next_count = 0;
+        return;
+    }
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
     const double b = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
     bool bad = false;
@@ -803,19 +864,10 @@ struct PrimD {
     double rho, u, v, T, Y;
 };
 
-template <class R>
-__device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &bc, int i, int j)
+__device__ __forceinline__ PrimD cfl_prim_of(double U0, double U1, double U2, double U3, double U4)
 {
 #pragma clang fp contract(off)
-    const CellSrc cs = map_cell(i, j, bc);
     PrimD w;
-    const double U0 = (double)fetch(U, plane, bc, cs.code, 0);
-    double U1 = (double)fetch(U, plane, bc, cs.code, 1);
-    double U2 = (double)fetch(U, plane, bc, cs.code, 2);
-    const double U3 = (double)fetch(U, plane, bc, cs.code, 3);
-    const double U4 = (double)fetch(U, plane, bc, cs.code, 4);
-    if (cs.fu) U1 = -U1;
-    if (cs.fv) U2 = -U2;
     w.rho = U0;
     w.u = U1 / U0;
     w.v = U2 / U0;
@@ -824,6 +876,20 @@ __device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &
     const double cv = (1.0 - w.Y) * kCva + w.Y * kCvv;
     w.T = (e + (1.0 - w.Y) * kCpa * kTref - w.Y * (kLv0 - kCpv * kTref)) / cv;
     return w;
+}
+
+template <class R>
+__device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &bc, int i, int j)
+{
+    const CellSrc cs = map_cell(i, j, bc);
+    const double U0 = (double)fetch(U, plane, bc, cs.code, 0);
+    double U1 = (double)fetch(U, plane, bc, cs.code, 1);
+    double U2 = (double)fetch(U, plane, bc, cs.code, 2);
+    const double U3 = (double)fetch(U, plane, bc, cs.code, 3);
+    const double U4 = (double)fetch(U, plane, bc, cs.code, 4);
+    if (cs.fu) U1 = -U1;
+    if (cs.fv) U2 = -U2;
+    return cfl_prim_of(U0, U1, U2, U3, U4);
 }
 
 // Time-step limit of cell (i, j) from its primitives and the neighbour velocities
@@ -883,17 +949,9 @@ struct PrimF {
     float rho, u, v, T, Y;
 };
 
-__device__ __forceinline__ PrimF cfl_prim_f32(const float *U, long plane, const BcInfo &bc, int i, int j)
+__device__ __forceinline__ PrimF cfl_prim_f32_of(float U0, float U1, float U2, float U3, float U4)
 {
 #pragma clang fp contract(off)   // the same operations wherever it is inlined
-    const CellSrc cs = map_cell(i, j, bc);
-    const float U0 = fetch(U, plane, bc, cs.code, 0);
-    float U1 = fetch(U, plane, bc, cs.code, 1);
-    float U2 = fetch(U, plane, bc, cs.code, 2);
-    const float U3 = fetch(U, plane, bc, cs.code, 3);
-    const float U4 = fetch(U, plane, bc, cs.code, 4);
-    if (cs.fu) U1 = -U1;
-    if (cs.fv) U2 = -U2;
     const float ir = __builtin_amdgcn_rcpf(U0);
     PrimF w;
     w.rho = U0;
@@ -904,6 +962,19 @@ __device__ __forceinline__ PrimF cfl_prim_f32(const float *U, long plane, const 
     const float cv = (1.0f - w.Y) * float(kCva) + w.Y * float(kCvv);
     w.T = (e + (1.0f - w.Y) * float(kCpa * kTref) - w.Y * float(kLv0 - kCpv * kTref)) * __builtin_amdgcn_rcpf(cv);
     return w;
+}
+
+__device__ __forceinline__ PrimF cfl_prim_f32(const float *U, long plane, const BcInfo &bc, int i, int j)
+{
+    const CellSrc cs = map_cell(i, j, bc);
+    const float U0 = fetch(U, plane, bc, cs.code, 0);
+    float U1 = fetch(U, plane, bc, cs.code, 1);
+    float U2 = fetch(U, plane, bc, cs.code, 2);
+    const float U3 = fetch(U, plane, bc, cs.code, 3);
+    const float U4 = fetch(U, plane, bc, cs.code, 4);
+    if (cs.fu) U1 = -U1;
+    if (cs.fv) U2 = -U2;
+    return cfl_prim_f32_of(U0, U1, U2, U3, U4);
 }
 
 __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, int j, const PrimF &w, float uN,
@@ -928,30 +999,66 @@ __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, i
     return __builtin_amdgcn_rcpf(rate);
 }
 
-template <int BX, int BY> __global__ void __launch_bounds__(BX *BY) k_cfl_tile_f32(CflArgs<float> a)
+// BX x BY threads over a BX x (BY * RPT) tile (RPT rows per thread).  A tile whose
+// 1-cell ring lies inside the mesh loads its cells directly, all five variables at
+// once; boundary tiles go through the ghost-cell mapping.
+template <int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile_f32(CflArgs<float> a)
 {
-    constexpr int EXC = BX + 2, NEC = EXC * (BY + 2);
+    constexpr int TY = BY * RPT, EXC = BX + 2, NEC = EXC * (TY + 2);
     __shared__ float pr[5][NEC];
     const BcInfo &bc = a.bc;
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
-    for (int e = threadIdx.x; e < NEC; e += BX * BY) {
-        const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
-        const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
-        pr[0][e] = w.rho;
-        pr[1][e] = w.u;
-        pr[2][e] = w.v;
-        pr[3][e] = w.T;
-        pr[4][e] = w.Y;
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * TY;
+    const bool inner = i0 >= 1 && j0 >= 1 && i0 + BX + 1 <= bc.nx && j0 + TY + 1 <= bc.nr;
+    if (inner) {
+        // every load of the thread's ring cells in flight before the first use
+        constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
+        float q[IT][5];
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                const float *u = a.U + (long)(j0 + e / EXC - 1) * bc.nx + i0 + e % EXC - 1;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) q[it][k] = u[k * a.plane];
+            }
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                const PrimF w = cfl_prim_f32_of(q[it][0], q[it][1], q[it][2], q[it][3], q[it][4]);
+                pr[0][e] = w.rho;
+                pr[1][e] = w.u;
+                pr[2][e] = w.v;
+                pr[3][e] = w.T;
+                pr[4][e] = w.Y;
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < NEC; e += BX * BY) {
+            const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
+            const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
+            pr[0][e] = w.rho;
+            pr[1][e] = w.u;
+            pr[2][e] = w.v;
+            pr[3][e] = w.T;
+            pr[4][e] = w.Y;
+        }
     }
     __syncthreads();
     double best = __builtin_huge_val();
-    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-    const int i = i0 + tx, j = j0 + ty;
-    if (i < bc.nx && j < bc.nr) {
-        const int l = (ty + 1) * EXC + tx + 1;
-        const PrimF w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
-        const double d = (double)cfl_limit_f32(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
-        if (d < best) best = d;
+    const int tx = threadIdx.x % BX;
+    #pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ty = threadIdx.x / BX + r * BY;
+        const int i = i0 + tx, j = j0 + ty;
+        if (i < bc.nx && j < bc.nr) {
+            const int l = (ty + 1) * EXC + tx + 1;
+            const PrimF w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
+            const double d =
+                (double)cfl_limit_f32(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
+            if (d < best) best = d;
+        }
     }
     cfl_block_min(best, a.acc, a.block_min);
 }
@@ -980,33 +1087,67 @@ template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a,
     cfl_block_min(best, a.acc, nullptr);
 }
 
-// Tiled form: the primitives of a BX x BY tile and its 1-cell ring are computed
-// once into LDS and shared by the neighbouring cells' limits (same arithmetic as
-// cfl_body, so the minimum is bit-identical).
-template <class R, int BX, int BY> __global__ void __launch_bounds__(BX *BY) k_cfl_tile(CflArgs<R> a)
+// Tiled form: the primitives of a BX x (BY * RPT) tile and its 1-cell ring are
+// computed once into LDS and shared by the neighbouring cells' limits (same
+// arithmetic as cfl_body, so the minimum is bit-identical); interior tiles load
+// their cells directly.
+template <class R, int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile(CflArgs<R> a)
 {
-    constexpr int EXC = BX + 2, NEC = EXC * (BY + 2);
+    constexpr int TY = BY * RPT, EXC = BX + 2, NEC = EXC * (TY + 2);
     __shared__ double pr[5][NEC];
     const BcInfo &bc = a.bc;
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
-    for (int e = threadIdx.x; e < NEC; e += BX * BY) {
-        const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
-        const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
-        pr[0][e] = w.rho;
-        pr[1][e] = w.u;
-        pr[2][e] = w.v;
-        pr[3][e] = w.T;
-        pr[4][e] = w.Y;
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * TY;
+    const bool inner = i0 >= 1 && j0 >= 1 && i0 + BX + 1 <= bc.nx && j0 + TY + 1 <= bc.nr;
+    if (inner) {
+        // every load of the thread's ring cells in flight before the first use
+        constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
+        R q[IT][5];
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                const R *u = a.U + (long)(j0 + e / EXC - 1) * bc.nx + i0 + e % EXC - 1;
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) q[it][k] = u[k * a.plane];
+            }
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                const PrimD w = cfl_prim_of((double)q[it][0], (double)q[it][1], (double)q[it][2], (double)q[it][3],
+                                            (double)q[it][4]);
+                pr[0][e] = w.rho;
+                pr[1][e] = w.u;
+                pr[2][e] = w.v;
+                pr[3][e] = w.T;
+                pr[4][e] = w.Y;
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < NEC; e += BX * BY) {
+            const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
+            const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
+            pr[0][e] = w.rho;
+            pr[1][e] = w.u;
+            pr[2][e] = w.v;
+            pr[3][e] = w.T;
+            pr[4][e] = w.Y;
+        }
     }
     __syncthreads();
     double best = __builtin_huge_val();
-    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-    const int i = i0 + tx, j = j0 + ty;
-    if (i < bc.nx && j < bc.nr) {
-        const int l = (ty + 1) * EXC + tx + 1;
-        const PrimD w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
-        const double d = cfl_limit(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
-        if (d < best) best = d;
+    const int tx = threadIdx.x % BX;
+    #pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ty = threadIdx.x / BX + r * BY;
+        const int i = i0 + tx, j = j0 + ty;
+        if (i < bc.nx && j < bc.nr) {
+            const int l = (ty + 1) * EXC + tx + 1;
+            const PrimD w{pr[0][l], pr[1][l], pr[2][l], pr[3][l], pr[4][l]};
+            const double d = cfl_limit(a, i, j, w, pr[1][l + EXC], pr[1][l - EXC], pr[2][l + 1], pr[2][l - 1]);
+            if (d < best) best = d;
+        }
     }
     cfl_block_min(best, a.acc, a.block_min);
 }
@@ -1253,12 +1394,12 @@ hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s)
 
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s)
 {
-    constexpr int BX = kCflBX, BY = kCflBY;
-    dim3 grid((a.bc.nx + BX - 1) / BX, (a.bc.nr + BY - 1) / BY);
+    constexpr int BX = kCflBX, BY = kCflBY, RPT = kCflRows;
+    dim3 grid((a.bc.nx + BX - 1) / BX, (a.bc.nr + BY * RPT - 1) / (BY * RPT));
     if constexpr (sizeof(R) == 4)
-        hipLaunchKernelGGL((k_cfl_tile_f32<BX, BY>), grid, dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((k_cfl_tile_f32<BX, BY, RPT>), grid, dim3(BX * BY), 0, s, a);
     else
-        hipLaunchKernelGGL((k_cfl_tile<R, BX, BY>), grid, dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((k_cfl_tile<R, BX, BY, RPT>), grid, dim3(BX * BY), 0, s, a);
     return hipGetLastError();
 }
 

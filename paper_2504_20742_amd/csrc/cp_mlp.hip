@@ -231,6 +231,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const uint16_t *X, int n_i
     __shared__ uint16_t Xs[64][kFusedKin + kFusedPad];
     __shared__ uint16_t Hs[64][kFusedNH + kFusedPad];
     const int M = M_dev ? min(*M_dev, M_max) : M_max;
+    if (blockIdx.x * 64 >= M) return;   // no row for this workgroup
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = 8 * (lane >> 4);   // A: row in block, first k; B/D: column
     const int ld = 4 * (lane >> 4);                     // D: first row

@@ -98,3 +98,16 @@ def test_batch_rejects_duct_without_gpu():
     rc = L.cp_batch_create(1, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cs, ctypes.c_void_p), 1, None,
                            ctypes.byref(h))
     assert rc == binding.CP_EUNSUPPORTED
+
+
+def test_create_rejects_oversized_mesh_without_gpu():
+    """At most 2^28 cells per context (a state plane stays below 2 GiB)."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("library not built")
+    L = binding.load()
+    from paper_2504_20742_amd import inputs
+    m = inputs.mesh(1 << 15, (1 << 13) + 1)
+    h = ctypes.c_void_p()
+    rc = L.cp_create(ctypes.byref(binding.make_mesh(m)), ctypes.byref(binding.make_case(inputs.case())), 0, None,
+                     ctypes.byref(h))
+    assert rc == binding.CP_EINVAL

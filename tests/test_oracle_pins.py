@@ -511,6 +511,39 @@ def test_uniform_box_stays_uniform_and_conserves_water(orc):
     assert d1["max_lnS_l"] < d0["max_lnS_l"]
 
 
+def test_box_relaxes_to_kelvin_equilibrium(orc):
+    """P13 fixed point (Eq. 1-3, 16, 21 through the sub-cycled source): a uniform box
+    of droplets (0.3 um, 1e11 m^-3) in slightly supersaturated vapour (S_l = 1.05,
+    283 K, no soot, nucleation negligible) grows its droplets until the vapour
+    reaches the Kelvin equilibrium of the mean radius, G(r20) = 0, i.e.
+    ln S_l = 2 sigma / (rho_l R_v T r20); water is conserved throughout."""
+    L = orc.lib()
+    T0, p, S0, r0, N0 = 283.0, 1.0e5, 1.05, 3e-7, 1e11
+    pv = S0 * math.exp(L.or_ln_psat_liq(T0))
+    rho_v, rho_a = pv / (461.52 * T0), (p - pv) / (287.0 * T0)
+    Y = rho_v / (rho_a + rho_v)
+    m, c = inputs.sa0(Y=Y, T=T0, n_soot=0.0)
+    o = orc.Oracle(m, c)
+    U = _cell(orc, T=T0, p=p, Y=Y, liq=(N0, N0 * r0, N0 * r0 ** 2, N0 * r0 ** 3))
+
+    def water(U):
+        return U[4] + 4.0 / 3.0 * math.pi * (1000.0 * U[8] + 917.0 * U[12])
+
+    W0 = water(U)
+    for _ in range(500):
+        Q, n = o.source_cell(U, 2e-3)
+        U = U + 2e-3 * Q
+    T = orc.cons_to_prim(U.copy())[15]
+    lnS = math.log(U[4] * 461.52 * T) - L.or_ln_psat_liq(T)
+    r20 = math.sqrt(U[7] / U[5])
+    kelvin = 2.0 * L.or_sigma_lg(T) / (1000.0 * 461.52 * T * r20)
+    assert 0 < lnS < 0.1 * math.log(S0)                  # the vapour excess has condensed
+    assert abs(lnS / kelvin - 1.0) < 1e-6, (lnS, kelvin)
+    assert r20 > 2 * r0 and T > T0                        # droplets grew, latent heat released
+    assert U[5] == pytest.approx(N0, rel=1e-9)            # no nucleation, no evaporation
+    assert water(U) == pytest.approx(W0, rel=1e-13)
+
+
 def test_closed_box_no_phase_change_conserves_energy(orc):
     """P19: without phase change a closed box conserves mass and total energy to
     rounding while the flow develops."""
