@@ -32,6 +32,10 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-updates/s at 2048x512 (mixed+surrogate vs plain FP64), % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_stage_mixed_2048x512_counters.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_stage_mixed_2048x512_valu.txt")
+# vector-instruction issue limit: 256 CUs x 4 SIMDs, one wave64 FP32 instruction per
+# SIMD every 4 cycles (16 lanes) at 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 KERNEL_SOURCES = ["paper_2504_20742_amd/csrc/cp_kernels.hip", "paper_2504_20742_amd/csrc/cp_physics.hpp",
                   "paper_2504_20742_amd/csrc/cp_internal.hpp"]
 
@@ -56,14 +60,13 @@ def kernel_source_hash(root=ROOT):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tile):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if
-    it was taken on the kernel sources as they are now and on this tile shape
-    (else None)."""
-    if not os.path.exists(COUNTER_FILE):
+def _counter_value(path, key, tile):
+    """A per-launch figure from a committed rocprofv3 counter summary, if it was
+    taken on the kernel sources as they are now and on this tile shape (else None)."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(COUNTER_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -72,9 +75,19 @@ def measured_traffic(tile):
     if vals.get("tile") != "%dx%d" % tuple(tile):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(tile):
+    """HBM bytes per stage launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return _counter_value(COUNTER_FILE, "hbm_bytes_per_launch", tile)
+
+
+def measured_valu(tile):
+    """Vector-ALU wave-instructions per stage launch (SQ_INSTS_VALU)."""
+    return _counter_value(VALU_FILE, "valu_wave_insts_per_launch", tile)
 
 
 def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None):
@@ -355,6 +368,12 @@ def main():
         "paths": {k: {kk: v[kk] for kk in ("cell_updates_per_s", "ms_per_step", "stage_ms", "tile",
                                             "max_lnS_l", "active_cells") if kk in v} for k, v in res.items()},
     }
+    valu = measured_valu(head["tile"]) if head["esz"] == 4 else None
+    if valu is not None:
+        rate = valu / (head["stage_ms"] / 1e3)
+        line["valu_issue"] = {"bound": "alu", "achieved": rate, "peak": VALU_PEAK_WAVE_INSTS,
+                              "unit": "wave-instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTS,
+                              "insts_per_launch": valu}
     if "fp64" in res:
         line["over_fp64"] = {k: v["cell_updates_per_s"] / res["fp64"]["cell_updates_per_s"]
                              for k, v in res.items() if k != "fp64"}
