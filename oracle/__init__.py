@@ -93,6 +93,7 @@ def lib():
         L.or_run.argtypes = [_V, _P, ctypes.c_int]
         L.or_diag.argtypes = [_V, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
+        L.or_set_equilibrium.argtypes = [_V, ctypes.c_int]
         L.or_set_area.restype = ctypes.c_int
         L.or_set_area.argtypes = [_V, _P]
         L.or_case_derived.argtypes = [_V, _P]
@@ -176,6 +177,11 @@ class Oracle:
         out = np.zeros(4)
         self.L.or_diag(self.h, _ptr(U), _ptr(out))
         return {"water": out[0], "max_lnS_l": out[1], "ice_number": out[2], "gas_mass": out[3]}
+
+    def set_equilibrium(self, on=True):
+        """Switch the phase change between the kinetic model and the equilibrium
+        comparison model (instantaneous phase equilibrium per cell)."""
+        self.L.or_set_equilibrium(self.h, 1 if on else 0)
 
     def set_area(self, area):
         """Quasi-1D duct only: cross-section areas at the nx+1 x faces."""

@@ -102,6 +102,7 @@ typedef struct {
     double f_theta;             /* Eq. 9 at the case's contact angle               */
     double soot_area;           /* 4 pi r_g^2 exp(2 ln^2 sigma_g) per particle     */
     double delta0;
+    int equilibrium;            /* 1: equilibrium phase change instead of kinetics */
 } or_ctx;
 
 /* ================================================================ Sec. 2.2 == */
@@ -535,8 +536,166 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
     return nsub;
 }
 
+/* ============================== equilibrium comparison model (Sec. 4.2) == */
+/* The paper's comparison model lets vapour condense as soon as the cell is
+ * supersaturated over liquid, with no nucleation barrier and no growth kinetics,
+ * and lets the condensate freeze once ice is the stable phase.  Read here as an
+ * instantaneous phase equilibrium of the cell's water at fixed dry air, velocity
+ * and energy: the condensate is liquid when the equilibrium temperature is at or
+ * above T_MELT, ice below it (at T_MELT both, split by the energy balance), and the
+ * vapour sits at saturation over that phase, or all water is vapour when the cell
+ * cannot saturate.  Like the kinetic model, ice never forms from vapour alone: a
+ * cell without condensate changes only once it is supersaturated over liquid.
+ * Energy: condensing vapour keeps its latent heat in the gas (the condensate
+ * carries its enthalpy h_l or h_i at the final temperature).                     */
+static const double T_MELT = 273.15;
+static const double R_EQ_NEW = 1.0e-7;   /* m: radius of condensate that forms without soot */
+
+typedef struct {
+    double rho_a, rho_v, m_l, m_s, W, u, v, ke, rhoE;
+} eq_cell_t;
+
+/* End state of one phase branch at trial temperature Ts: vapour at saturation over
+ * the phase (ice = 0 liquid, 1 ice; capped by the water available), the rest
+ * condensed in that phase.  Returns the temperature the gas then has.           */
+static double eq_branch_T(const eq_cell_t *e, int ice, double Ts, double *rho_v_out, double *cond_out)
+{
+    double lnp = ice ? or_ln_psat_ice(Ts) : or_ln_psat_liq(Ts);
+    double rho_sat = exp(lnp) / (RGAS_VAP * Ts);
+    double cond = e->W - rho_sat;
+    if (cond < 0.0) cond = 0.0;
+    double rho_v = e->W - cond;
+    double hv = L_VAP0 + CP_VAP * (Ts - T_REF);
+    double hl = hv - latent_vap(Ts), hi = hv - latent_sub(Ts);
+    double L = ice ? 0.0 : cond, I = ice ? cond : 0.0;
+    double rhoE = e->rhoE - (L - e->m_l) * (hl + e->ke) - (I - e->m_s) * (hi + e->ke);
+    double rho = e->rho_a + rho_v;
+    double Y = rho_v / rho;
+    double eint = rhoE / rho - e->ke;
+    if (rho_v_out) *rho_v_out = rho_v;
+    if (cond_out) *cond_out = cond;
+    return (eint - mix_h0(Y)) / mix_cv(Y);
+}
+
+/* Root of T_gas(Ts) = Ts of one branch by bisection (the gas temperature falls as
+ * Ts rises: warmer saturation keeps more vapour and releases less heat).        */
+static double eq_branch_root(const eq_cell_t *e, int ice)
+{
+    double a = 100.0, b = 1000.0;
+    for (int it = 0; it < 64; ++it) {
+        double m = 0.5 * (a + b);
+        if (eq_branch_T(e, ice, m, NULL, NULL) > m) a = m;
+        else b = m;
+    }
+    return 0.5 * (a + b);
+}
+
+/* Moments of a population of mass M [kg/m^3] of material density rho_p: N
+ * particles of one radius.                                                      */
+static void eq_population(double M, double N, double rho_p, double *mom)
+{
+    if (!(M > 0.0) || !(N > 0.0)) {
+        for (int k = 0; k < 4; ++k) mom[k] = 0.0;
+        return;
+    }
+    double r = cbrt(M / (4.0 / 3.0 * PI * rho_p * N));
+    mom[0] = N; mom[1] = N * r; mom[2] = N * r * r; mom[3] = N * r * r * r;
+}
+
+static int source_equilibrium(const or_ctx *cx, const double *U, double dt, double *Q)
+{
+    for (int v = 0; v < NV; ++v) Q[v] = 0.0;
+    if (!cx->c.phase_change) return 0;
+    prim_t w;
+    cons_to_prim(U, &w);
+    /* no condensate and not supersaturated over liquid: nothing happens */
+    if (!(U[5] > N_MIN) && !(U[9] > N_MIN)) {
+        if (!(U[4] > 0.0)) return 0;
+        double pv = U[4] * RGAS_VAP * w.T;
+        if (pv < PV_FLOOR) pv = PV_FLOOR;
+        if (!(log(pv) - or_ln_psat_liq(w.T) > 0.0)) return 0;
+    }
+    const double fpi = 4.0 / 3.0 * PI;
+    eq_cell_t e;
+    e.rho_v = U[4];
+    e.rho_a = U[0] - U[4];
+    e.m_l = U[5] > N_MIN ? fpi * RHO_LIQ * U[8] : 0.0;
+    e.m_s = U[9] > N_MIN ? fpi * RHO_ICE * U[12] : 0.0;
+    e.W = e.rho_v + e.m_l + e.m_s;
+    e.u = w.u; e.v = w.v;
+    e.ke = 0.5 * (w.u * w.u + w.v * w.v);
+    e.rhoE = U[3];
+
+    /* phase of the condensate: liquid if its branch settles at or above T_MELT, ice
+     * if the ice branch settles below, else both at T_MELT                          */
+    double T_end, rho_v_end, L = 0.0, I = 0.0;
+    double TL = eq_branch_root(&e, 0), cL;
+    eq_branch_T(&e, 0, TL, &rho_v_end, &cL);
+    if (TL >= T_MELT) {
+        T_end = TL; L = cL;
+    } else {
+        double TI = eq_branch_root(&e, 1), cI;
+        eq_branch_T(&e, 1, TI, &rho_v_end, &cI);
+        if (TI < T_MELT) {
+            T_end = TI; I = cI;
+        } else {
+            /* both phases at T_MELT, vapour saturated over liquid; the ice share is the
+             * one that puts the gas at T_MELT (freezing releases h_sl = h_l - h_i)       */
+            T_end = T_MELT;
+            double rho_sat = exp(or_ln_psat_liq(T_MELT)) / (RGAS_VAP * T_MELT);
+            double C = e.W - rho_sat;
+            if (C < 0.0) C = 0.0;
+            rho_v_end = e.W - C;
+            double hv = L_VAP0 + CP_VAP * (T_MELT - T_REF);
+            double hl = hv - latent_vap(T_MELT), hi = hv - latent_sub(T_MELT);
+            double rho = e.rho_a + rho_v_end, Y = rho_v_end / rho;
+            double rhoE_need = rho * (mix_h0(Y) + mix_cv(Y) * T_MELT + e.ke);
+            double rhoE_liq = e.rhoE - (C - e.m_l) * (hl + e.ke) + e.m_s * (hi + e.ke);
+            I = (rhoE_need - rhoE_liq) / (hl - hi);   /* each kg frozen adds h_l - h_i */
+            if (I < 0.0) I = 0.0;
+            if (I > C) I = C;
+            L = C - I;
+        }
+    }
+    (void)T_end;
+
+    /* end state: dry air, velocity kept; gas mass and energy follow the exchange */
+    double Un[NV];
+    memcpy(Un, U, sizeof(Un));
+    double rho = e.rho_a + rho_v_end;
+    double hvT = L_VAP0 + CP_VAP * (T_end - T_REF);
+    double hlT = hvT - latent_vap(T_end), hiT = hvT - latent_sub(T_end);
+    Un[0] = rho;
+    Un[1] = rho * e.u;
+    Un[2] = rho * e.v;
+    Un[3] = e.rhoE - (L - e.m_l) * (hlT + e.ke) - (I - e.m_s) * (hiT + e.ke);
+    Un[4] = rho_v_end;
+    /* particle numbers: the condensate keeps the particles it has (freezing and
+     * melting move them between the phases); condensate that forms from none sits
+     * on the soot, or without soot on particles of radius R_EQ_NEW               */
+    double Nl = U[5] > N_MIN ? U[5] : 0.0, Ns = U[9] > N_MIN ? U[9] : 0.0;
+    double N = Nl + Ns, C = L + I;
+    int seeded = 0;
+    if (C > 0.0 && !(N > N_MIN)) {
+        if (U[13] > N_MIN) { N = U[13]; seeded = 1; }
+        else N = C / (fpi * (I > 0.0 ? RHO_ICE : RHO_LIQ) * R_EQ_NEW * R_EQ_NEW * R_EQ_NEW);
+    }
+    double mom[4];
+    eq_population(L, C > 0.0 ? N * L / C : 0.0, RHO_LIQ, mom);
+    for (int k = 0; k < 4; ++k) Un[5 + k] = mom[k];
+    eq_population(I, C > 0.0 ? N * I / C : 0.0, RHO_ICE, mom);
+    for (int k = 0; k < 4; ++k) Un[9 + k] = mom[k];
+    if (seeded) Un[14] = U[13];
+    if (!(C > 0.0)) Un[14] = 0.0;
+    for (int v = 0; v < NV; ++v) Q[v] = (Un[v] - U[v]) / dt;
+    return 1;
+}
+
+void or_set_equilibrium(or_ctx *cx, int on) { cx->equilibrium = on ? 1 : 0; }
+
 int or_source_cell(const or_ctx *cx, const double *U, double dt, double *Q)
 {
+    if (cx->equilibrium) return source_equilibrium(cx, U, dt, Q);
     return source_integrate(cx, U, dt, Q);
 }
 
@@ -1013,7 +1172,7 @@ long or_source(const or_ctx *cx, const double *U, double dt, double *Q)
         for (int i = 0; i < nx; ++i) {
             double Uc[NV], Qc[NV];
             for (int v = 0; v < NV; ++v) Uc[v] = U[v * plane + (size_t)j * nx + i];
-            total += source_integrate(cx, Uc, dt, Qc);
+            total += cx->equilibrium ? source_equilibrium(cx, Uc, dt, Qc) : source_integrate(cx, Uc, dt, Qc);
             for (int v = 0; v < NV; ++v) Q[v * plane + (size_t)j * nx + i] = Qc[v];
         }
     return total;

@@ -598,3 +598,150 @@ def test_oracle_thread_count_independent(orc):
         env = dict(os.environ, OMP_NUM_THREADS=nt, PYTHONPATH=root)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env, cwd=root).strip())
     assert outs[0] == outs[1]
+
+
+# ------------------------------------------- equilibrium comparison model (Sec. 4.2)
+def _eq_setup(orc, **case_kw):
+    m, c = inputs.sa0()
+    c = dict(c, **case_kw)
+    o = orc.Oracle(m, c)
+    o.set_equilibrium(True)
+    return o
+
+
+def _y_for(orc, T, p, S_l):
+    pv = S_l * math.exp(orc.lib().or_ln_psat_liq(T))
+    rho_v, rho_a = pv / (461.52 * T), (p - pv) / (287.0 * T)
+    return rho_v / (rho_a + rho_v)
+
+
+def _eq_jump(o, U, dt=1e-6):
+    Q, n = o.source_cell(U, dt)
+    return U + dt * Q, n
+
+
+def _water(U):
+    return U[4] + 4.0 / 3.0 * math.pi * (1000.0 * U[8] + 917.0 * U[12])
+
+
+def _lnS(orc, U, ice):
+    L = orc.lib()
+    T = orc.cons_to_prim(U.copy())[15]
+    lnp = math.log(U[4] * 461.52 * T)
+    return lnp - (L.or_ln_psat_ice(T) if ice else L.or_ln_psat_liq(T)), T
+
+
+def _check_conservation(orc, U, Un):
+    assert _water(Un) == pytest.approx(_water(U), rel=1e-13)
+    assert Un[0] - Un[4] == pytest.approx(U[0] - U[4], rel=1e-14)         # dry air
+    assert Un[1] / Un[0] == pytest.approx(U[1] / U[0], rel=1e-14)          # velocity kept
+    assert Un[13] == U[13]
+
+
+@pytest.mark.parametrize("case", ["warm", "cold", "melting", "evaporating"])
+def test_equilibrium_branches(orc, case):
+    """Equilibrium model (the paper's comparison model, Sec. 4.2): a supersaturated
+    cell above freezing condenses liquid to exact liquid saturation, below freezing
+    ice to exact ice saturation, at the melting point both phases coexist at
+    273.15 K; a subsaturated cell with droplets evaporates them completely.  Water,
+    dry air and velocity are conserved; latent heat moves T the right way by about
+    (h - R_v T) dm / (rho c_v), the constant-volume heat of the transition."""
+    p = 1.0e5
+    if case == "warm":
+        T, S, liq, ns = 290.0, 1.5, (0, 0, 0, 0), 0.0
+    elif case == "cold":
+        T, S, liq, ns = 235.0, 1.2, (0, 0, 0, 0), 1e12
+    elif case == "melting":
+        T, S, liq, ns = 273.1, 1.007, (0, 0, 0, 0), 1e12   # lands between the branches
+    else:
+        N, r = 1e9, 2e-6
+        T, S, liq, ns = 300.0, 0.5, (N, N * r, N * r * r, N * r ** 3), 1e12
+    Y = _y_for(orc, T, p, S)
+    o = _eq_setup(orc)
+    U = _cell(orc, T=T, p=p, Y=Y, u=120.0, v=-3.0, liq=liq, ns=ns, na=ns if case == "evaporating" else 0.0)
+    Un, n = _eq_jump(o, U)
+    assert n == 1
+    _check_conservation(orc, U, Un)
+    Tn = orc.cons_to_prim(Un.copy())[15]
+    dm = U[4] - Un[4]                                        # vapour condensed (kg/m^3)
+    cv = 0.5 * (717.5 * (1 - Y) + 1384.56 * Y) + 0.5 * (717.5 * (1 - Un[4] / Un[0]) + 1384.56 * Un[4] / Un[0])
+    # at fixed volume the condensing vapour also gives up its p dV share R_v T:
+    # rho c_v dT = dm (h - R_v T)
+    RvT = 461.52 * 0.5 * (T + Tn)
+    if case == "warm":
+        lnS, _ = _lnS(orc, Un, ice=False)
+        assert abs(lnS) < 1e-10 and Un[9] == 0.0 and Un[8] > 0.0 and Tn > T
+        assert Un[5] == pytest.approx(dm / (4 / 3 * math.pi * 1000.0 * 1e-21), rel=1e-12)  # r = 0.1 um, no soot
+        h = 2.5008e6 + (1846.08 - 4218.0) * (Tn - 273.15)
+        assert (Tn - T) == pytest.approx((h - RvT) * dm / (Un[0] * cv), rel=0.01)
+    elif case == "cold":
+        lnS, _ = _lnS(orc, Un, ice=True)
+        assert abs(lnS) < 1e-10 and Un[5] == 0.0 and Un[12] > 0.0 and T < Tn < 273.15
+        assert Un[9] == pytest.approx(1e12, rel=1e-12) and Un[14] == pytest.approx(1e12)  # on the soot
+        h = 2.8345e6 + (1846.08 - 2106.0) * (Tn - 273.15)
+        assert (Tn - T) == pytest.approx((h - RvT) * dm / (Un[0] * cv), rel=0.01)
+    elif case == "melting":
+        assert Tn == pytest.approx(273.15, abs=1e-9)
+        assert Un[8] > 0.0 and Un[12] > 0.0                   # both phases
+        lnS, _ = _lnS(orc, Un, ice=False)
+        assert abs(lnS) < 1e-10
+    else:
+        assert Un[5] == 0.0 and Un[8] == 0.0 and Un[9] == 0.0 and Un[14] == 0.0
+        lnS, _ = _lnS(orc, Un, ice=False)
+        assert lnS < 0.0 and Tn < T
+        h = 2.5008e6 + (1846.08 - 4218.0) * (T - 273.15)
+        assert (T - Tn) == pytest.approx((h - RvT) * (-dm) / (Un[0] * cv), rel=0.01)
+
+
+def test_equilibrium_needs_liquid_supersaturation(orc):
+    """Ice never forms from vapour alone: a dry-of-condensate cell that is
+    supersaturated over ice but not over liquid is left as it is (Q = 0)."""
+    o = _eq_setup(orc)
+    T, p = 225.0, 2.4e4
+    Y = _y_for(orc, T, p, 0.9)
+    U = _cell(orc, T=T, p=p, Y=Y, ns=1e12)
+    assert _lnS(orc, U, ice=True)[0] > 0.05
+    Q, n = o.source_cell(U, 1e-6)
+    assert n == 0 and np.all(Q == 0.0)
+
+
+def test_equilibrium_is_a_fixed_point(orc):
+    """The equilibrium state is its own equilibrium (idempotent jump) for random
+    realisable cells of all regimes, and every jump conserves water and dry air."""
+    o = _eq_setup(orc)
+    d = inputs.random_cells(300, seed=11)
+    checked = 0
+    for k in range(300):
+        U = _cell(orc, T=d["T"][k], p=d["p"][k], Y=d["Y"][k], u=d["u"][k], v=d["v"][k],
+                  liq=tuple(d["liq"][:, k]), ice=tuple(d["ice"][:, k]), ns=d["n_soot"][k], na=d["n_act"][k])
+        U1, n1 = _eq_jump(o, U)
+        if n1 == 0:
+            continue
+        checked += 1
+        _check_conservation(orc, U, U1)
+        U2, n2 = _eq_jump(o, U1)
+        # U + dt Q reproduces the end state to rounding of the larger of the two
+        scale = np.abs(U1) + np.abs(U) + 1e-300
+        assert np.all(np.abs(U2 - U1) <= 1e-9 * scale), k
+    assert checked > 100
+
+
+def test_equilibrium_condenses_more_than_kinetics(orc):
+    """The paper's comparison (Sec. 4.2): without the nucleation barrier and growth
+    kinetics the equilibrium model holds more condensed water than the kinetic
+    model on the same source-active jet, and its condensate-bearing cells sit at
+    saturation."""
+    m, c = inputs.sa1(1)
+    res = {}
+    for eq in (False, True):
+        o = orc.Oracle(m, c)
+        o.set_equilibrium(eq)
+        U = o.init()
+        o.run(U, 120)
+        V = np.outer(np.diff(o.faces()[1]) * 0.5 * (o.faces()[1][1:] + o.faces()[1][:-1]), np.diff(o.faces()[0]))
+        cond = 4.0 / 3.0 * math.pi * (1000.0 * U[8] + 917.0 * U[12])
+        res[eq] = (V * cond).sum()
+        if eq:
+            assert res[eq] > 0
+    print("condensed water per radian: kinetic %.4e, equilibrium %.4e" % (res[False], res[True]))
+    assert res[True] >= res[False]
