@@ -90,12 +90,25 @@ def measured_valu(tile):
     return _counter_value(VALU_FILE, "valu_wave_insts_per_launch", tile)
 
 
-def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None):
+def condensed_water(s, U):
+    """Condensed water (liquid + ice) per radian of the axisymmetric domain [kg]."""
+    import math
+    import torch
+    xf, rf = s.faces()
+    dx = torch.as_tensor(xf[1:] - xf[:-1], device=U.device, dtype=torch.float64)
+    rdr = torch.as_tensor((rf[1:] - rf[:-1]) * 0.5 * (rf[1:] + rf[:-1]), device=U.device, dtype=torch.float64)
+    cond = 4.0 / 3.0 * math.pi * (1000.0 * U[8].double() + 917.0 * U[12].double())
+    return float((cond * rdr[:, None] * dx[None, :]).sum())
+
+
+def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None, qmode=None):
     import torch
     s = binding.Solver(m, c, precision)
     U = s.init()
     if tile:
         s.set_tile(*tile)
+    if qmode is not None:
+        s.set_qmode(qmode)
     if sur is not None:
         s.sur_set(sur[0], sur[1])
         s.set_qmode(binding.CP_Q_SURROGATE)
@@ -116,6 +129,7 @@ def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, ke
                sim_time_s=sim_t, tile=list(s.get_tile()), max_lnS_l=d["max_lnS_l"],
                active_cells=d["active_cells"], esz=8 if precision == binding.CP_FP64 else 4, cells=cells)
     if d["active_cells"] > 0:
+        out["condensed_water_per_rad"] = condensed_water(s, U)
         # exact-source sub-steps over the timed steps, per cell-stage of the active set
         subs = d["nsub_total"] - d0["nsub_total"]
         out["source_substeps_per_step"] = subs / steps
@@ -166,7 +180,8 @@ def train_surrogate(binding, inputs, log):
 
 
 def run_source_active(binding, inputs, steps, warmup, trained):
-    """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate."""
+    """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate,
+    and the mixed path with the equilibrium comparison model."""
     import torch
     net, norm, rep = trained
     m, c = inputs.sa2(0)
@@ -175,6 +190,9 @@ def run_source_active(binding, inputs, steps, warmup, trained):
     res["mixed"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True)
     res["mixed_surrogate"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, sur=(net, norm.pack()),
                                       keep=True)
+    # the paper's comparison model (a different model: no error against the kinetics)
+    res["mixed_equilibrium"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
+                                        qmode=binding.CP_Q_EQUILIBRIUM)
     Uref = res["fp64"].pop("U")
     for k in ("mixed", "mixed_surrogate"):
         res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)
@@ -182,6 +200,9 @@ def run_source_active(binding, inputs, steps, warmup, trained):
     torch.cuda.empty_cache()
     out = {k: {kk: v for kk, v in d.items() if kk not in ("esz", "cells", "wall_s")} for k, d in res.items()}
     out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
+    if res["mixed"].get("condensed_water_per_rad"):
+        out["equilibrium_over_kinetic_condensed_water"] = (res["mixed_equilibrium"].get("condensed_water_per_rad", 0.0)
+                                                           / res["mixed"]["condensed_water_per_rad"])
     out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": rep["seconds"],
                                  "val_loss": rep["final_val_loss"]}
     out["steps"] = steps

@@ -63,7 +63,9 @@ enum cp_precision {
 enum cp_qmode {
     CP_Q_EXACT = 0,        /* sub-cycled exact source (Sec. 2.2, Sec. 3.2)          */
     CP_Q_SURROGATE = 1,    /* learned MLP source with exact fallback                */
-    CP_Q_OFF = 2           /* no phase change                                       */
+    CP_Q_OFF = 2,          /* no phase change                                       */
+    CP_Q_EQUILIBRIUM = 3   /* the paper's equilibrium comparison model (Sec. 4.2):
+                              instantaneous phase equilibrium of each cell's water  */
 };
 
 /* AXI: r-weighted axisymmetric cells (Sec. 4.1).  PLANAR: unit-depth cells.
@@ -149,7 +151,15 @@ int cp_cfl_dt(cp_ctx *ctx, const void *U, double *dt_host);
  * simulated time to *t_host (may be NULL).                                        */
 int cp_step_n(cp_ctx *ctx, void *U, int n, double *t_host);
 
-/* Select how Q is evaluated (cp_qmode).  CP_Q_SURROGATE needs cp_sur_set first.   */
+/* Select how Q is evaluated (cp_qmode).  CP_Q_SURROGATE needs cp_sur_set first.
+ * CP_Q_EQUILIBRIUM: Q = (Phi_eq(U) - U)/dt, Phi_eq the cell's water brought to phase
+ * equilibrium at fixed dry air, velocity and energy bookkeeping: liquid at or above
+ * 273.15 K, ice below, both at 273.15 K where neither branch alone is consistent;
+ * vapour at saturation over that phase, or all water evaporated.  A cell without
+ * condensate changes only once supersaturated over liquid.  Particle numbers are
+ * kept (new condensate sits on the soot, or on 0.1 um particles without soot), each
+ * population monodisperse at its mean-mass radius.  Computed in FP64 for both
+ * precisions.  Errors: CP_EINVAL for an unknown mode, CP_ESTATE (see above).       */
 int cp_set_qmode(cp_ctx *ctx, int qmode);
 
 /* Diagnostics (synchronises): out[0] total water mass per radian

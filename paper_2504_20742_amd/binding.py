@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "contrail.h")
 
 CP_OK, CP_EINVAL, CP_EHIP, CP_ENONFINITE, CP_EDT, CP_ESTATE, CP_ENOMEM, CP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 CP_FP64, CP_MIXED = 0, 1
-CP_Q_EXACT, CP_Q_SURROGATE, CP_Q_OFF = 0, 1, 2
+CP_Q_EXACT, CP_Q_SURROGATE, CP_Q_OFF, CP_Q_EQUILIBRIUM = 0, 1, 2, 3
 NV = 15
 
 _lib = None

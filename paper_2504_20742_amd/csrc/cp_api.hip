@@ -763,8 +763,10 @@ int cp_set_qmode(cp_ctx *c, int qmode)
 {
     if (!c) return CP_EINVAL;
     if (qmode == CP_Q_SURROGATE && !c->sur_ready) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
-    if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE) return fail(c, CP_EINVAL, "bad qmode");
+    if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE && qmode != CP_Q_EQUILIBRIUM)
+        return fail(c, CP_EINVAL, "bad qmode");
     c->qmode = qmode;
+    c->sp.equilibrium = qmode == CP_Q_EQUILIBRIUM ? 1 : 0;
     drop_graphs(c);
     return CP_OK;
 }

@@ -48,6 +48,7 @@ struct SourceParams {
     double ice_ratio[4];   // (rho_l / rho_s)^(k/3)
     int n_sub_max;
     int enabled;
+    int equilibrium;       // 1: the equilibrium comparison model replaces the kinetics
 };
 
 // Division: IEEE in FP64; a hardware reciprocal (about 1 ulp) in the FP32 path.
@@ -315,14 +316,148 @@ template <class R> __device__ __forceinline__ bool clearly_inactive(R rho_v, R M
     return lnSl < R(-0.01);
 }
 
+// ----------------------------------------------- equilibrium comparison model
+// Sec. 4.2 compares the kinetics with a model in which the cell's water is in
+// phase equilibrium at every instant: the condensate is liquid at or above the
+// melting point, ice below it (both at the melting point when the liquid branch
+// settles below it and the ice branch above), the vapour at saturation over that
+// phase, or all water evaporated.  Dry air, velocity and water are kept; the gas
+// energy follows the kinetic exchange (condensate leaves with h_l or h_i at the end
+// temperature), so the end temperature solves T_gas(T) = T on the chosen branch.
+constexpr double kTmelt = 273.15;
+constexpr double kRnew = 1.0e-7;   // m: particles of condensate that forms without soot
+
+struct EqCell {
+    double rho_a, rho_v, m_l, m_s, W, u, v, ke, rhoE;
+};
+
+// Gas temperature of the branch end state at trial temperature Ts (ice: condensate
+// is ice); also the vapour density and condensate mass of that state.
+__device__ __forceinline__ double eq_gas_T(const EqCell &e, bool ice, double Ts, double &rho_v, double &cond)
+{
+    const double rho_sat = exp(ln_psat(ice ? kSonI : kSonW, Ts)) / (kRv * Ts);
+    cond = fmax(e.W - rho_sat, 0.0);
+    rho_v = e.W - cond;
+    const double hv = kLv0 + kCpv * (Ts - kTref);
+    const double hl = hv - (kLv0 + (kCpv - kCl) * (Ts - kTref)), hi = hv - (kLs0 + (kCpv - kCi) * (Ts - kTref));
+    const double dL = (ice ? 0.0 : cond) - e.m_l, dI = (ice ? cond : 0.0) - e.m_s;
+    const double rhoE = e.rhoE - dL * (hl + e.ke) - dI * (hi + e.ke);
+    const double rho = e.rho_a + rho_v, Y = rho_v / rho;
+    return gas_T<double>(rhoE / rho - e.ke, Y);
+}
+
+// The branch's end temperature: T_gas falls as Ts rises (warmer saturation keeps
+// more vapour and releases less heat), so bisection on [100, 1000] K.
+__device__ __forceinline__ double eq_root(const EqCell &e, bool ice)
+{
+    double a = 100.0, b = 1000.0, rv, c;
+    for (int it = 0; it < 64; ++it) {
+        const double m = 0.5 * (a + b);
+        if (eq_gas_T(e, ice, m, rv, c) > m) a = m;
+        else b = m;
+    }
+    return 0.5 * (a + b);
+}
+
+__device__ __forceinline__ void eq_moments(double M, double N, double rho_p, double *mom)
+{
+    if (!(M > 0.0) || !(N > 0.0)) {
+        mom[0] = mom[1] = mom[2] = mom[3] = 0.0;
+        return;
+    }
+    const double r = cbrt(M / (kFourThirdsPi * rho_p * N));
+    mom[0] = N;
+    mom[1] = N * r;
+    mom[2] = N * r * r;
+    mom[3] = N * r * r * r;
+}
+
+// Q = (Phi_eq(U) - U) / dt; returns 1 when the cell changed phase state, else 0.
+__device__ inline int source_equilibrium(const double *U, double dt, double *Q)
+{
+    CellThermo th;
+    cell_thermo(U, th);
+    if (source_inactive(U, th.T)) return 0;   // no condensate, not supersaturated over liquid
+    EqCell e;
+    e.rho_v = U[4];
+    e.rho_a = U[0] - U[4];
+    e.m_l = U[5] > kNmin ? kFourThirdsPi * kRhoL * U[8] : 0.0;
+    e.m_s = U[9] > kNmin ? kFourThirdsPi * kRhoS * U[12] : 0.0;
+    e.W = e.rho_v + e.m_l + e.m_s;
+    e.u = th.u;
+    e.v = th.v;
+    e.ke = 0.5 * (th.u * th.u + th.v * th.v);
+    e.rhoE = U[3];
+
+    double T, rho_v, L = 0.0, I = 0.0, c;
+    const double TL = eq_root(e, false);
+    eq_gas_T(e, false, TL, rho_v, c);
+    if (TL >= kTmelt) {
+        T = TL;
+        L = c;
+    } else {
+        const double TI = eq_root(e, true);
+        eq_gas_T(e, true, TI, rho_v, c);
+        if (TI < kTmelt) {
+            T = TI;
+            I = c;
+        } else {   // both phases at the melting point; the ice share closes the energy balance
+            T = kTmelt;
+            const double C = fmax(e.W - exp(ln_psat(kSonW, kTmelt)) / (kRv * kTmelt), 0.0);
+            rho_v = e.W - C;
+            const double hv = kLv0 + kCpv * (kTmelt - kTref);
+            const double hl = hv - (kLv0 + (kCpv - kCl) * (kTmelt - kTref));
+            const double hi = hv - (kLs0 + (kCpv - kCi) * (kTmelt - kTref));
+            const double rho = e.rho_a + rho_v, Y = rho_v / rho;
+            const double need = rho * (gas_h0<double>(Y) + gas_cv<double>(Y) * kTmelt + e.ke);
+            const double all_liquid = e.rhoE - (C - e.m_l) * (hl + e.ke) + e.m_s * (hi + e.ke);
+            I = fmin(fmax((need - all_liquid) / (hl - hi), 0.0), C);
+            L = C - I;
+        }
+    }
+    double Un[NVAR];
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Un[v] = U[v];
+    const double rho = e.rho_a + rho_v;
+    const double hv = kLv0 + kCpv * (T - kTref);
+    const double hl = hv - (kLv0 + (kCpv - kCl) * (T - kTref)), hi = hv - (kLs0 + (kCpv - kCi) * (T - kTref));
+    Un[0] = rho;
+    Un[1] = rho * e.u;
+    Un[2] = rho * e.v;
+    Un[3] = e.rhoE - (L - e.m_l) * (hl + e.ke) - (I - e.m_s) * (hi + e.ke);
+    Un[4] = rho_v;
+    // particles: kept across freezing and melting; new condensate on the soot, or on
+    // kRnew particles without soot
+    const double C = L + I;
+    double N = (U[5] > kNmin ? U[5] : 0.0) + (U[9] > kNmin ? U[9] : 0.0);
+    bool seeded = false;
+    if (C > 0.0 && !(N > kNmin)) {
+        if (U[13] > kNmin) {
+            N = U[13];
+            seeded = true;
+        } else {
+            N = C / (kFourThirdsPi * (I > 0.0 ? kRhoS : kRhoL) * kRnew * kRnew * kRnew);
+        }
+    }
+    eq_moments(L, C > 0.0 ? N * L / C : 0.0, kRhoL, Un + 5);
+    eq_moments(I, C > 0.0 ? N * I / C : 0.0, kRhoS, Un + 9);
+    if (seeded) Un[14] = U[13];
+    if (!(C > 0.0)) Un[14] = 0.0;
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Q[v] = (Un[v] - U[v]) / dt;
+    return 1;
+}
+
 // Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
-// scaling, complete evaporation / sublimation and the mu1 realisability clamp.
-// Returns the number of sub-steps (0 when the cell is inactive).
+// scaling, complete evaporation / sublimation and the mu1 realisability clamp
+// (or by the equilibrium model when selected).  Returns the number of sub-steps
+// (0 when the cell is inactive).
 __device__ inline int source_integrate(const double *U0, double dt, const SourceParams &sp, double *Q)
 {
     #pragma unroll
     for (int v = 0; v < NVAR; ++v) Q[v] = 0.0;
     if (!sp.enabled) return 0;
+    if (sp.equilibrium) return source_equilibrium(U0, dt, Q);
     CellThermo th;
     cell_thermo(U0, th);
     if (source_inactive(U0, th.T)) return 0;
