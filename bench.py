@@ -101,7 +101,8 @@ def condensed_water(s, U):
     return float((cond * rdr[:, None] * dx[None, :]).sum())
 
 
-def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None, qmode=None):
+def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None, qmode=None,
+             table_h=0.0):
     import torch
     s = binding.Solver(m, c, precision)
     U = s.init()
@@ -109,6 +110,8 @@ def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, ke
         s.set_tile(*tile)
     if qmode is not None:
         s.set_qmode(qmode)
+    if table_h > 0.0:
+        s.set_property_table(table_h)
     if sur is not None:
         s.sur_set(sur[0], sur[1])
         s.set_qmode(binding.CP_Q_SURROGATE)
@@ -181,7 +184,8 @@ def train_surrogate(binding, inputs, log):
 
 def run_source_active(binding, inputs, steps, warmup, trained):
     """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate,
-    and the mixed path with the equilibrium comparison model."""
+    mixed with tabulated water properties, and the mixed path with the equilibrium
+    comparison model."""
     import torch
     net, norm, rep = trained
     m, c = inputs.sa2(0)
@@ -190,11 +194,13 @@ def run_source_active(binding, inputs, steps, warmup, trained):
     res["mixed"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True)
     res["mixed_surrogate"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, sur=(net, norm.pack()),
                                       keep=True)
+    # water properties from 0.25 K tables read by second-order Taylor expansion
+    res["mixed_tables"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, table_h=0.25)
     # the paper's comparison model (a different model: no error against the kinetics)
     res["mixed_equilibrium"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
                                         qmode=binding.CP_Q_EQUILIBRIUM)
     Uref = res["fp64"].pop("U")
-    for k in ("mixed", "mixed_surrogate"):
+    for k in ("mixed", "mixed_surrogate", "mixed_tables"):
         res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)
     del Uref
     torch.cuda.empty_cache()

@@ -171,6 +171,18 @@ int cp_set_qmode(cp_ctx *ctx, int qmode);
  * to the exact fallback, summed over every stage since cp_sur_set.              */
 int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
 
+/* Water properties of the phase-change source (ln p_sat over liquid and ice, the
+ * surface tension) from a table instead of the closed forms, as the paper reads its
+ * pre-tabulated properties (Sec. 3.2): nodes every h kelvin on [150, 700] K, each
+ * holding value, slope and half curvature; a lookup expands to second order about
+ * the nearest node (about the end node outside the range), so the error falls as
+ * h^3 (about 2e-8 in ln p_sat at h = 0.25 K).  Saturation temperatures invert the
+ * expanded ln p_sat.  Whether a cell's source can be non-zero is still decided on
+ * the closed form.  h = 0 returns to the closed forms.  The context keeps its own
+ * device copy; the call synchronises the stream.  Errors: CP_EINVAL (h < 0, or
+ * more than 1e6 nodes), CP_ENOMEM, CP_EHIP.                                       */
+int cp_set_property_table(cp_ctx *ctx, double h);
+
 /* Tile shape of the stage kernel: (tx, ty) from the built set, or (0, 0) to run the
  * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built.     */
 int cp_set_tile(cp_ctx *ctx, int tx, int ty);

@@ -94,6 +94,12 @@ def lib():
         L.or_diag.argtypes = [_V, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
         L.or_set_equilibrium.argtypes = [_V, ctypes.c_int]
+        L.or_property.restype = _D
+        L.or_property.argtypes = [_V, ctypes.c_int, _D]
+        L.or_property_tsat.restype = _D
+        L.or_property_tsat.argtypes = [_V, ctypes.c_int, _D, _D]
+        L.or_set_property_table.restype = ctypes.c_int
+        L.or_set_property_table.argtypes = [_V, _D]
         L.or_set_area.restype = ctypes.c_int
         L.or_set_area.argtypes = [_V, _P]
         L.or_case_derived.argtypes = [_V, _P]
@@ -182,6 +188,16 @@ class Oracle:
         """Switch the phase change between the kinetic model and the equilibrium
         comparison model (instantaneous phase equilibrium per cell)."""
         self.L.or_set_equilibrium(self.h, 1 if on else 0)
+
+    def set_property_table(self, h):
+        """Water properties from a table of spacing h [K] read by a second-order Taylor
+        expansion (h = 0: the closed forms)."""
+        if self.L.or_set_property_table(self.h, float(h)) != 0:
+            raise ValueError("or_set_property_table: spacing must be >= 0 and give at most 1e6 nodes")
+
+    def property(self, q, T):
+        """Water property q (0 ln p_sat,w, 1 ln p_sat,i, 2 sigma) as the source reads it."""
+        return self.L.or_property(self.h, int(q), float(T))
 
     def set_area(self, area):
         """Quasi-1D duct only: cross-section areas at the nx+1 x faces."""

@@ -103,6 +103,9 @@ typedef struct {
     double soot_area;           /* 4 pi r_g^2 exp(2 ln^2 sigma_g) per particle     */
     double delta0;
     int equilibrium;            /* 1: equilibrium phase change instead of kinetics */
+    double *ptab;               /* water property table (null: closed forms)       */
+    int ptab_n;
+    double ptab_T0, ptab_h;
 } or_ctx;
 
 /* ================================================================ Sec. 2.2 == */
@@ -145,6 +148,117 @@ double or_sigma_lg(double T)
 {
     double tau = 1.0 - T / 647.096;
     return 0.2358 * pow(tau, 1.256) * (1.0 - 0.625 * tau);
+}
+
+/* ======================================= tabulated water properties (Sec. 3.2) == */
+/* The paper tabulates the water properties before the run and interpolates them
+ * with a second-order Taylor expansion.  Here: nodes T_k = T0 + k h on [150, 700] K
+ * holding f, f' and f''/2 of ln p_sat over liquid, ln p_sat over ice and the
+ * surface tension, from their closed forms and analytic derivatives; a lookup
+ * expands about the nearest node (outside the range, about the end node).        */
+enum { PT_LNPW = 0, PT_LNPI = 1, PT_SIGMA = 2, PT_NPROP = 3 };
+static const double PT_T0 = 150.0, PT_T1 = 700.0;
+
+static void sonntag_derivs(int ice, double T, double *f)
+{
+    double a, c, d, e;
+    if (ice) { a = -6024.5282; c = 1.0613868e-2; d = -1.3198825e-5; e = -0.49382577; }
+    else     { a = -6096.9385; c = -2.711193e-2; d = 1.673952e-5; e = 2.433502; }
+    f[0] = ice ? or_ln_psat_ice(T) : or_ln_psat_liq(T);
+    f[1] = -a / (T * T) + c + 2.0 * d * T + e / T;
+    f[2] = 0.5 * (2.0 * a / (T * T * T) + 2.0 * d - e / (T * T));
+}
+
+static void sigma_derivs(double T, double *f)
+{
+    /* sigma = B (tau^m - 0.625 tau^(m+1)), tau = 1 - T/Tc */
+    const double B = 0.2358, m = 1.256, Tc = 647.096;
+    double tau = 1.0 - T / Tc;
+    if (!(tau > 0.0)) {   /* no surface tension at and above the critical point */
+        f[0] = f[1] = f[2] = 0.0;
+        return;
+    }
+    double s1 = B * (m * pow(tau, m - 1.0) - 0.625 * (m + 1.0) * pow(tau, m));
+    double s2 = B * (m * (m - 1.0) * pow(tau, m - 2.0) - 0.625 * (m + 1.0) * m * pow(tau, m - 1.0));
+    f[0] = or_sigma_lg(T);
+    f[1] = -s1 / Tc;
+    f[2] = 0.5 * s2 / (Tc * Tc);
+}
+
+int or_set_property_table(or_ctx *cx, double h)
+{
+    free(cx->ptab);
+    cx->ptab = NULL;
+    cx->ptab_n = 0;
+    if (h == 0.0) return 0;
+    if (!(h > 0.0) || (PT_T1 - PT_T0) / h > 1.0e6) return -1;
+    int n = (int)floor((PT_T1 - PT_T0) / h) + 1;
+    cx->ptab = malloc(sizeof(double) * 3 * PT_NPROP * n);
+    cx->ptab_n = n;
+    cx->ptab_T0 = PT_T0;
+    cx->ptab_h = h;
+    for (int k = 0; k < n; ++k) {
+        double T = PT_T0 + k * h;
+        double *row = cx->ptab + 3 * PT_NPROP * k;
+        sonntag_derivs(0, T, row + 3 * PT_LNPW);
+        sonntag_derivs(1, T, row + 3 * PT_LNPI);
+        sigma_derivs(T, row + 3 * PT_SIGMA);
+    }
+    return 0;
+}
+
+/* Taylor expansion of property q about the node nearest T; *dfdT its slope.       */
+static double ptab_eval(const or_ctx *cx, int q, double T, double *dfdT)
+{
+    double u = (T - cx->ptab_T0) / cx->ptab_h;
+    int k = (int)floor(u + 0.5);
+    if (k < 0) k = 0;
+    if (k > cx->ptab_n - 1) k = cx->ptab_n - 1;
+    const double *c = cx->ptab + 3 * PT_NPROP * k + 3 * q;
+    double d = T - (cx->ptab_T0 + k * cx->ptab_h);
+    if (dfdT) *dfdT = c[1] + 2.0 * c[2] * d;
+    return c[0] + d * (c[1] + d * c[2]);
+}
+
+/* The water properties the phase change reads: the table when one is set, else
+ * the closed forms.                                                               */
+static double prop_lnp(const or_ctx *cx, int ice, double T)
+{
+    if (cx->ptab) return ptab_eval(cx, ice ? PT_LNPI : PT_LNPW, T, NULL);
+    return ice ? or_ln_psat_ice(T) : or_ln_psat_liq(T);
+}
+
+static double prop_sigma(const or_ctx *cx, double T)
+{
+    if (cx->ptab) return ptab_eval(cx, PT_SIGMA, T, NULL);
+    return or_sigma_lg(T);
+}
+
+/* Saturation temperature at ln p_v: with a table, the same four Newton steps in
+ * x = 1/T from the gas temperature on the expanded ln p_sat, whose slope in x is
+ * -T^2 d(ln p_sat)/dT.                                                            */
+static double prop_tsat(const or_ctx *cx, int ice, double lnpv, double T_start)
+{
+    if (!cx->ptab) return tsat_newton(ice, lnpv, T_start);
+    double x = 1.0 / T_start;
+    for (int it = 0; it < 4; ++it) {
+        double T = 1.0 / x, g;
+        double f = ptab_eval(cx, ice ? PT_LNPI : PT_LNPW, T, &g) - lnpv;
+        x = x - f / (-T * T * g);
+    }
+    return 1.0 / x;
+}
+
+/* Property q (0 ln p_sat liquid, 1 ln p_sat ice, 2 surface tension) as the phase
+ * change reads it, and the saturation temperature over liquid (ice = 0) or ice.  */
+double or_property(const or_ctx *cx, int q, double T)
+{
+    return q == PT_SIGMA ? prop_sigma(cx, T) : prop_lnp(cx, q == PT_LNPI, T);
+}
+
+double or_property_tsat(const or_ctx *cx, int ice, double lnpv, double T_start)
+{
+    return prop_tsat(cx, ice, lnpv, T_start);
 }
 
 static double latent_vap(double T) { return L_VAP0 + (CP_VAP - C_LIQ) * (T - T_REF); }
@@ -201,12 +315,16 @@ double or_contact_factor(double theta_rad)
 /* Eq. 12: homogeneous freezing rate of Koop et al. (2000), the water-activity
  * polynomial, converted from cm^-3 s^-1 to m^-3 s^-1.  Pure water droplets
  * (a_w = 1), so Delta a_w = 1 - p_sat,ice/p_sat,liq, clamped to the fit range.  */
-double or_koop_delta_aw(double T)
+static double koop_clamp(double d)
 {
-    double d = 1.0 - exp(or_ln_psat_ice(T) - or_ln_psat_liq(T));
     if (d < 0.26) d = 0.26;
     if (d > 0.34) d = 0.34;
     return d;
+}
+
+double or_koop_delta_aw(double T)
+{
+    return koop_clamp(1.0 - exp(or_ln_psat_ice(T) - or_ln_psat_liq(T)));
 }
 
 double or_koop_rate(double daw)
@@ -334,11 +452,11 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     double pv = rho_v * RGAS_VAP * T;
     if (pv < PV_FLOOR) pv = PV_FLOOR;
     const double lnpv = log(pv);
-    const double lnpw = or_ln_psat_liq(T), lnpi = or_ln_psat_ice(T);
+    const double lnpw = prop_lnp(cx, 0, T), lnpi = prop_lnp(cx, 1, T);
     const double lnSl = lnpv - lnpw, lnSi = lnpv - lnpi;
     r->lnSl = lnSl; r->lnSi = lnSi;
 
-    const double sigma = or_sigma_lg(T);
+    const double sigma = prop_sigma(cx, T);
     const double hfg = latent_vap(T), hsg = latent_sub(T);
     const double mu = or_mu_sutherland(T);
     const double lambda_g = w.cp * mu / PRANDTL;
@@ -373,7 +491,7 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     /* Eq. 16, 21: droplet growth at r20 with the Kelvin factor (1 - r_crit/r) */
     if (liquid) {
         double r20 = sqrt(M[2] / M[0]);
-        double Tsat = tsat_newton(0, lnpv, T);
+        double Tsat = prop_tsat(cx, 0, lnpv, T);
         double dT = Tsat - T;
         double drive;
         if (fabs(lnSl) < 1e-12)
@@ -386,7 +504,7 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     /* ice crystals grow analogously with ice properties, no Kelvin factor */
     if (ice) {
         double r20 = sqrt(N[2] / N[0]);
-        double Tsat = tsat_newton(1, lnpv, T);
+        double Tsat = prop_tsat(cx, 1, lnpv, T);
         double dT = Tsat - T;
         double nu = or_young_nu(Tsat, hsg);
         r->Gs = or_young_growth(lambda_g, dT, r20, RHO_ICE, hsg, nu, lbar);
@@ -401,7 +519,7 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
         double Mh[7];
         Mh[3] = M[3];
         for (int n = 4; n <= 6; ++n) Mh[n] = M[0] * exp(n * lnrg + 0.5 * n * n * s2);
-        double Jhom_s = or_koop_rate(or_koop_delta_aw(T));
+        double Jhom_s = or_koop_rate(koop_clamp(1.0 - exp(lnpi - lnpw)));
         double Jhet_s = cx->c.k_imm * cx->c.n_s * Ns * cx->soot_area;
         double Jf = Jhom_s + Jhet_s;
         for (int k = 0; k < 4; ++k) r->F[k] = Jf * (4.0 / 3.0 * PI) * Mh[k + 3];
@@ -455,6 +573,20 @@ void or_source_rates_cell(const or_ctx *cx, const double *U, double h, double *S
     }
 }
 
+/* A cell with no particles that is not supersaturated over liquid has no source:
+ * no nucleation, growth or freezing can start there (the rates below are all zero).
+ * Decided on the closed-form saturation pressure in either property mode.        */
+static int source_idle(const double *U)
+{
+    if (U[5] > N_MIN || U[9] > N_MIN) return 0;
+    if (!(U[4] > 0.0)) return 1;
+    prim_t w;
+    cons_to_prim(U, &w);
+    double pv = U[4] * RGAS_VAP * w.T;
+    if (pv < PV_FLOOR) pv = PV_FLOOR;
+    return !(log(pv) - or_ln_psat_liq(w.T) > 0.0);
+}
+
 /* Stiff source integration over dt (explicit sub-cycling, per-step positivity
  * scaling, complete-evaporation rule, mu1 realisability clamp). Returns
  * Q = (U(t+dt) - U(t)) / dt and the number of sub-steps taken.                   */
@@ -462,7 +594,7 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
 {
     double U[NV];
     memcpy(U, U0, sizeof(U));
-    if (!cx->c.phase_change) {
+    if (!cx->c.phase_change || source_idle(U)) {
         for (int v = 0; v < NV; ++v) Q[v] = 0.0;
         return 0;
     }
@@ -558,10 +690,9 @@ typedef struct {
 /* End state of one phase branch at trial temperature Ts: vapour at saturation over
  * the phase (ice = 0 liquid, 1 ice; capped by the water available), the rest
  * condensed in that phase.  Returns the temperature the gas then has.           */
-static double eq_branch_T(const eq_cell_t *e, int ice, double Ts, double *rho_v_out, double *cond_out)
+static double eq_branch_T(const or_ctx *cx, const eq_cell_t *e, int ice, double Ts, double *rho_v_out, double *cond_out)
 {
-    double lnp = ice ? or_ln_psat_ice(Ts) : or_ln_psat_liq(Ts);
-    double rho_sat = exp(lnp) / (RGAS_VAP * Ts);
+    double rho_sat = exp(prop_lnp(cx, ice, Ts)) / (RGAS_VAP * Ts);
     double cond = e->W - rho_sat;
     if (cond < 0.0) cond = 0.0;
     double rho_v = e->W - cond;
@@ -579,12 +710,12 @@ static double eq_branch_T(const eq_cell_t *e, int ice, double Ts, double *rho_v_
 
 /* Root of T_gas(Ts) = Ts of one branch by bisection (the gas temperature falls as
  * Ts rises: warmer saturation keeps more vapour and releases less heat).        */
-static double eq_branch_root(const eq_cell_t *e, int ice)
+static double eq_branch_root(const or_ctx *cx, const eq_cell_t *e, int ice)
 {
     double a = 100.0, b = 1000.0;
     for (int it = 0; it < 64; ++it) {
         double m = 0.5 * (a + b);
-        if (eq_branch_T(e, ice, m, NULL, NULL) > m) a = m;
+        if (eq_branch_T(cx, e, ice, m, NULL, NULL) > m) a = m;
         else b = m;
     }
     return 0.5 * (a + b);
@@ -606,15 +737,9 @@ static int source_equilibrium(const or_ctx *cx, const double *U, double dt, doub
 {
     for (int v = 0; v < NV; ++v) Q[v] = 0.0;
     if (!cx->c.phase_change) return 0;
+    if (source_idle(U)) return 0;   /* no condensate, not supersaturated over liquid */
     prim_t w;
     cons_to_prim(U, &w);
-    /* no condensate and not supersaturated over liquid: nothing happens */
-    if (!(U[5] > N_MIN) && !(U[9] > N_MIN)) {
-        if (!(U[4] > 0.0)) return 0;
-        double pv = U[4] * RGAS_VAP * w.T;
-        if (pv < PV_FLOOR) pv = PV_FLOOR;
-        if (!(log(pv) - or_ln_psat_liq(w.T) > 0.0)) return 0;
-    }
     const double fpi = 4.0 / 3.0 * PI;
     eq_cell_t e;
     e.rho_v = U[4];
@@ -629,20 +754,20 @@ static int source_equilibrium(const or_ctx *cx, const double *U, double dt, doub
     /* phase of the condensate: liquid if its branch settles at or above T_MELT, ice
      * if the ice branch settles below, else both at T_MELT                          */
     double T_end, rho_v_end, L = 0.0, I = 0.0;
-    double TL = eq_branch_root(&e, 0), cL;
-    eq_branch_T(&e, 0, TL, &rho_v_end, &cL);
+    double TL = eq_branch_root(cx, &e, 0), cL;
+    eq_branch_T(cx, &e, 0, TL, &rho_v_end, &cL);
     if (TL >= T_MELT) {
         T_end = TL; L = cL;
     } else {
-        double TI = eq_branch_root(&e, 1), cI;
-        eq_branch_T(&e, 1, TI, &rho_v_end, &cI);
+        double TI = eq_branch_root(cx, &e, 1), cI;
+        eq_branch_T(cx, &e, 1, TI, &rho_v_end, &cI);
         if (TI < T_MELT) {
             T_end = TI; I = cI;
         } else {
             /* both phases at T_MELT, vapour saturated over liquid; the ice share is the
              * one that puts the gas at T_MELT (freezing releases h_sl = h_l - h_i)       */
             T_end = T_MELT;
-            double rho_sat = exp(or_ln_psat_liq(T_MELT)) / (RGAS_VAP * T_MELT);
+            double rho_sat = exp(prop_lnp(cx, 0, T_MELT)) / (RGAS_VAP * T_MELT);
             double C = e.W - rho_sat;
             if (C < 0.0) C = 0.0;
             rho_v_end = e.W - C;
@@ -800,6 +925,7 @@ void or_destroy(or_ctx *cx)
     free(cx->xf); free(cx->rf); free(cx->xc); free(cx->rc); free(cx->dx); free(cx->dr);
     free(cx->inflow);
     free(cx->ax);
+    free(cx->ptab);
     free(cx);
 }
 

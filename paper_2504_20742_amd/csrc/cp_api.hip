@@ -30,6 +30,7 @@ struct cp_ctx {
     long plane = 0;
     std::vector<double> xf, rf, xc, rc, dx, dr;     // host mesh
     std::vector<double> ax;                         // quasi-1D duct areas at the x faces
+    double *ptab = nullptr;                         // water property table (device), or null
     std::vector<void *> allocs;                     // device memory owned by the context
     double *inflow = nullptr, *ambient = nullptr, *vol = nullptr;
     double *xc_d = nullptr, *rc_d = nullptr, *inv_dx_d = nullptr, *inv_dr_d = nullptr;
@@ -99,6 +100,46 @@ double h_cv(double Y) { return h_cp(Y) - h_R(Y); }
 double h_ln_psat_ice(double T)
 {
     return -6024.5282 / T + 24.7219 + 1.0613868e-2 * T - 1.3198825e-5 * T * T - 0.49382577 * log(T) + log(100.0);
+}
+
+// Water property table: on nodes T0 + k h the value, slope and half curvature of
+// ln p_sat over liquid and over ice (Sonntag) and of the IAPWS surface tension
+// (zero at and above the critical point), from the closed forms' analytic
+// derivatives.
+constexpr double kTabT0 = 150.0, kTabT1 = 700.0;
+
+void sonntag_taylor(const double *k, double T, double *f)   // k: a, b, c, d, e
+{
+    f[0] = k[0] / T + k[1] + k[2] * T + k[3] * T * T + k[4] * log(T) + log(100.0);
+    f[1] = -k[0] / (T * T) + k[2] + 2.0 * k[3] * T + k[4] / T;
+    f[2] = k[0] / (T * T * T) + k[3] - 0.5 * k[4] / (T * T);
+}
+
+void sigma_taylor(double T, double *f)
+{
+    const double B = 0.2358, m = 1.256, Tc = 647.096, t = 1.0 - T / Tc;
+    if (!(t > 0.0)) {
+        f[0] = f[1] = f[2] = 0.0;
+        return;
+    }
+    // sigma(t) = B (t^m - 0.625 t^(m+1)); d/dT = -(1/Tc) d/dt
+    f[0] = B * pow(t, m) * (1.0 - 0.625 * t);
+    f[1] = -B * (m * pow(t, m - 1.0) - 0.625 * (m + 1.0) * pow(t, m)) / Tc;
+    f[2] = 0.5 * B * (m * (m - 1.0) * pow(t, m - 2.0) - 0.625 * (m + 1.0) * m * pow(t, m - 1.0)) / (Tc * Tc);
+}
+
+std::vector<double> property_table(double h, int n)
+{
+    static const double liq[5] = {-6096.9385, 16.635794, -2.711193e-2, 1.673952e-5, 2.433502};
+    static const double ice[5] = {-6024.5282, 24.7219, 1.0613868e-2, -1.3198825e-5, -0.49382577};
+    std::vector<double> t((size_t)n * 9);
+    for (int k = 0; k < n; ++k) {
+        const double T = kTabT0 + k * h;
+        sonntag_taylor(liq, T, &t[9 * (size_t)k]);
+        sonntag_taylor(ice, T, &t[9 * (size_t)k + 3]);
+        sigma_taylor(T, &t[9 * (size_t)k + 6]);
+    }
+    return t;
 }
 
 // Conserved state of a jet or of the free stream: pressure-matched, no radial
@@ -606,6 +647,7 @@ void cp_destroy(cp_ctx *c)
     drop_graphs(c);
     for (void *p : c->allocs)
         if (p) hipFree(p);
+    if (c->ptab) hipFree(c->ptab);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     delete c;
 }
@@ -830,6 +872,31 @@ int cp_set_tile(cp_ctx *c, int tx, int ty)
         c->ty = ty;
     }
     drop_graphs(c);
+    return CP_OK;
+}
+
+int cp_set_property_table(cp_ctx *c, double h)
+{
+    if (!c) return CP_EINVAL;
+    if (!(h >= 0.0) || (h > 0.0 && (kTabT1 - kTabT0) / h > 1.0e6)) return fail(c, CP_EINVAL, "table spacing");
+    // captured steps carry the old table pointer: drop them, and let queued work finish
+    drop_graphs(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->ptab) hipFree(c->ptab);
+    c->ptab = nullptr;
+    c->sp.ptab = nullptr;
+    c->sp.ptab_n = 0;
+    if (h == 0.0) return CP_OK;
+    const int n = (int)floor((kTabT1 - kTabT0) / h) + 1;
+    const std::vector<double> t = property_table(h, n);
+    void *p = nullptr;
+    if (hipMalloc(&p, t.size() * sizeof(double)) != hipSuccess) return fail(c, CP_ENOMEM, "property table");
+    c->ptab = (double *)p;
+    HIPCHK(c, hipMemcpy(c->ptab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->sp.ptab = c->ptab;
+    c->sp.ptab_T0 = kTabT0;
+    c->sp.ptab_h = h;
+    c->sp.ptab_n = n;
     return CP_OK;
 }
 

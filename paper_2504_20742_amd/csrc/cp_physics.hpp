@@ -49,6 +49,11 @@ struct SourceParams {
     int n_sub_max;
     int enabled;
     int equilibrium;       // 1: the equilibrium comparison model replaces the kinetics
+    // water property table (null: closed forms): nodes T0 + k h, k < n, each holding
+    // (f, f', f''/2) of ln p_sat over liquid, ln p_sat over ice, surface tension
+    const double *ptab;
+    double ptab_T0, ptab_h;
+    int ptab_n;
 };
 
 // Division: IEEE in FP64; a hardware reciprocal (about 1 ulp) in the FP32 path.
@@ -139,6 +144,50 @@ __device__ __forceinline__ double surface_tension(double T)
     return 0.2358 * pow(tau, 1.256) * (1.0 - 0.625 * tau);
 }
 
+// ------------------------------------------------ tabulated water properties
+// The paper interpolates pre-tabulated water properties with a second-order
+// Taylor expansion (Sec. 3.2): about the node nearest T (the end node outside the
+// table), f + f' d + (f''/2) d^2.  Without a table the closed forms are used.
+constexpr int kPropLnpw = 0, kPropLnpi = 1, kPropSigma = 2, kPropStride = 9;
+
+__device__ __forceinline__ double ptab_eval(const SourceParams &sp, int q, double T, double *dfdT)
+{
+    const double kd = fmin(fmax(floor((T - sp.ptab_T0) / sp.ptab_h + 0.5), 0.0), (double)(sp.ptab_n - 1));
+    const int k = (int)kd;
+    const double *c = sp.ptab + kPropStride * k + 3 * q;
+    const double d = T - (sp.ptab_T0 + k * sp.ptab_h);
+    if (dfdT) *dfdT = c[1] + 2.0 * c[2] * d;
+    return c[0] + d * (c[1] + d * c[2]);
+}
+
+__device__ __forceinline__ double prop_lnp(const SourceParams &sp, bool ice, double T)
+{
+    if (sp.ptab) return ptab_eval(sp, ice ? kPropLnpi : kPropLnpw, T, nullptr);
+    return ln_psat(ice ? kSonI : kSonW, T);
+}
+
+__device__ __forceinline__ double prop_sigma(const SourceParams &sp, double T)
+{
+    if (sp.ptab) return ptab_eval(sp, kPropSigma, T, nullptr);
+    return surface_tension(T);
+}
+
+// T_sat: with a table the same four Newton steps in x = 1/T on the expanded
+// ln p_sat (slope in x: -T^2 d ln p_sat / dT).
+__device__ __forceinline__ double prop_tsat(const SourceParams &sp, bool ice, double lnpv, double T)
+{
+    if (!sp.ptab) return t_sat(ice ? kSonI : kSonW, lnpv, T);
+    double x = 1.0 / T;
+    #pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const double t = 1.0 / x;
+        double g;
+        const double f = ptab_eval(sp, ice ? kPropLnpi : kPropLnpw, t, &g) - lnpv;
+        x = x - f / (-t * t * g);
+    }
+    return 1.0 / x;
+}
+
 // Young's parameter nu (Eq. 16) with gamma, c_p of the vapour and q_c.
 __device__ __forceinline__ double young_nu(double Tsat, double h)
 {
@@ -195,9 +244,9 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
 
     double pv = fmax(rv * kRv * T, kPvFloor);
     const double lnpv = log(pv);
-    const double lw = ln_psat(kSonW, T);
+    const double lw = prop_lnp(sp, false, T);
     const double lnSl = lnpv - lw;
-    const double sig = surface_tension(T);
+    const double sig = prop_sigma(sp, T);
     const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
     const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
     const double mu = sutherland<double>(T);
@@ -229,7 +278,7 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
     r.gone_s = N0 > kNmin && !ice;
     if (liq) {
         double r20 = sqrt(M2 / M0);
-        double Ts = t_sat(kSonW, lnpv, T);
+        double Ts = prop_tsat(sp, false, lnpv, T);
         double dT = Ts - T;
         double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
                                           : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
@@ -237,7 +286,7 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
     }
     if (ice) {
         double r20 = sqrt(N2 / N0);
-        double Ts = t_sat(kSonI, lnpv, T);
+        double Ts = prop_tsat(sp, true, lnpv, T);
         r.Gs = young_G(lam, Ts - T, r20, kRhoS, hsg, young_nu(Ts, hsg), lbar);
     }
 
@@ -247,7 +296,7 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
         double l2 = log(M2 / M0), l3 = log(M3 / M0);
         double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
         double lrg = 0.5 * l2 - s2;
-        double daw = 1.0 - exp(ln_psat(kSonI, T) - lw);
+        double daw = 1.0 - exp(prop_lnp(sp, true, T) - lw);
         daw = fmin(fmax(daw, 0.26), 0.34);
         double lg = -906.7 + 8502.0 * daw - 26924.0 * daw * daw + 29180.0 * daw * daw * daw;
         double Jf = 1.0e6 * exp(lg * 2.302585092994046) + sp.het_freeze * Ns;   // Eq. 12 + 14
@@ -333,9 +382,10 @@ struct EqCell {
 
 // Gas temperature of the branch end state at trial temperature Ts (ice: condensate
 // is ice); also the vapour density and condensate mass of that state.
-__device__ __forceinline__ double eq_gas_T(const EqCell &e, bool ice, double Ts, double &rho_v, double &cond)
+__device__ __forceinline__ double eq_gas_T(const SourceParams &sp, const EqCell &e, bool ice, double Ts, double &rho_v,
+                                           double &cond)
 {
-    const double rho_sat = exp(ln_psat(ice ? kSonI : kSonW, Ts)) / (kRv * Ts);
+    const double rho_sat = exp(prop_lnp(sp, ice, Ts)) / (kRv * Ts);
     cond = fmax(e.W - rho_sat, 0.0);
     rho_v = e.W - cond;
     const double hv = kLv0 + kCpv * (Ts - kTref);
@@ -348,12 +398,12 @@ __device__ __forceinline__ double eq_gas_T(const EqCell &e, bool ice, double Ts,
 
 // The branch's end temperature: T_gas falls as Ts rises (warmer saturation keeps
 // more vapour and releases less heat), so bisection on [100, 1000] K.
-__device__ __forceinline__ double eq_root(const EqCell &e, bool ice)
+__device__ __forceinline__ double eq_root(const SourceParams &sp, const EqCell &e, bool ice)
 {
     double a = 100.0, b = 1000.0, rv, c;
     for (int it = 0; it < 64; ++it) {
         const double m = 0.5 * (a + b);
-        if (eq_gas_T(e, ice, m, rv, c) > m) a = m;
+        if (eq_gas_T(sp, e, ice, m, rv, c) > m) a = m;
         else b = m;
     }
     return 0.5 * (a + b);
@@ -373,7 +423,7 @@ __device__ __forceinline__ void eq_moments(double M, double N, double rho_p, dou
 }
 
 // Q = (Phi_eq(U) - U) / dt; returns 1 when the cell changed phase state, else 0.
-__device__ inline int source_equilibrium(const double *U, double dt, double *Q)
+__device__ inline int source_equilibrium(const double *U, double dt, const SourceParams &sp, double *Q)
 {
     CellThermo th;
     cell_thermo(U, th);
@@ -390,20 +440,20 @@ __device__ inline int source_equilibrium(const double *U, double dt, double *Q)
     e.rhoE = U[3];
 
     double T, rho_v, L = 0.0, I = 0.0, c;
-    const double TL = eq_root(e, false);
-    eq_gas_T(e, false, TL, rho_v, c);
+    const double TL = eq_root(sp, e, false);
+    eq_gas_T(sp, e, false, TL, rho_v, c);
     if (TL >= kTmelt) {
         T = TL;
         L = c;
     } else {
-        const double TI = eq_root(e, true);
-        eq_gas_T(e, true, TI, rho_v, c);
+        const double TI = eq_root(sp, e, true);
+        eq_gas_T(sp, e, true, TI, rho_v, c);
         if (TI < kTmelt) {
             T = TI;
             I = c;
         } else {   // both phases at the melting point; the ice share closes the energy balance
             T = kTmelt;
-            const double C = fmax(e.W - exp(ln_psat(kSonW, kTmelt)) / (kRv * kTmelt), 0.0);
+            const double C = fmax(e.W - exp(prop_lnp(sp, false, kTmelt)) / (kRv * kTmelt), 0.0);
             rho_v = e.W - C;
             const double hv = kLv0 + kCpv * (kTmelt - kTref);
             const double hl = hv - (kLv0 + (kCpv - kCl) * (kTmelt - kTref));
@@ -457,7 +507,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     #pragma unroll
     for (int v = 0; v < NVAR; ++v) Q[v] = 0.0;
     if (!sp.enabled) return 0;
-    if (sp.equilibrium) return source_equilibrium(U0, dt, Q);
+    if (sp.equilibrium) return source_equilibrium(U0, dt, sp, Q);
     CellThermo th;
     cell_thermo(U0, th);
     if (source_inactive(U0, th.T)) return 0;

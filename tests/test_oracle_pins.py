@@ -745,3 +745,62 @@ def test_equilibrium_condenses_more_than_kinetics(orc):
             assert res[eq] > 0
     print("condensed water per radian: kinetic %.4e, equilibrium %.4e" % (res[False], res[True]))
     assert res[True] >= res[False]
+
+
+# ------------------------------------------ tabulated water properties (Sec. 3.2)
+def test_property_table_taylor_order(orc):
+    """The paper reads its pre-tabulated water properties by a second-order Taylor
+    expansion (Sec. 3.2): against the closed forms the error of ln p_sat (liquid,
+    ice) and of the surface tension falls as h^3 (observed order 3 when the node
+    spacing halves) and sits at rounding on the nodes; the saturation temperature
+    from the expanded ln p_sat inverts it."""
+    L = orc.lib()
+    m, c = inputs.sa0()
+    o = orc.Oracle(m, c)
+    T = np.linspace(160.3, 639.7, 4001)   # below the critical point (647 K), where sigma exists
+    fns = [L.or_ln_psat_liq, L.or_ln_psat_ice, L.or_sigma_lg]
+    closed = [np.array([f(t) for t in T]) for f in fns]
+    errs = []
+    for h in (1.0, 0.5, 0.25):
+        o.set_property_table(h)
+        errs.append([np.abs(np.array([o.property(q, t) for t in T]) - closed[q]).max() for q in range(3)])
+        for q in range(3):   # on a node the expansion returns the closed form itself
+            t = 150.0 + 400 * h
+            assert o.property(q, t) == pytest.approx(fns[q](t), rel=1e-15)
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    print("max table errors (ln p_w, ln p_i, sigma) for h = 1, 0.5, 0.25:", errs, "orders", orders)
+    assert np.all(orders > 2.7) and np.all(orders < 3.3)
+    # (h/2)^3 / 6 |f'''| at h = 0.25 K: 1.8e-8 for ln p_sat at 160 K, 1.3e-10 for sigma
+    assert errs[-1, 0] < 2e-8 and errs[-1, 1] < 2e-8 and errs[-1, 2] < 2e-10
+    # T_sat of the expanded ln p_sat_w reproduces p_v
+    lnpv = L.or_ln_psat_liq(251.3)
+    Ts = L.or_property_tsat(o.h, 0, lnpv, 240.0)
+    assert o.property(0, Ts) == pytest.approx(lnpv, abs=1e-12)
+    o.set_property_table(0.0)
+    assert o.property(0, 251.3) == L.or_ln_psat_liq(251.3)
+
+
+def test_property_table_source_matches_closed_forms(orc):
+    """The sub-cycled source read from the tables stays close to the closed-form
+    source (its end states move by the interpolation error, amplified where
+    nucleation is exponentially sensitive to ln S and sigma, and by the occasional
+    capped activation or sub-step count that the shifted rates change: not a smooth
+    function of h); cells that the closed form leaves idle stay idle."""
+    m, c = inputs.sa0()
+    o = orc.Oracle(m, c)
+    d = inputs.random_cells(400, seed=21)
+    worst = {0.5: 0.0, 0.25: 0.0}
+    for k in range(400):
+        U = _cell(orc, T=d["T"][k], p=d["p"][k], Y=d["Y"][k], u=d["u"][k], v=d["v"][k],
+                  liq=tuple(d["liq"][:, k]), ice=tuple(d["ice"][:, k]), ns=d["n_soot"][k], na=d["n_act"][k])
+        o.set_property_table(0.0)
+        Q0, n0 = o.source_cell(U, 1e-7)
+        for h in worst:
+            o.set_property_table(h)
+            Q1, n1 = o.source_cell(U, 1e-7)
+            assert (n0 == 0) == (n1 == 0)
+            err = np.abs(1e-7 * (Q1 - Q0)) / (np.abs(U) + np.abs(1e-7 * Q0) + 1e-300)
+            worst[h] = max(worst[h], err.max())
+    print("table vs closed-form source, worst relative end-state difference:", worst)
+    assert worst[0.25] < 1e-4 and worst[0.5] < 1e-4
