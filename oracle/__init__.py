@@ -94,6 +94,7 @@ def lib():
         L.or_diag.argtypes = [_V, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
         L.or_set_equilibrium.argtypes = [_V, ctypes.c_int]
+        L.or_set_drift.argtypes = [_V, ctypes.c_int]
         L.or_property.restype = _D
         L.or_property.argtypes = [_V, ctypes.c_int, _D]
         L.or_property_tsat.restype = _D
@@ -188,6 +189,11 @@ class Oracle:
         """Switch the phase change between the kinetic model and the equilibrium
         comparison model (instantaneous phase equilibrium per cell)."""
         self.L.or_set_equilibrium(self.h, 1 if on else 0)
+
+    def set_drift(self, on=True):
+        """Droplets and crystals drift against the gas with their Stokes-Cunningham
+        terminal slip in the pressure gradient (drift-flux reading of Eq. 24)."""
+        self.L.or_set_drift(self.h, 1 if on else 0)
 
     def set_property_table(self, h):
         """Water properties from a table of spacing h [K] read by a second-order Taylor

@@ -804,3 +804,83 @@ def test_property_table_source_matches_closed_forms(orc):
             worst[h] = max(worst[h], err.max())
     print("table vs closed-form source, worst relative end-state difference:", worst)
     assert worst[0.25] < 1e-4 and worst[0.5] < 1e-4
+
+
+# ------------------------------------------------- drift of the particles (Eq. 24)
+def _drift_row(orc, dpdx, liq, ice=(0, 0, 0, 0), nx=4):
+    """A planar row of nx cells at rest, 250 K, p rising linearly along x; particles
+    only in cell 1.  Returns the residual difference (drift on - off), cell width,
+    and the face-mean gas state of the face between cells 1 and 2."""
+    Lx = 0.04
+    m = inputs.mesh(nx, 1, Lx=Lx, Lr=0.01, geom=inputs.GEOM_PLANAR,
+                    bc=(inputs.BC_WALL, inputs.BC_WALL, inputs.BC_WALL, inputs.BC_WALL))
+    c = inputs.case(kappa_m=0.0, phase_change=0)
+    o = orc.Oracle(m, c)
+    dx = Lx / nx
+    U = o.empty()
+    p = 2.4e4 + dpdx * dx * (np.arange(nx) + 0.5)
+    for i in range(nx):
+        has = i == 1
+        U[:, 0, i] = _cell(orc, T=250.0, p=p[i], Y=0.0, liq=liq if has else (0, 0, 0, 0),
+                           ice=ice if has else (0, 0, 0, 0))
+    R0 = o.residual(U)
+    o.set_drift(True)
+    R1 = o.residual(U)
+    rho = 0.5 * (U[0, 0, 1] + U[0, 0, 2])
+    return R1 - R0, dx, rho, 0.5 * (p[1] + p[2])
+
+
+def _stokes_cunningham(orc, r, rho_p, rho, pf, dpdx, T=250.0, Rg=287.0):
+    L = orc.lib()
+    mu = L.or_mu_sutherland(T)
+    lbar = 1.5 * mu * math.sqrt(Rg * T) / pf
+    Kn = lbar / (2.0 * r)
+    Cc = 1.0 + 2.0 * L.or_cunningham_ac(Kn) * Kn
+    return 2.0 * rho_p * r * r * Cc / (9.0 * mu) * (1.0 - rho / rho_p) * dpdx / rho, mu
+
+
+def test_drift_monodisperse_stokes_cunningham(orc):
+    """Drift-flux reading of the drag law (Eq. 24): monodisperse droplets (and
+    crystals) leave their cell through the downstream face of the pressure gradient
+    with the Stokes terminal slip corrected by Cunningham's factor, moment by moment
+    (flux of M_k = N r^k w); reversing the gradient sends them the other way; the
+    gas and the soot do not drift; a closed box keeps every moment's total."""
+    N, r, dpdx = 1e10, 2e-6, 5e3
+    liq = (N, N * r, N * r * r, N * r ** 3)
+    rs = 1.5e-6
+    ice = (N, N * rs, N * rs * rs, N * rs ** 3)
+    D, dx, rho, pf = _drift_row(orc, dpdx, liq, ice)
+    for base, rr, rho_p in ((5, r, 1000.0), (9, rs, 917.0)):
+        w, mu = _stokes_cunningham(orc, rr, rho_p, rho, pf, dpdx)
+        assert w > 0.0 and 2.0 * rr * rho * w / mu < 0.1           # particle Reynolds number: Stokes regime
+        for k in range(4):
+            F = N * rr ** k * w
+            assert D[base + k, 0, 1] == pytest.approx(-F / dx, rel=1e-10)
+            assert D[base + k, 0, 2] == pytest.approx(F / dx, rel=1e-10)
+            assert D[base + k, 0, 0] == 0.0 and D[base + k, 0, 3] == 0.0
+            assert abs(D[base + k].sum()) <= 1e-12 * abs(F / dx)   # closed box: the total is kept
+    assert np.all(D[:5] == 0.0) and np.all(D[13:] == 0.0)
+    Dm, dx, rho, pf = _drift_row(orc, -dpdx, liq)
+    assert Dm[5, 0, 0] > 0.0 and Dm[5, 0, 2] == 0.0 and Dm[5, 0, 1] < 0.0
+
+
+def test_drift_lognormal_against_quadrature(orc):
+    """For a lognormal population the lognormal closure of M4, M5 is exact, so the
+    drift flux of each moment equals brute-force quadrature of r^k w(r) over the
+    distribution (A_C taken at the mean radius r20, as in the flux)."""
+    N, rg, sg, dpdx = 1e10, 8e-7, 1.5, 5e3
+    liq = tuple(_lognormal(N, rg, sg))
+    D, dx, rho, pf = _drift_row(orc, dpdx, liq)
+    L = orc.lib()
+    mu = L.or_mu_sutherland(250.0)
+    lbar = 1.5 * mu * math.sqrt(287.0 * 250.0) / pf
+    r20 = math.sqrt(liq[2] / liq[0])
+    A = L.or_cunningham_ac(lbar / (2.0 * r20))
+    s = math.log(sg)
+    x = np.linspace(-9.0, 9.0, 200001)            # ln r in standard deviations about ln rg
+    rr = rg * np.exp(s * x)
+    pdf = np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+    c = 2.0 * 1000.0 * (1.0 - rho / 1000.0) * dpdx / (9.0 * mu * rho)
+    for k in range(4):
+        F = c * N * np.trapezoid(rr ** (k + 2) * (1.0 + A * lbar / rr) * pdf, x)
+        assert D[5 + k, 0, 1] == pytest.approx(-F / dx, rel=1e-8), k
