@@ -102,10 +102,12 @@ def condensed_water(s, U):
 
 
 def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None, qmode=None,
-             table_h=0.0):
+             table_h=0.0, drift=False):
     import torch
     s = binding.Solver(m, c, precision)
     U = s.init()
+    if drift:
+        s.set_drift(True)
     if tile:
         s.set_tile(*tile)
     if qmode is not None:
@@ -184,8 +186,8 @@ def train_surrogate(binding, inputs, log):
 
 def run_source_active(binding, inputs, steps, warmup, trained):
     """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate,
-    mixed with tabulated water properties, and the mixed path with the equilibrium
-    comparison model."""
+    mixed with tabulated water properties, mixed with particle drift, and the mixed
+    path with the equilibrium comparison model."""
     import torch
     net, norm, rep = trained
     m, c = inputs.sa2(0)
@@ -196,11 +198,14 @@ def run_source_active(binding, inputs, steps, warmup, trained):
                                       keep=True)
     # water properties from 0.25 K tables read by second-order Taylor expansion
     res["mixed_tables"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, table_h=0.25)
+    # droplets and crystals drifting against the gas (a model extension: its change
+    # against the FP64 path without drift is the drift's own effect)
+    res["mixed_drift"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, drift=True)
     # the paper's comparison model (a different model: no error against the kinetics)
     res["mixed_equilibrium"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
                                         qmode=binding.CP_Q_EQUILIBRIUM)
     Uref = res["fp64"].pop("U")
-    for k in ("mixed", "mixed_surrogate", "mixed_tables"):
+    for k in ("mixed", "mixed_surrogate", "mixed_tables", "mixed_drift"):
         res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)
     del Uref
     torch.cuda.empty_cache()

@@ -171,6 +171,18 @@ int cp_set_qmode(cp_ctx *ctx, int qmode);
  * to the exact fallback, summed over every stage since cp_sur_set.              */
 int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
 
+/* Drift of droplets and crystals against the gas (on != 0), the drag law (Eq. 24)
+ * read as a drift flux in this one-velocity solver: particles lag the gas's
+ * pressure-driven acceleration with their Stokes terminal slip
+ *   w(r) = 2 rho_p r^2 Cc(r) (1 - rho/rho_p) (dp/dn) / (9 mu rho),
+ *   Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r), lbar = 1.5 mu sqrt(R T) / p,
+ * and each population drifts as a whole with the slip of its mean radius r20:
+ * moment k crosses a face with w(r20) M_k, upwind in its sign (the moment set
+ * stays realisable).  Soot stays with the gas.  Applied
+ * in every stage (and cp_residual) by a pass after the stage kernel, in FP64.
+ * Off by default.  Errors: CP_EUNSUPPORTED in the quasi-1D duct.                   */
+int cp_set_drift(cp_ctx *ctx, int on);
+
 /* Water properties of the phase-change source (ln p_sat over liquid and ice, the
  * surface tension) from a table instead of the closed forms, as the paper reads its
  * pre-tabulated properties (Sec. 3.2): nodes every h kelvin on [150, 700] K, each

@@ -1120,14 +1120,13 @@ static void roe_flux(const double *L, const double *R, double *F)
 
 /* ================================================ drift of the particles (Eq. 24) == */
 /* The drag law (Eq. 24) read as a drift flux: droplets and crystals lag the gas's
- * pressure-driven acceleration, so relative to the gas they move with their
- * terminal slip w(r) = (2 rho_p r^2 Cc(r) / (9 mu)) (1 - rho/rho_p) (dp/dn) / rho,
- * Stokes drag with the Cunningham factor Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r)
- * (the Schiller-Naumann factor is 1 at these particle Reynolds numbers).  Moment k
- * of a population then crosses a face with sum over particles of r^k w(r) =
- * c (M_{k+2} + A_C lbar M_{k+1}), c = 2 rho_p (1 - rho/rho_p)(dp/dn) / (9 mu rho),
- * A_C at the mean radius r20, M4 and M5 from the lognormal closure of (M0, M2, M3);
- * upwind in the sign of c.  Face values: means of the two cells; lbar = 1.5 mu
+ * pressure-driven acceleration, so relative to the gas a particle of radius r moves
+ * with its terminal slip w(r) = (2 rho_p r^2 Cc(r) / (9 mu)) (1 - rho/rho_p) (dp/dn)
+ * / rho, Stokes drag with the Cunningham factor Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r)
+ * (the Schiller-Naumann factor is 1 at these particle Reynolds numbers).  Each
+ * population drifts as a whole with the slip of its mean radius r20, so all its
+ * moments cross a face with the same velocity (upwind in its sign), which keeps the
+ * moment set realisable.  Face values: means of the two cells; lbar = 1.5 mu
  * sqrt(R T) / p.  Soot stays with the gas (its response time is negligible).     */
 static void drift_add(const prim_t *a, const prim_t *b, double mu_a, double mu_b, double dn, double *F)
 {
@@ -1140,17 +1139,13 @@ static void drift_add(const prim_t *a, const prim_t *b, double mu_a, double mu_b
         double rho_p = pop ? RHO_ICE : RHO_LIQ;
         double c = 2.0 * rho_p * (1.0 - rho / rho_p) * dpdn / (9.0 * mu * rho);
         const prim_t *w = c > 0.0 ? a : b;
-        double M[6];
+        double M[4];
         for (int k = 0; k < 4; ++k) M[k] = w->rho * w->phi[base + k];
         if (!population_valid(M)) continue;
-        double l2 = log(M[2] / M[0]), l3 = log(M[3] / M[0]);
-        double s2 = 2.0 / 3.0 * l3 - l2;
-        if (s2 < 0.0) s2 = 0.0;
-        double lnrg = 0.5 * l2 - s2;
-        M[4] = M[0] * exp(4.0 * lnrg + 8.0 * s2);
-        M[5] = M[0] * exp(5.0 * lnrg + 12.5 * s2);
-        double A = or_cunningham_ac(lbar / (2.0 * sqrt(M[2] / M[0])));
-        for (int k = 0; k < 4; ++k) F[base + k] += c * (M[k + 2] + A * lbar * M[k + 1]);
+        double r20 = sqrt(M[2] / M[0]);
+        double Kn = lbar / (2.0 * r20);
+        double W = c * r20 * r20 * (1.0 + 2.0 * or_cunningham_ac(Kn) * Kn);
+        for (int k = 0; k < 4; ++k) F[base + k] += W * M[k];
     }
 }
 

@@ -67,6 +67,7 @@ _SIGS = {
     "cp_diag": (_I, [_P, _P, _DP]),
     "cp_set_tile": (_I, [_P, _I, _I]),
     "cp_set_property_table": (_I, [_P, _D]),
+    "cp_set_drift": (_I, [_P, _I]),
     "cp_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "cp_mesh_faces": (_I, [_P, _DP, _DP]),
     "cp_time_stage": (_I, [_P, _P, _I, _DP]),
@@ -247,6 +248,9 @@ class Solver:
 
     def set_tile(self, tx, ty):
         self._chk(self.L.cp_set_tile(self.h, int(tx), int(ty)))
+
+    def set_drift(self, on=True):
+        self._chk(self.L.cp_set_drift(self.h, 1 if on else 0))
 
     def set_property_table(self, h):
         self._chk(self.L.cp_set_property_table(self.h, float(h)))

@@ -31,6 +31,8 @@ struct cp_ctx {
     std::vector<double> xf, rf, xc, rc, dx, dr;     // host mesh
     std::vector<double> ax;                         // quasi-1D duct areas at the x faces
     double *ptab = nullptr;                         // water property table (device), or null
+    bool drift = false;                             // particles drift against the gas
+    double *rfa_d = nullptr, *invVr_d = nullptr;    // double r-face areas and 1/(r_c dr) for the drift
     std::vector<void *> allocs;                     // device memory owned by the context
     double *inflow = nullptr, *ambient = nullptr, *vol = nullptr;
     double *xc_d = nullptr, *rc_d = nullptr, *inv_dx_d = nullptr, *inv_dr_d = nullptr;
@@ -269,6 +271,10 @@ template <class R> int upload_metrics(cp_ctx *c)
     c->inv_dr_d = (double *)p;
     if ((r = upload_as<double>(c, vol, &p))) return r;
     c->vol = (double *)p;
+    if ((r = upload_as<double>(c, rfa, &p))) return r;
+    c->rfa_d = (double *)p;
+    if ((r = upload_as<double>(c, invV_r, &p))) return r;
+    c->invVr_d = (double *)p;
     return CP_OK;
 }
 
@@ -438,6 +444,28 @@ int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage,
     else
         e = launch_stage<float>(stage_args<float>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
+    if (c->drift) {
+        auto drift = [&](auto *tag) {
+            using R = std::remove_pointer_t<decltype(tag)>;
+            DriftArgs<R> d;
+            d.Uin = (const R *)Uin;
+            d.Uout = (R *)Uout;
+            d.dt_dev = dt_dev;
+            d.dt = dt;
+            d.plane = c->plane;
+            d.stage = stage;
+            d.bc = bcinfo(c);
+            d.xc = c->xc_d;
+            d.rc = c->rc_d;
+            d.inv_dx = c->inv_dx_d;
+            d.rfa = c->rfa_d;
+            d.invV_r = c->invVr_d;
+            d.flag = c->flag_d;
+            return launch_drift<R>(d, s);
+        };
+        e = c->precision == CP_FP64 ? drift((double *)nullptr) : drift((float *)nullptr);
+        if (e != hipSuccess) return fail(c, CP_EHIP, std::string("drift launch: ") + hipGetErrorString(e));
+    }
     const bool src = stage >= 0 && c->cs.phase_change != 0 && c->qmode != CP_Q_OFF;
     if (!src) return CP_OK;
     if (c->qmode == CP_Q_SURROGATE) return surrogate_any(c, Uin, Uout, stage, dt, dt_dev, s);
@@ -871,6 +899,15 @@ int cp_set_tile(cp_ctx *c, int tx, int ty)
         c->tx = tx;
         c->ty = ty;
     }
+    drop_graphs(c);
+    return CP_OK;
+}
+
+int cp_set_drift(cp_ctx *c, int on)
+{
+    if (!c) return CP_EINVAL;
+    if (on && c->mesh.geom == CP_GEOM_QUASI1D) return fail(c, CP_EUNSUPPORTED, "no drift in the quasi-1D duct");
+    c->drift = on != 0;
     drop_graphs(c);
     return CP_OK;
 }

@@ -56,6 +56,24 @@ template <class R> struct StageArgs {
     unsigned long long *sur_tot;
 };
 
+// Drift of droplets and crystals (drift-flux reading of the drag law, Eq. 24): a
+// separate pass after a stage adds b dt R_drift(U^(s-1)) to the stage output (or
+// R_drift to a residual), computed in FP64.
+template <class R> struct DriftArgs {
+    const R *Uin;              // state the drift is evaluated on
+    R *Uout;                   // stage output or residual, updated in place
+    const double *dt_dev;
+    double dt;
+    long plane;
+    int stage;                 // 0, 1, 2: weight 1, 1/4, 2/3 of dt; -1: residual (weight 1, no dt)
+    BcInfo bc;
+    const double *xc, *rc;     // centres, ghost-offset by 2
+    const double *inv_dx;      // nx
+    const double *rfa;         // nr+1: r-face area per unit axial length
+    const double *invV_r;      // nr
+    int *flag;
+};
+
 template <class R> struct SourceFixArgs {
     const R *Uin;              // stage input U^(s-1): the source is evaluated here
     R *Uout;                   // stage output, updated in place
@@ -108,6 +126,7 @@ void mlp_dims(const cp_mlp *n, int *n_in, int *n_out);
 template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s);
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s);
+template <class R> hipError_t launch_drift(const DriftArgs<R> &a, hipStream_t s);
 hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
 // dt = cfl * min(block_min[0..n)), t += dt (t nullable)
 hipError_t launch_cfl_finalize_blocks(const double *block_min, int n, double cfl, double *dt, double *t, hipStream_t s);

@@ -646,6 +646,97 @@ template <class R> __global__ void __launch_bounds__(64) k_source_fix(SourceFixA
     source_fix_body(a, blockIdx.x, gridDim.x);
 }
 
+// ------------------------------------------------------------------ drift
+// Droplets and crystals lag the gas's pressure-driven acceleration with their
+// Stokes terminal slip w(r) = 2 rho_p r^2 Cc(r) (1 - rho/rho_p) (dp/dn) / (9 mu rho),
+// Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r) (Eq. 24 in the Stokes regime).  A population
+// drifts as a whole with the slip of its mean radius r20: every moment crosses a
+// face with w(r20) M_k, upwind in its sign (the moment set stays realisable); face
+// means of rho, mu, p, T and R; lbar = 1.5 mu sqrt(R T) / p.
+struct DriftCell {
+    double rho, p, T, Rm, mu, M[8];   // M: liquid then ice moments per unit volume
+};
+
+template <class R> __device__ __forceinline__ DriftCell drift_cell(const R *U, long plane, const BcInfo &bc, int i, int j)
+{
+    const CellSrc cs = map_cell(i, j, bc);
+    double u[NVAR];
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) u[v] = (double)fetch(U, plane, bc, cs.code, v);
+    CellThermo th;
+    cell_thermo(u, th);   // the momentum flips of mirror cells do not change these
+    DriftCell d;
+    d.rho = th.rho;
+    d.p = th.p;
+    d.T = th.T;
+    d.Rm = th.Rm;
+    d.mu = sutherland<double>(th.T);
+    #pragma unroll
+    for (int k = 0; k < 8; ++k) d.M[k] = u[5 + k];
+    return d;
+}
+
+// Drift fluxes of the 8 moments through the face from cell a to cell b.
+__device__ __forceinline__ void drift_face(const DriftCell &a, const DriftCell &b, double dn, double *F)
+{
+    const double rho = 0.5 * (a.rho + b.rho), mu = 0.5 * (a.mu + b.mu);
+    const double p = 0.5 * (a.p + b.p), T = 0.5 * (a.T + b.T), Rm = 0.5 * (a.Rm + b.Rm);
+    const double lbar = 1.5 * mu * sqrt(Rm * T) / p;
+    const double dpdn = (b.p - a.p) / dn;
+    #pragma unroll
+    for (int pop = 0; pop < 2; ++pop) {
+        const double rho_p = pop ? kRhoS : kRhoL;
+        const double c = 2.0 * rho_p * (1.0 - rho / rho_p) * dpdn / (9.0 * mu * rho);
+        const double *M = (c > 0.0 ? a.M : b.M) + 4 * pop;
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) F[4 * pop + k] = 0.0;
+        if (!pop_valid(M[0], M[2], M[3])) continue;
+        const double r20 = sqrt(M[2] / M[0]);
+        const double Kn = lbar / (2.0 * r20);
+        const double W = c * r20 * r20 * (1.0 + 2.0 * (1.257 + 0.4 * exp(-1.1 / (2.0 * Kn))) * Kn);
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) F[4 * pop + k] = W * M[k];
+    }
+}
+
+__device__ __forceinline__ bool has_particles(const DriftCell &d)
+{
+    return d.M[0] > kNmin || d.M[4] > kNmin;
+}
+
+template <class R> __global__ void __launch_bounds__(256) k_drift(DriftArgs<R> a)
+{
+    const BcInfo &bc = a.bc;
+    const int i = blockIdx.x * 64 + threadIdx.x % 64, j = blockIdx.y * 4 + threadIdx.x / 64;
+    if (i >= bc.nx || j >= bc.nr) return;
+    const DriftCell C = drift_cell(a.Uin, a.plane, bc, i, j);
+    const DriftCell W = drift_cell(a.Uin, a.plane, bc, i - 1, j), E = drift_cell(a.Uin, a.plane, bc, i + 1, j);
+    const DriftCell S = drift_cell(a.Uin, a.plane, bc, i, j - 1), N = drift_cell(a.Uin, a.plane, bc, i, j + 1);
+    if (!(has_particles(C) || has_particles(W) || has_particles(E) || has_particles(S) || has_particles(N))) return;
+    double Fw[8], Fe[8], Fs[8], Fn[8];
+    drift_face(W, C, a.xc[i + 2] - a.xc[i + 1], Fw);
+    drift_face(C, E, a.xc[i + 3] - a.xc[i + 2], Fe);
+    drift_face(S, C, a.rc[j + 2] - a.rc[j + 1], Fs);
+    drift_face(C, N, a.rc[j + 3] - a.rc[j + 2], Fn);
+    const double idx = a.inv_dx[i], as = a.rfa[j], an = a.rfa[j + 1], ivr = a.invV_r[j];
+    const bool axis = bc.geom == kGeomAxi && j == 0;   // zero-area axis face
+    double w = 1.0;
+    if (a.stage >= 0) {
+        const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+        w = (a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0)) * dt;
+    }
+    const long c = (long)j * bc.nx + i;
+    bool bad = false;
+    #pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double rd = -(Fe[k] - Fw[k]) * idx - (Fn[k] * an - (axis ? 0.0 : Fs[k] * as)) * ivr;
+        const R out = a.Uout[(5 + k) * a.plane + c] + (R)(w * rd);
+        a.Uout[(5 + k) * a.plane + c] = out;
+        bad |= !isfinite(out);
+    }
+    if (bad) atomicOr(a.flag, 1);
+}
+
 // batched: blockIdx.y selects the plume
 template <class R> __global__ void __launch_bounds__(256) k_source_fix_batch(const SourceFixArgs<R> *args)
 {
@@ -1346,6 +1437,13 @@ hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
     return hipGetLastError();
 }
 
+template <class R> hipError_t launch_drift(const DriftArgs<R> &a, hipStream_t s)
+{
+    dim3 grid((a.bc.nx + 63) / 64, (a.bc.nr + 3) / 4);
+    hipLaunchKernelGGL((k_drift<R>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
 {
     // enough one-wavefront workgroups for every CU; the list length is only known
@@ -1454,6 +1552,7 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \
+    template hipError_t launch_drift<R>(const DriftArgs<R> &, hipStream_t);                                  \
     template hipError_t launch_stage_batch<R>(const StageArgs<R> *, const int *, const int *, int, int, int,   \
                                               hipStream_t);                                                   \
     template hipError_t launch_source_fix_batch<R>(const SourceFixArgs<R> *, int, long, hipStream_t);        \
