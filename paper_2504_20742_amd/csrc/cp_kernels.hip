@@ -122,23 +122,35 @@ template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
     return (a * b > R(0)) ? q : R(0);
 }
 
-// LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), per-cell
-// viscosities and limited slopes of one direction on the tile plus a 1-cell ring
-// (RX x RY), and one face buffer reused for the x-faces and the r-faces.
+// LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), vapour
+// diffusivity, eddy viscosity and limited slopes of one direction on the tile plus a
+// 1-cell ring (RX x RY), and one face buffer reused for the x-faces, the r-faces and
+// the scalars' r slopes.  Whatever is cheap to recompute (molecular viscosity, the
+// faces' eddy diffusivity, a halo cell's source address) is not stored: the FP32 tile
+// then fits six workgroups per CU.
 template <class R, int TX, int TY> struct Tile {
     static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
     static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     static constexpr int NFX = (TX + 1) * TY, NFR = TX * (TY + 1);
     static constexpr int NF = NFX > NFR ? NFX : NFR;
+    static constexpr int NFB = 6 * NF > 5 * NR ? 6 * NF : 5 * NR;
     R rho[N], u[N], v[N], p[N], T[N], Y[N];   // u..Y are reused for 5 scalars at a time
-    R mu[NR], D[NR], mut[NR];
+    R D[NR], mut[NR];
     R sl[5][NR];                 // slopes of one direction (x, then r); the scalars' x slopes
-    R face[7][NF];               // F (5 components), Roe mass flux, eddy diffusivity / dn;
-                                 // the scalars' r slopes during the scalar phase
-    int code[N];
+    R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF];
+                                 // the scalars' r slopes during the scalar phase, [5][NR]
     int nonzero[2];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
-    static_assert(7 * NF >= 5 * NR, "face buffer must hold five ring arrays");
+    __device__ R (*face())[NF] { return reinterpret_cast<R(*)[NF]>(fbuf); }
+    __device__ R (*rslope())[NR] { return reinterpret_cast<R(*)[NR]>(fbuf); }
 };
+
+// Eddy diffusivity / dn of the passive scalars at a face, from the cells' eddy
+// viscosities (recomputed where the scalar fluxes need it rather than kept in LDS).
+template <class R> __device__ __forceinline__ R face_kd(R mut_a, R mut_b, R inv_dn)
+{
+    const R mut = R(0.5) * (mut_a + mut_b);
+    return mut * R(1.0 / kSct) * inv_dn;
+}
 
 // ext index of ring cell r, and ring index of ext cell e (inside the ring)
 template <int TX, int TY> __device__ __forceinline__ int ext_of_ring(int r)
@@ -153,11 +165,10 @@ template <int TX, int TY> __device__ __forceinline__ int ring_of_ext(int e)
 // Gas flux through the face between ext cells a and b = a + s (normal stride s,
 // tangential stride ts; ra, rb their ring indices): MUSCL states from the cell
 // slopes, Roe convective flux, central viscous + eddy flux.  Writes F^c - F^v on
-// (rho, rho u, rho v, rho E, rho Y) in global components, the Roe mass flux and the
-// eddy diffusivity / dn for the passive scalars.
+// (rho, rho u, rho v, rho E, rho Y) in global components and the Roe mass flux.
 template <class R, class TileT>
 __device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, int s, int ts, bool xdir, R inv_dn,
-                                         R inv_d2t, R inv_r, R pref, R *F, R &Fm, R &kd)
+                                         R inv_d2t, R inv_r, R pref, R *F, R &Fm)
 {
     const int b = a + s;
     const R(*sl)[TileT::NR] = t.sl;   // slopes of the face-normal direction
@@ -179,7 +190,7 @@ __device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, 
     Fm = Fc[0];
     const R FY = Fm * (Fm >= R(0) ? qL[4] : qR[4]);
 
-    const R mu = R(0.5) * (t.mu[ra] + t.mu[rb]);
+    const R mu = R(0.5) * (sutherland_t(t.T[a]) + sutherland_t(t.T[b]));
     const R mut = R(0.5) * (t.mut[ra] + t.mut[rb]);
     const R rho = R(0.5) * (t.rho[a] + t.rho[b]);
     const R cpf = R(0.5) * (gas_cp(t.Y[a]) + gas_cp(t.Y[b]));
@@ -210,7 +221,6 @@ __device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, 
         F[3] = Fc[3] - (uf * tnt + vf * tnn - qn);
     }
     F[4] = FY + Jv;
-    kd = mut * R(1.0 / kSct) * inv_dn;
 }
 
 // Flux divergence per unit volume from face fluxes, evaluated without contraction
@@ -298,6 +308,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // A tile whose 2-cell halo lies inside the mesh (most tiles) addresses its cells
     // directly; only boundary tiles go through the ghost-cell mapping.
     const bool inner = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= nx && j0 + TY + 2 <= nr;
+    R(*face)[TileT::NF] = t.face();
 
     if (tid == 0) t.nonzero[0] = t.nonzero[1] = 0;
     // phase 1: gas primitives of tile + halo
@@ -328,7 +339,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
         const R eint = U3 * ir - R(0.5) * (u * u + v * v);
         const R T = tdiv(eint + (R(1) - Y) * R(kCpa * kTref) - Y * R(kLv0 - kCpv * kTref), gas_cv(Y));
-        t.code[e] = code;
         t.rho[e] = U0;
         t.u[e] = u;
         t.v[e] = v;
@@ -343,7 +353,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int l = ext_of_ring<TX, TY>(r);
         const int i = min(i0 + r % RX - 1, nx), j = min(j0 + r / RX - 1, nr);
         const R T = t.T[l];
-        t.mu[r] = sutherland_t(T);
         t.D[r] = R(kD0) * fpow_pos(T * R(1.0 / kTref), R(kDexp)) * tdiv(R(kP0), t.p[l]);
         const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
         const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
@@ -366,12 +375,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
         const int la = (fj + 2) * EX + fi + 1;
         const int ra = (fj + 1) * RX + fi;
-        R F[5], fm, kdv;
-        gas_face<R>(t, la, ra, ra + 1, 1, EX, true, m.inv_dxf[ig], m.inv_d2r[jg + 1], m.inv_rc[jg + 1], pref, F, fm, kdv);
+        R F[5], fm;
+        gas_face<R>(t, la, ra, ra + 1, 1, EX, true, m.inv_dxf[ig], m.inv_d2r[jg + 1], m.inv_rc[jg + 1], pref, F, fm);
         #pragma unroll
-        for (int k = 0; k < 5; ++k) t.face[k][f] = F[k];
-        t.face[5][f] = fm;
-        t.face[6][f] = kdv;
+        for (int k = 0; k < 5; ++k) face[k][f] = F[k];
+        face[5][f] = fm;
     }
     __syncthreads();
     R res[NVAR];
@@ -384,16 +392,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             // reference pressure having been taken out of the momentum fluxes as well
             const R aw = m.axf[i], ae = m.axf[i + 1], iv = m.invVx[i];
             #pragma unroll
-            for (int k = 0; k < 5; ++k) res[k] = assemble_duct(t.face[k][fw + 1], ae, t.face[k][fw], aw, iv);
+            for (int k = 0; k < 5; ++k) res[k] = assemble_duct(face[k][fw + 1], ae, face[k][fw], aw, iv);
             res[1] += ((t.p[l] - pref) * (ae - aw)) * iv;
         } else {
             #pragma unroll
-            for (int k = 0; k < 5; ++k) res[k] = assemble_x(t.face[k][fw + 1], t.face[k][fw], idx);
+            for (int k = 0; k < 5; ++k) res[k] = assemble_x(face[k][fw + 1], face[k][fw], idx);
         }
-        Fm0 = t.face[5][fw];
-        kd0 = t.face[6][fw];
-        Fm1 = t.face[5][fw + 1];
-        kd1 = t.face[6][fw + 1];
+        Fm0 = face[5][fw];
+        Fm1 = face[5][fw + 1];
+        kd0 = face_kd(t.mut[rl - 1], t.mut[rl], m.inv_dxf[i]);
+        kd1 = face_kd(t.mut[rl], t.mut[rl + 1], m.inv_dxf[i + 1]);
     }
     // r-direction gas slopes, over the x slopes the x-faces no longer need
     for (int r = tid; r < NRG; r += NT) {
@@ -407,34 +415,34 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     for (int f = tid; f < TileT::NFR; f += NT) {
         const int fi = f % TX, fj = f / TX;
         const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
-        R F[5] = {R(0), R(0), R(0), R(0), R(0)}, fm = R(0), kdv = R(0);
+        R F[5] = {R(0), R(0), R(0), R(0), R(0)}, fm = R(0);
         if (!(axi && jg == 0) && !q1d) {
             const int la = (fj + 1) * EX + fi + 2;
             const int ra = fj * RX + fi + 1;
-            gas_face<R>(t, la, ra, ra + RX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1], m.inv_rf[jg], pref, F, fm,
-                        kdv);
+            gas_face<R>(t, la, ra, ra + RX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1], m.inv_rf[jg], pref, F, fm);
         }
         #pragma unroll
-        for (int k = 0; k < 5; ++k) t.face[k][f] = F[k];
-        t.face[5][f] = fm;
-        t.face[6][f] = kdv;
+        for (int k = 0; k < 5; ++k) face[k][f] = F[k];
+        face[5][f] = fm;
     }
     __syncthreads();
     if (valid) {
         const int fs = ty * TX + tx, fn = fs + TX;
         const R ivr = m.invV_r[j], as = m.rfa[j], an = m.rfa[j + 1];
         #pragma unroll
-        for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], t.face[k][fn], an, t.face[k][fs], as, ivr);
-        Fm2 = t.face[5][fs];
-        kd2 = t.face[6][fs];
-        Fm3 = t.face[5][fn];
-        kd3 = t.face[6][fn];
+        for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], face[k][fn], an, face[k][fs], as, ivr);
+        Fm2 = face[5][fs];
+        Fm3 = face[5][fn];
+        if (!q1d) {   // the axis face's scalar flux is zeroed where it is used
+            kd2 = face_kd(t.mut[rl - RX], t.mut[rl], m.inv_drf[j]);
+            kd3 = face_kd(t.mut[rl], t.mut[rl + RX], m.inv_drf[j + 1]);
+        }
         if (axi) {   // (p - p_ref - tau_thetatheta) / r_c on radial momentum
             const R ir = m.inv_rc[j + 1];
             const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
             const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
             const R vr = t.v[l] * ir;
-            const R mue = t.mu[rl] + t.mut[rl];
+            const R mue = sutherland_t(t.T[l]) + t.mut[rl];
             const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
             res[2] += ((t.p[l] - pref) - ttt) * ir;
         }
@@ -452,7 +460,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         int nz = 0;
         if (inner) {
             for (int e = tid; e < NE; e += NT) {
-                const unsigned code = t.code[e];
+                const unsigned code = (unsigned)((j0 + e / EX - 2) * nx + i0 + e % EX - 2);
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
@@ -463,7 +471,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
         } else {
             for (int e = tid; e < NE; e += NT) {
-                const int code = t.code[e];
+                const int code = map_cell(min(i0 + e % EX - 2, nx + 1), min(j0 + e / EX - 2, nr + 1), bc).code;
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
@@ -476,7 +484,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         if (nz) atomicOr(&t.nonzero[g], nz);
         __syncthreads();
         const int live = t.nonzero[g];   // block-uniform
-        R(*srs)[NRG] = reinterpret_cast<R(*)[NRG]>(&t.face[0][0]);   // r slopes in the free face buffer
+        R(*srs)[NRG] = t.rslope();   // r slopes in the free face buffer
         for (int r = tid; r < NRG; r += NT) {
             const int le = ext_of_ring<TX, TY>(r);
             #pragma unroll
@@ -576,8 +584,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     if (bad) atomicOr(a.flag, 1);
 }
 
+// FP32: registers held to 80 per lane (6 wavefronts per SIMD), which is what the
+// LDS tile allows for 256-thread tiles; FP64 is held to three by both.
+#define CP_STAGE_WAVES __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1)))
+
 template <class R, int TX, int TY, bool DUCT = false>
-__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
+__global__ void __launch_bounds__(TX *TY) CP_STAGE_WAVES k_stage(StageArgs<R> a)
 {
     __shared__ Tile<R, TX, TY> t;
     // surrogate counters of the previous stage, consumed by now (saves a launch)
@@ -590,7 +602,7 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs<R> a)
 // Batched operating points: workgroup b takes work item b (XCD-banded) of a list of
 // (plume, tile) pairs and runs the stage of that plume's tile.
 template <class R, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_stage_batch(const StageArgs<R> *args, const int *work_plume,
+__global__ void __launch_bounds__(TX *TY) CP_STAGE_WAVES k_stage_batch(const StageArgs<R> *args, const int *work_plume,
                                                         const int *work_tile, int nwork)
 {
     __shared__ Tile<R, TX, TY> t;
