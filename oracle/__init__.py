@@ -18,7 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "contrail_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-NV = 15
+NV = 15          # variables per cell; 19 with two liquid populations (set_bimodal)
+NV_BIMODAL = 19
 
 _lib = None
 
@@ -93,8 +94,14 @@ def lib():
         L.or_run.argtypes = [_V, _P, ctypes.c_int]
         L.or_diag.argtypes = [_V, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
+        L.or_set_equilibrium.restype = ctypes.c_int
         L.or_set_equilibrium.argtypes = [_V, ctypes.c_int]
+        L.or_set_drift.restype = ctypes.c_int
         L.or_set_drift.argtypes = [_V, ctypes.c_int]
+        L.or_set_bimodal.restype = ctypes.c_int
+        L.or_set_bimodal.argtypes = [_V, ctypes.c_int]
+        L.or_nvar.restype = ctypes.c_int
+        L.or_nvar.argtypes = [_V]
         L.or_property.restype = _D
         L.or_property.argtypes = [_V, ctypes.c_int, _D]
         L.or_property_tsat.restype = _D
@@ -129,7 +136,8 @@ def make_case(c):
 
 
 class Oracle:
-    """One mesh + case on the host; arrays are float64 ``U[15][nr][nx]``."""
+    """One mesh + case on the host; arrays are float64 ``U[nv][nr][nx]`` with nv = 15,
+    or 19 once ``set_bimodal`` splits the liquid into two populations."""
 
     def __init__(self, mesh, case):
         self.L = lib()
@@ -150,8 +158,12 @@ class Oracle:
         except Exception:
             pass
 
+    @property
+    def nv(self):
+        return self.L.or_nvar(self.h)
+
     def empty(self):
-        return np.zeros((NV, self.nr, self.nx), dtype=np.float64)
+        return np.zeros((self.nv, self.nr, self.nx), dtype=np.float64)
 
     def init(self):
         U = self.empty()
@@ -188,12 +200,20 @@ class Oracle:
     def set_equilibrium(self, on=True):
         """Switch the phase change between the kinetic model and the equilibrium
         comparison model (instantaneous phase equilibrium per cell)."""
-        self.L.or_set_equilibrium(self.h, 1 if on else 0)
+        if self.L.or_set_equilibrium(self.h, 1 if on else 0) != 0:
+            raise ValueError("or_set_equilibrium: not with two liquid populations")
 
     def set_drift(self, on=True):
         """Droplets and crystals drift against the gas with their Stokes-Cunningham
         terminal slip in the pressure gradient (drift-flux reading of Eq. 24)."""
-        self.L.or_set_drift(self.h, 1 if on else 0)
+        if self.L.or_set_drift(self.h, 1 if on else 0) != 0:
+            raise ValueError("or_set_drift: not with two liquid populations")
+
+    def set_bimodal(self, on=True):
+        """Carry the liquid as two populations (Sec. 2.2): soot-activated droplets in
+        variables 5..8, homogeneously nucleated ones in 15..18 (arrays of 19 planes)."""
+        if self.L.or_set_bimodal(self.h, 1 if on else 0) != 0:
+            raise ValueError("or_set_bimodal: not with the equilibrium model or drift")
 
     def set_property_table(self, h):
         """Water properties from a table of spacing h [K] read by a second-order Taylor
@@ -225,13 +245,15 @@ class Oracle:
 
     def source_cell(self, Uc, dt):
         Uc = np.ascontiguousarray(Uc, dtype=np.float64)
-        Q = np.zeros(NV)
+        assert Uc.shape == (self.nv,)
+        Q = np.zeros(self.nv)
         n = self.L.or_source_cell(self.h, _ptr(Uc), float(dt), _ptr(Q))
         return Q, n
 
     def rates_cell(self, Uc, h=1e-6):
         Uc = np.ascontiguousarray(Uc, dtype=np.float64)
-        S = np.zeros(NV)
+        assert Uc.shape == (self.nv,)
+        S = np.zeros(self.nv)
         d = np.zeros(8)
         self.L.or_source_rates_cell(self.h, _ptr(Uc), float(h), _ptr(S), _ptr(d))
         names = ["Gl", "Gs", "Jhom", "Jhet", "rcrit", "lnSl", "lnSi", "mdot_f"]

@@ -30,7 +30,12 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NV 15
+/* Per-cell arrays hold NV entries: the 15 variables of the state, and four more
+ * (15..18) for the homogeneously nucleated droplets when the liquid is carried as
+ * two populations (Sec. 2.2); unused entries stay zero.  Arrays in memory hold
+ * cx->nv planes (15 or 19).                                                    */
+#define NV 19
+#define NV_BASE 15
 
 /* ---------------------------------------------------------------- constants -- */
 /* Ideal-gas two-species carrier (dry air pseudo-component + water vapour),
@@ -104,6 +109,9 @@ typedef struct {
     double delta0;
     int equilibrium;            /* 1: equilibrium phase change instead of kinetics */
     int drift;                  /* 1: droplets and crystals drift against the gas  */
+    int bimodal;                /* 1: two liquid populations (soot-activated in 5..8,
+                                 *    homogeneously nucleated in 15..18)           */
+    int nv;                     /* variables per cell in memory: 15, or 19 bimodal */
     double *ptab;               /* water property table (null: closed forms)       */
     int ptab_n;
     double ptab_T0, ptab_h;
@@ -402,31 +410,40 @@ static void prim_to_cons(double rho, double u, double v, double p, double Y,
     for (int m = 5; m < NV; ++m) U[m] = rho * (phi ? phi[m] : 0.0);
 }
 
-void or_prim_to_cons(const double *W /* rho,u,v,p,Y,phi5..phi14 */, double *U)
+void or_prim_to_cons(const double *W /* rho,u,v,p,Y,phi5..phi14 */, double *U /* 15 */)
 {
-    double phi[NV] = {0};
-    for (int m = 5; m < NV; ++m) phi[m] = W[m];
-    prim_to_cons(W[0], W[1], W[2], W[3], W[4], phi, U);
+    double phi[NV] = {0}, Ul[NV];
+    for (int m = 5; m < NV_BASE; ++m) phi[m] = W[m];
+    prim_to_cons(W[0], W[1], W[2], W[3], W[4], phi, Ul);
+    memcpy(U, Ul, sizeof(double) * NV_BASE);
 }
 
-void or_cons_to_prim(const double *U, double *W /* rho,u,v,p,Y,phi5..14,T,c */)
+void or_cons_to_prim(const double *U /* 15 */, double *W /* rho,u,v,p,Y,phi5..14,T,c */)
 {
+    double Ul[NV] = {0};
+    memcpy(Ul, U, sizeof(double) * NV_BASE);
     prim_t w;
-    cons_to_prim(U, &w);
+    cons_to_prim(Ul, &w);
     W[0] = w.rho; W[1] = w.u; W[2] = w.v; W[3] = w.p; W[4] = w.Y;
-    for (int m = 5; m < NV; ++m) W[m] = w.phi[m];
+    for (int m = 5; m < NV_BASE; ++m) W[m] = w.phi[m];
     W[15] = w.T; W[16] = w.c;
 }
 
 /* ================================================= source: rates (Eq. 1-21) == */
+/* Liquid populations: 0 holds all droplets (one population), or the soot-activated
+ * ones when the liquid is carried as two populations; 1 holds the homogeneously
+ * nucleated droplets (Sec. 2.2: two moment sets evolved side by side, each with its
+ * own nucleation source, growth closure and freezing).                           */
+static int liq_base(int pop) { return pop ? 15 : 5; }
+
 typedef struct {
-    double dM[4], dN[4];   /* liquid / ice moment rates                            */
-    double act;            /* soot activation rate                                 */
-    double F[4];           /* moments lost to freezing                             */
-    double mdot_f;         /* liquid -> ice mass rate                              */
-    double Gl, Gs;         /* growth rates at r20                                  */
+    double dM[2][4], dN[4]; /* liquid moment rates per population / ice moment rates */
+    double act;             /* soot activation rate                                 */
+    double F[2][4];         /* moments each liquid population loses to freezing     */
+    double mdot_f;          /* liquid -> ice mass rate                              */
+    double Gl[2], Gs;       /* growth rates at r20                                  */
     double Jhom, Jhet, rcrit, lnSl, lnSi;
-    int stale_l, stale_s;  /* number left without mass: evaporated population      */
+    int stale_l[2], stale_s;/* number left without mass: evaporated population      */
 } rates_t;
 
 /* A population with particles (mu0 > N_MIN) is valid while its mean radii
@@ -437,8 +454,9 @@ static int population_valid(const double *m)
     return m[0] > N_MIN && m[2] > m[0] * R_MIN * R_MIN && m[3] > m[0] * R_MIN * R_MIN * R_MIN;
 }
 
-/* One evaluation of the phase-change rates at state U; h is the sub-step length,
- * which bounds the activation rate so that at most the unactivated soot activates. */
+/* One evaluation of the phase-change rates at state U (NV entries); h is the
+ * sub-step length, which bounds the activation rate so that at most the
+ * unactivated soot activates.                                                    */
 static void phase_change_rates(const or_ctx *cx, const double *U, double h, rates_t *r)
 {
     memset(r, 0, sizeof(*r));
@@ -446,8 +464,9 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     cons_to_prim(U, &w);
     const double T = w.T;
     const double rho_v = U[4];
-    const double *M = U + 5, *N = U + 9;
+    const double *N = U + 9;
     const double Ns = U[13], Na = U[14];
+    const int npop = cx->bimodal ? 2 : 1;
 
     /* Eq. 1: driving potentials */
     double pv = rho_v * RGAS_VAP * T;
@@ -463,8 +482,10 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
     const double lambda_g = w.cp * mu / PRANDTL;
     const double lbar = 1.5 * mu * sqrt(w.R * T) / w.p;
 
-    /* Eq. 3-6, 8-11: nucleation (only for a supersaturated vapour) */
-    double Jl = 0.0;
+    /* Eq. 3-6, 8-11: nucleation (only for a supersaturated vapour).  J[pop] is the
+     * number of new droplets of population pop per m^3 and s: all of them in one
+     * population, or the soot-activated ones in 0 and the homogeneous ones in 1. */
+    double J[2] = {0.0, 0.0};
     if (lnSl > 0.0 && rho_v > 0.0) {
         double rc = or_critical_radius(sigma, T, lnSl);
         double x = or_barrier_hom(sigma, rc) / (BOLTZMANN * T);
@@ -481,26 +502,57 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
         r->Jhom = Jhom;
         r->rcrit = rc;
         r->act = act;
-        Jl = Jhom + act;
+        if (npop == 1) J[0] = Jhom + act;
+        else { J[0] = act; J[1] = Jhom; }
     }
 
-    const int liquid = population_valid(M);
     const int ice = population_valid(N);
-    r->stale_l = (M[0] > N_MIN && !liquid);
     r->stale_s = (N[0] > N_MIN && !ice);
+    double Jhom_s = 0.0, Jhet_s = 0.0;
+    if (T < T_REF) {
+        Jhom_s = or_koop_rate(koop_clamp(1.0 - exp(lnpi - lnpw)));
+        Jhet_s = cx->c.k_imm * cx->c.n_s * Ns * cx->soot_area;
+    }
 
-    /* Eq. 16, 21: droplet growth at r20 with the Kelvin factor (1 - r_crit/r) */
-    if (liquid) {
-        double r20 = sqrt(M[2] / M[0]);
-        double Tsat = prop_tsat(cx, 0, lnpv, T);
-        double dT = Tsat - T;
-        double drive;
-        if (fabs(lnSl) < 1e-12)
-            drive = dT - 2.0 * sigma * Tsat / (RHO_LIQ * hfg * r20);
-        else
-            drive = dT * (1.0 - or_critical_radius(sigma, T, lnSl) / r20);
-        double nu = or_young_nu(Tsat, hfg);
-        r->Gl = or_young_growth(lambda_g, drive, r20, RHO_LIQ, hfg, nu, lbar);
+    for (int pop = 0; pop < npop; ++pop) {
+        const double *M = U + liq_base(pop);
+        const int liquid = population_valid(M);
+        r->stale_l[pop] = (M[0] > N_MIN && !liquid);
+        /* Eq. 16, 21: droplet growth at r20 with the Kelvin factor (1 - r_crit/r) */
+        if (liquid) {
+            double r20 = sqrt(M[2] / M[0]);
+            double Tsat = prop_tsat(cx, 0, lnpv, T);
+            double dT = Tsat - T;
+            double drive;
+            if (fabs(lnSl) < 1e-12)
+                drive = dT - 2.0 * sigma * Tsat / (RHO_LIQ * hfg * r20);
+            else
+                drive = dT * (1.0 - or_critical_radius(sigma, T, lnSl) / r20);
+            double nu = or_young_nu(Tsat, hfg);
+            r->Gl[pop] = or_young_growth(lambda_g, drive, r20, RHO_LIQ, hfg, nu, lbar);
+        }
+        /* Eq. 12-15: freezing of droplets; moments above mu3 from a lognormal
+         * closure.  Immersion freezing needs a soot core: homogeneously nucleated
+         * droplets freeze by the homogeneous (Koop) rate alone.                   */
+        if (T < T_REF && liquid) {
+            double l2 = log(M[2] / M[0]), l3 = log(M[3] / M[0]);
+            double s2 = 2.0 / 3.0 * l3 - l2;
+            if (s2 < 0.0) s2 = 0.0;
+            double lnrg = 0.5 * l2 - s2;
+            double Mh[7];
+            Mh[3] = M[3];
+            for (int n = 4; n <= 6; ++n) Mh[n] = M[0] * exp(n * lnrg + 0.5 * n * n * s2);
+            double Jf = pop == 0 ? Jhom_s + Jhet_s : Jhom_s;
+            for (int k = 0; k < 4; ++k) r->F[pop][k] = Jf * (4.0 / 3.0 * PI) * Mh[k + 3];
+            r->mdot_f += RHO_LIQ * (4.0 / 3.0 * PI) * r->F[pop][3];
+        }
+        /* Eq. 21 moment sources of the population */
+        double rk = 1.0;
+        for (int k = 0; k < 4; ++k) {
+            double grow_l = k > 0 ? k * M[k - 1] * r->Gl[pop] : 0.0;
+            r->dM[pop][k] = grow_l + J[pop] * rk - r->F[pop][k];
+            rk *= r->rcrit;
+        }
     }
     /* ice crystals grow analogously with ice properties, no Kelvin factor */
     if (ice) {
@@ -510,51 +562,38 @@ static void phase_change_rates(const or_ctx *cx, const double *U, double h, rate
         double nu = or_young_nu(Tsat, hsg);
         r->Gs = or_young_growth(lambda_g, dT, r20, RHO_ICE, hsg, nu, lbar);
     }
-
-    /* Eq. 12-15: freezing of droplets; moments above mu3 from a lognormal closure */
-    if (T < T_REF && liquid) {
-        double l2 = log(M[2] / M[0]), l3 = log(M[3] / M[0]);
-        double s2 = 2.0 / 3.0 * l3 - l2;
-        if (s2 < 0.0) s2 = 0.0;
-        double lnrg = 0.5 * l2 - s2;
-        double Mh[7];
-        Mh[3] = M[3];
-        for (int n = 4; n <= 6; ++n) Mh[n] = M[0] * exp(n * lnrg + 0.5 * n * n * s2);
-        double Jhom_s = or_koop_rate(koop_clamp(1.0 - exp(lnpi - lnpw)));
-        double Jhet_s = cx->c.k_imm * cx->c.n_s * Ns * cx->soot_area;
-        double Jf = Jhom_s + Jhet_s;
-        for (int k = 0; k < 4; ++k) r->F[k] = Jf * (4.0 / 3.0 * PI) * Mh[k + 3];
-        r->mdot_f = RHO_LIQ * (4.0 / 3.0 * PI) * r->F[3];
-    }
-
-    /* Eq. 21 moment sources (+ freezing transfer, crystal radius r (rho_l/rho_s)^1/3) */
-    double rk = 1.0;
+    /* frozen droplets join the crystals with radius r (rho_l/rho_s)^(1/3) */
     for (int k = 0; k < 4; ++k) {
-        double grow_l = k > 0 ? k * M[k - 1] * r->Gl : 0.0;
         double grow_s = k > 0 ? k * N[k - 1] * r->Gs : 0.0;
-        r->dM[k] = grow_l + Jl * rk - r->F[k];
-        r->dN[k] = grow_s + pow(RHO_LIQ / RHO_ICE, k / 3.0) * r->F[k];
-        rk *= r->rcrit;
+        double Ft = r->F[0][k];
+        if (npop == 2) Ft += r->F[1][k];
+        r->dN[k] = grow_s + pow(RHO_LIQ / RHO_ICE, k / 3.0) * Ft;
     }
 }
 
 /* Eq. 22-26 source vector from moment rates: vapour sink keeps total water exact,
  * the gas carries the vapour's momentum, latent heats go to the gas.            */
-static void exchange_terms(const double *U, const double *dM, const double *dN,
+static void exchange_terms(const double *U, const double (*dM)[4], const double *dN, int npop,
                            double act, double mdot_f, double *S)
 {
     prim_t w;
     cons_to_prim(U, &w);
     const double T = w.T;
-    for (int k = 0; k < 4; ++k) { S[5 + k] = dM[k]; S[9 + k] = dN[k]; }
+    for (int k = 0; k < 4; ++k) {
+        S[5 + k] = dM[0][k];
+        S[9 + k] = dN[k];
+        S[15 + k] = npop == 2 ? dM[1][k] : 0.0;
+    }
     S[13] = 0.0;
     S[14] = act;
     const double fpi = 4.0 / 3.0 * PI;
-    S[4] = -fpi * (RHO_LIQ * S[8] + RHO_ICE * S[12]);
+    double liq3 = S[8];
+    if (npop == 2) liq3 += S[18];
+    S[4] = -fpi * (RHO_LIQ * liq3 + RHO_ICE * S[12]);
     S[0] = S[4];
     S[1] = S[4] * w.u;
     S[2] = S[4] * w.v;
-    double mdot_l = fpi * RHO_LIQ * S[8] + mdot_f;
+    double mdot_l = fpi * RHO_LIQ * liq3 + mdot_f;
     double mdot_s = fpi * RHO_ICE * S[12] - mdot_f;
     double hv = L_VAP0 + CP_VAP * (T - T_REF);
     double hl = hv - latent_vap(T), hi = hv - latent_sub(T);
@@ -562,14 +601,18 @@ static void exchange_terms(const double *U, const double *dM, const double *dN,
     S[3] = -mdot_l * (hl + ke) - mdot_s * (hi + ke) + mdot_f * (latent_sub(T) - latent_vap(T));
 }
 
-/* Instantaneous source S(U) (no sub-cycling), for pins.                          */
-void or_source_rates_cell(const or_ctx *cx, const double *U, double h, double *S, double *diag)
+/* Instantaneous source S(U) (no sub-cycling), for pins.  U and S hold cx->nv
+ * entries.                                                                       */
+void or_source_rates_cell(const or_ctx *cx, const double *Uin, double h, double *Sout, double *diag)
 {
+    double U[NV] = {0}, S[NV];
+    memcpy(U, Uin, sizeof(double) * cx->nv);
     rates_t r;
     phase_change_rates(cx, U, h, &r);
-    exchange_terms(U, r.dM, r.dN, r.act, r.mdot_f, S);
+    exchange_terms(U, (const double(*)[4])r.dM, r.dN, cx->bimodal ? 2 : 1, r.act, r.mdot_f, S);
+    memcpy(Sout, S, sizeof(double) * cx->nv);
     if (diag) {
-        diag[0] = r.Gl; diag[1] = r.Gs; diag[2] = r.Jhom; diag[3] = r.Jhet;
+        diag[0] = r.Gl[0]; diag[1] = r.Gs; diag[2] = r.Jhom; diag[3] = r.Jhet;
         diag[4] = r.rcrit; diag[5] = r.lnSl; diag[6] = r.lnSi; diag[7] = r.mdot_f;
     }
 }
@@ -579,7 +622,7 @@ void or_source_rates_cell(const or_ctx *cx, const double *U, double h, double *S
  * Decided on the closed-form saturation pressure in either property mode.        */
 static int source_idle(const double *U)
 {
-    if (U[5] > N_MIN || U[9] > N_MIN) return 0;
+    if (U[5] > N_MIN || U[9] > N_MIN || U[15] > N_MIN) return 0;
     if (!(U[4] > 0.0)) return 1;
     prim_t w;
     cons_to_prim(U, &w);
@@ -588,9 +631,13 @@ static int source_idle(const double *U)
     return !(log(pv) - or_ln_psat_liq(w.T) > 0.0);
 }
 
+/* Components whose depletion bounds the sub-step and the positivity scaling:
+ * vapour, liquid and ice moments (both liquid populations).                      */
+static int depletable(int c) { return (c >= 4 && c <= 12) || (c >= 15 && c <= 18); }
+
 /* Stiff source integration over dt (explicit sub-cycling, per-step positivity
- * scaling, complete-evaporation rule, mu1 realisability clamp). Returns
- * Q = (U(t+dt) - U(t)) / dt and the number of sub-steps taken.                   */
+ * scaling, complete-evaporation rule, mu1 realisability clamp). U0 and Q hold NV
+ * entries. Returns Q = (U(t+dt) - U(t)) / dt and the number of sub-steps taken.   */
 static int source_integrate(const or_ctx *cx, const double *U0, double dt, double *Q)
 {
     double U[NV];
@@ -599,13 +646,15 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         for (int v = 0; v < NV; ++v) Q[v] = 0.0;
         return 0;
     }
+    const int npop = cx->bimodal ? 2 : 1;
+    const double fpi = 4.0 / 3.0 * PI;
     rates_t r;
     double S[NV];
     phase_change_rates(cx, U, dt, &r);
-    exchange_terms(U, r.dM, r.dN, r.act, r.mdot_f, S);
+    exchange_terms(U, (const double(*)[4])r.dM, r.dN, npop, r.act, r.mdot_f, S);
     double tau = HUGE_VAL;
-    for (int c = 4; c <= 12; ++c)
-        if (S[c] < 0.0) {
+    for (int c = 4; c < NV; ++c)
+        if (depletable(c) && S[c] < 0.0) {
             double t = U[c] / (-S[c]);
             if (t < tau) tau = t;
         }
@@ -618,29 +667,40 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
     const double h = dt / nsub;
     for (int s = 0; s < nsub; ++s) {
         phase_change_rates(cx, U, h, &r);
-        double dM[4], dN[4], act = r.act, mdf = r.mdot_f;
-        for (int k = 0; k < 4; ++k) { dM[k] = r.dM[k]; dN[k] = r.dN[k]; }
-        int evap_l = 0, evap_s = 0;
-        if (r.stale_l || (r.Gl < 0.0 && U[8] + h * dM[3] <= 0.0)) {
-            /* all droplets evaporate within the sub-step: no freezing, soot deactivates */
-            evap_l = 1;
-            for (int k = 0; k < 4; ++k) {
-                dM[k] = -U[5 + k] / h;
-                dN[k] = k > 0 ? k * U[9 + k - 1] * r.Gs : 0.0;
+        double dM[2][4], dN[4], act = r.act, mdf = r.mdot_f;
+        for (int k = 0; k < 4; ++k) { dM[0][k] = r.dM[0][k]; dM[1][k] = r.dM[1][k]; dN[k] = r.dN[k]; }
+        int evap_l[2] = {0, 0}, evap_s = 0;
+        for (int pop = 0; pop < npop; ++pop) {
+            const int b = liq_base(pop);
+            if (r.stale_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * dM[pop][3] <= 0.0)) {
+                /* all droplets of the population evaporate within the sub-step: none of
+                 * them freezes; soot-activated ones release their soot */
+                evap_l[pop] = 1;
+                for (int k = 0; k < 4; ++k) dM[pop][k] = -U[b + k] / h;
+                if (pop == 0) act = -U[14] / h;
             }
+        }
+        if (evap_l[0] || evap_l[1]) {
+            /* the crystals keep their growth and the freezing of the surviving population */
             mdf = 0.0;
-            act = -U[14] / h;
+            for (int k = 0; k < 4; ++k) dN[k] = k > 0 ? k * U[9 + k - 1] * r.Gs : 0.0;
+            for (int pop = 0; pop < npop; ++pop) {
+                if (evap_l[pop]) continue;
+                for (int k = 0; k < 4; ++k) dN[k] += pow(RHO_LIQ / RHO_ICE, k / 3.0) * r.F[pop][k];
+                mdf += RHO_LIQ * fpi * r.F[pop][3];
+            }
         }
         if (r.stale_s || (r.Gs < 0.0 && U[12] + h * dN[3] <= 0.0)) {
             evap_s = 1;
             for (int k = 0; k < 4; ++k) dN[k] = -U[9 + k] / h;
         }
-        exchange_terms(U, dM, dN, act, mdf, S);
+        exchange_terms(U, (const double(*)[4])dM, dN, npop, act, mdf, S);
         /* positivity scaling; an evaporating population reaches zero at theta = 1 by
          * construction and is left out of the minimum */
         double theta = 1.0;
-        for (int c = 4; c <= 12; ++c) {
-            if ((evap_l && c >= 5 && c <= 8) || (evap_s && c >= 9)) continue;
+        for (int c = 4; c < NV; ++c) {
+            if (!depletable(c)) continue;
+            if ((evap_l[0] && c >= 5 && c <= 8) || (evap_s && c >= 9 && c <= 12) || (evap_l[1] && c >= 15)) continue;
             if (S[c] < 0.0) {
                 double t = U[c] / (-h * S[c]);
                 if (t < theta) theta = t;
@@ -648,15 +708,16 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         }
         for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];
         if (theta == 1.0) {
-            if (evap_l) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if (evap_l[0]) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if (evap_l[1]) { U[15] = U[16] = U[17] = U[18] = 0.0; }
             if (evap_s) { U[9] = U[10] = U[11] = U[12] = 0.0; }
         }
         /* Hoelder bounds on mu1 given (mu0, mu2, mu3): mu2^2/mu3 <= mu1 <= sqrt(mu0 mu2).
          * When the interval is empty (an unrealisable (mu0, mu2, mu3) triple) mu1 takes
          * the upper bound, so the clamp is continuous where the interval degenerates
          * (monodisperse populations, e.g. freshly nucleated or frozen ones). */
-        for (int set = 0; set < 2; ++set) {
-            double *m = U + (set ? 9 : 5);
+        for (int set = 0; set < 3; ++set) {
+            double *m = U + (set == 0 ? 5 : set == 1 ? 9 : 15);
             if (population_valid(m)) {
                 double lo = m[2] * m[2] / m[3], hi = sqrt(m[0] * m[2]);
                 if (lo > hi) lo = hi;
@@ -817,12 +878,34 @@ static int source_equilibrium(const or_ctx *cx, const double *U, double dt, doub
     return 1;
 }
 
-void or_set_equilibrium(or_ctx *cx, int on) { cx->equilibrium = on ? 1 : 0; }
-
-int or_source_cell(const or_ctx *cx, const double *U, double dt, double *Q)
+int or_set_equilibrium(or_ctx *cx, int on)
 {
-    if (cx->equilibrium) return source_equilibrium(cx, U, dt, Q);
-    return source_integrate(cx, U, dt, Q);
+    if (on && cx->bimodal) return -1;   /* the equilibrium model has one liquid population */
+    cx->equilibrium = on ? 1 : 0;
+    return 0;
+}
+
+/* Two liquid populations (Sec. 2.2): soot-activated droplets keep variables 5..8,
+ * homogeneously nucleated ones get 15..18, and arrays in memory hold 19 planes.
+ * Not with the equilibrium model or particle drift (one liquid population each). */
+int or_set_bimodal(or_ctx *cx, int on)
+{
+    if (on && (cx->equilibrium || cx->drift)) return -1;
+    cx->bimodal = on ? 1 : 0;
+    cx->nv = on ? NV : NV_BASE;
+    return 0;
+}
+
+int or_nvar(const or_ctx *cx) { return cx->nv; }
+
+/* Source of one cell; U and Q hold cx->nv entries.                               */
+int or_source_cell(const or_ctx *cx, const double *Uin, double dt, double *Qout)
+{
+    double U[NV] = {0}, Q[NV];
+    memcpy(U, Uin, sizeof(double) * cx->nv);
+    int n = cx->equilibrium ? source_equilibrium(cx, U, dt, Q) : source_integrate(cx, U, dt, Q);
+    memcpy(Qout, Q, sizeof(double) * cx->nv);
+    return n;
 }
 
 /* ========================================================== mesh (Sec. 4.1) == */
@@ -891,6 +974,7 @@ or_ctx *or_create(const or_mesh *m, const or_case *c)
     cx->c = *c;
     cx->nx = m->nx;
     cx->nr = m->nr;
+    cx->nv = NV_BASE;
     build_mesh(cx);
     if (m->geom == GEOM_Q1D) {
         cx->ax = malloc(sizeof(double) * (m->nx + 1));
@@ -959,7 +1043,7 @@ int or_init(const or_ctx *cx, double *U)
     const size_t plane = (size_t)nx * nr;
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < nx; ++i)
-            for (int v = 0; v < NV; ++v) U[v * plane + (size_t)j * nx + i] = cx->inflow[NV * j + v];
+            for (int v = 0; v < cx->nv; ++v) U[v * plane + (size_t)j * nx + i] = cx->inflow[NV * j + v];
     return 0;
 }
 
@@ -995,7 +1079,7 @@ static void cell_state(const or_ctx *cx, const double *U, int i, int j, double *
     }
     if (src) memcpy(out, src, sizeof(double) * NV);
     else
-        for (int v = 0; v < NV; ++v) out[v] = U[v * plane + (size_t)j * nx + i];
+        for (int v = 0; v < NV; ++v) out[v] = v < cx->nv ? U[v * plane + (size_t)j * nx + i] : 0.0;
     if (flip_u) out[1] = -out[1];
     if (flip_v) out[2] = -out[2];
 }
@@ -1149,7 +1233,12 @@ static void drift_add(const prim_t *a, const prim_t *b, double mu_a, double mu_b
     }
 }
 
-void or_set_drift(or_ctx *cx, int on) { cx->drift = on ? 1 : 0; }
+int or_set_drift(or_ctx *cx, int on)
+{
+    if (on && cx->bimodal) return -1;   /* drift is defined for one liquid population */
+    cx->drift = on ? 1 : 0;
+    return 0;
+}
 
 /* Convective minus viscous flux through one face, in global components.
  * dir 0: face between (i,j) and (i+1,j); dir 1: between (i,j) and (i,j+1).       */
@@ -1297,14 +1386,14 @@ static void transport_residual(const or_ctx *cx, const double *U, double *Rout)
             if (q1d) {
                 double Aw = cx->ax[i], Ae = cx->ax[i + 1];
                 double Vq = cell_volume(cx, i, j);
-                for (int v = 0; v < NV; ++v) {
+                for (int v = 0; v < cx->nv; ++v) {
                     double Rv = -(Fe[v] * Ae - Fw[v] * Aw);
                     if (v == 1) Rv += FW(&f, i, j).p * (Ae - Aw);
                     Rout[v * plane + (size_t)j * nx + i] = Rv / Vq;
                 }
                 continue;
             }
-            for (int v = 0; v < NV; ++v) {
+            for (int v = 0; v < cx->nv; ++v) {
                 double net = (Fe[v] - Fw[v]) * Ax + (Fn[v] * An - Fs[v] * As);
                 double Rv = -net;
                 if (v == 2) Rv += Sax;
@@ -1331,10 +1420,10 @@ long or_source(const or_ctx *cx, const double *U, double dt, double *Q)
 #pragma omp parallel for schedule(static) reduction(+ : total)
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < nx; ++i) {
-            double Uc[NV], Qc[NV];
-            for (int v = 0; v < NV; ++v) Uc[v] = U[v * plane + (size_t)j * nx + i];
+            double Uc[NV] = {0}, Qc[NV];
+            for (int v = 0; v < cx->nv; ++v) Uc[v] = U[v * plane + (size_t)j * nx + i];
             total += cx->equilibrium ? source_equilibrium(cx, Uc, dt, Qc) : source_integrate(cx, Uc, dt, Qc);
-            for (int v = 0; v < NV; ++v) Q[v * plane + (size_t)j * nx + i] = Qc[v];
+            for (int v = 0; v < cx->nv; ++v) Q[v * plane + (size_t)j * nx + i] = Qc[v];
         }
     return total;
 }
@@ -1368,7 +1457,7 @@ int or_cfl_dt(const or_ctx *cx, const double *U, double *dt_out)
 /* One SSP-RK3 (Shu-Osher) step with L(U) = R(U)/V + Q(U, dt).                     */
 int or_step(const or_ctx *cx, double *U, double dt)
 {
-    const size_t n = (size_t)NV * cx->nx * cx->nr;
+    const size_t n = (size_t)cx->nv * cx->nx * cx->nr;
     double *R = malloc(sizeof(double) * n), *Q = malloc(sizeof(double) * n);
     double *U1 = malloc(sizeof(double) * n), *U2 = malloc(sizeof(double) * n);
     transport_residual(cx, U, R);
@@ -1407,11 +1496,13 @@ void or_diag(const or_ctx *cx, const double *U, double *out)
         for (int i = 0; i < nx; ++i) {
             size_t k = (size_t)j * nx + i;
             double V = cell_volume(cx, i, j);
-            water += V * (U[4 * plane + k] + 4.0 / 3.0 * PI * (RHO_LIQ * U[8 * plane + k] + RHO_ICE * U[12 * plane + k]));
+            double liq = U[8 * plane + k];
+            if (cx->bimodal) liq += U[18 * plane + k];
+            water += V * (U[4 * plane + k] + 4.0 / 3.0 * PI * (RHO_LIQ * liq + RHO_ICE * U[12 * plane + k]));
             nice += V * U[9 * plane + k];
             gas += V * U[k];
-            double Uc[NV];
-            for (int v = 0; v < NV; ++v) Uc[v] = U[v * plane + k];
+            double Uc[NV] = {0};
+            for (int v = 0; v < cx->nv; ++v) Uc[v] = U[v * plane + k];
             prim_t w;
             cons_to_prim(Uc, &w);
             double pv = Uc[4] * RGAS_VAP * w.T;
