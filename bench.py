@@ -91,20 +91,24 @@ def measured_valu(tile):
 
 
 def condensed_water(s, U):
-    """Condensed water (liquid + ice) per radian of the axisymmetric domain [kg]."""
+    """Condensed water (liquid of both populations + ice) per radian of the
+    axisymmetric domain [kg]."""
     import math
     import torch
     xf, rf = s.faces()
     dx = torch.as_tensor(xf[1:] - xf[:-1], device=U.device, dtype=torch.float64)
     rdr = torch.as_tensor((rf[1:] - rf[:-1]) * 0.5 * (rf[1:] + rf[:-1]), device=U.device, dtype=torch.float64)
-    cond = 4.0 / 3.0 * math.pi * (1000.0 * U[8].double() + 917.0 * U[12].double())
+    liq = U[8].double() + (U[18].double() if U.shape[0] > 15 else 0.0)
+    cond = 4.0 / 3.0 * math.pi * (1000.0 * liq + 917.0 * U[12].double())
     return float((cond * rdr[:, None] * dx[None, :]).sum())
 
 
 def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, keep=False, tile=None, qmode=None,
-             table_h=0.0, drift=False):
+             table_h=0.0, drift=False, bimodal=False):
     import torch
     s = binding.Solver(m, c, precision)
+    if bimodal:
+        s.set_bimodal(True)
     U = s.init()
     if drift:
         s.set_drift(True)
@@ -135,6 +139,9 @@ def run_path(binding, m, c, precision, steps, warmup, stage_reps=0, sur=None, ke
                active_cells=d["active_cells"], esz=8 if precision == binding.CP_FP64 else 4, cells=cells)
     if d["active_cells"] > 0:
         out["condensed_water_per_rad"] = condensed_water(s, U)
+        if bimodal:   # share of the droplet number in the homogeneously nucleated population
+            n_het, n_hom = float(U[5].double().sum()), float(U[15].double().sum())
+            out["homogeneous_droplet_number_share"] = n_hom / max(n_het + n_hom, 1e-300)
         # exact-source sub-steps over the timed steps, per cell-stage of the active set
         subs = d["nsub_total"] - d0["nsub_total"]
         out["source_substeps_per_step"] = subs / steps
@@ -186,8 +193,9 @@ def train_surrogate(binding, inputs, log):
 
 def run_source_active(binding, inputs, steps, warmup, trained):
     """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate,
-    mixed with tabulated water properties, mixed with particle drift, and the mixed
-    path with the equilibrium comparison model."""
+    mixed with tabulated water properties, mixed with particle drift, the mixed path
+    with the equilibrium comparison model, and two liquid populations in FP64 and
+    mixed."""
     import torch
     net, norm, rep = trained
     m, c = inputs.sa2(0)
@@ -204,6 +212,12 @@ def run_source_active(binding, inputs, steps, warmup, trained):
     # the paper's comparison model (a different model: no error against the kinetics)
     res["mixed_equilibrium"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
                                         qmode=binding.CP_Q_EQUILIBRIUM)
+    # two liquid populations (19 variables): the mixed path against the FP64 path of
+    # the same model
+    res["fp64_bimodal"] = run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True, bimodal=True)
+    res["mixed_bimodal"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, bimodal=True)
+    res["mixed_bimodal"]["error_vs_fp64_bimodal"] = rel_errors(res["mixed_bimodal"].pop("U"),
+                                                              res["fp64_bimodal"].pop("U"))
     Uref = res["fp64"].pop("U")
     for k in ("mixed", "mixed_surrogate", "mixed_tables", "mixed_drift"):
         res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)

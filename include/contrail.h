@@ -13,7 +13,8 @@
  *
  * Conventions for every call
  *  - Arrays are caller-owned DEVICE pointers (hipMalloc'ed memory or torch CUDA
- *    tensors), contiguous structure-of-arrays U[15][nr][nx] (x index fastest).
+ *    tensors), contiguous structure-of-arrays U[15][nr][nx] (x index fastest),
+ *    or U[19][nr][nx] once cp_set_bimodal has split the liquid (cp_nvar).
  *    Element type: double for CP_FP64 contexts, float for CP_MIXED contexts.
  *    The library never frees caller memory.
  *  - Component order of U (per m^3):
@@ -26,6 +27,9 @@
  *      9..12        rho mu_k of the ice crystals, k = 0..3  Eq. 19, 26
  *      13           soot number density                     Sec. 2.2 (soot at the inflow)
  *      14           activated soot number density           Sec. 2.2 (heterogeneous nucleation)
+ *      15..18       rho mu_k of the homogeneously nucleated droplets, k = 0..3, with
+ *                   two liquid populations (cp_set_bimodal; 5..8 then hold the
+ *                   soot-activated droplets)                 Sec. 2.2
  *  - Every call is ordered on the HIP stream given to cp_create and returns
  *    without synchronising unless stated.  Status codes are returned, never
  *    exceptions; cp_error_string gives the last message of a context.
@@ -194,6 +198,25 @@ int cp_set_drift(cp_ctx *ctx, int on);
  * device copy; the call synchronises the stream.  Errors: CP_EINVAL (h < 0, or
  * more than 1e6 nodes), CP_ENOMEM, CP_EHIP.                                       */
 int cp_set_property_table(cp_ctx *ctx, double h);
+
+/* Two liquid populations (on != 0), the bimodal moment approach of Sec. 2.2: the
+ * soot-activated droplets keep variables 5..8 and the homogeneously nucleated ones
+ * take 15..18, so every state, residual and source array of the context then has
+ * 19 planes.  Each population has its own nucleation source (the activation rate,
+ * or the homogeneous rate, at the critical radius), r20 growth closure and
+ * lognormal freezing closure; immersion freezing acts on the soot-activated
+ * droplets only (it needs a soot core), and only their complete evaporation
+ * releases the activated soot; frozen droplets of both join the one crystal
+ * population.  The inflow and far field carry no homogeneous droplets.  The stage
+ * kernel uses the 32 x 8 tile.  Off by default; switching drops the captured
+ * steps.  Errors: CP_EUNSUPPORTED in the quasi-1D duct, with drift, with the
+ * surrogate or the equilibrium model selected (each has one liquid population;
+ * cp_set_qmode and cp_set_drift refuse them in turn).                            */
+int cp_set_bimodal(cp_ctx *ctx, int on);
+
+/* Variables per cell of the context's arrays: 15, or 19 with two liquid
+ * populations.  CP_EINVAL for a null context.                                     */
+int cp_nvar(const cp_ctx *ctx);
 
 /* Tile shape of the stage kernel: (tx, ty) from the built set, or (0, 0) to run the
  * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built.     */

@@ -2,7 +2,8 @@
 
 Argument marshalling only: every step of the method runs in the HIP kernels of
 the library.  Arrays are torch CUDA tensors (or raw device pointers) shaped
-``(15, nr, nx)``; float64 for CP_FP64 contexts, float32 for CP_MIXED contexts.
+``(nv, nr, nx)`` (nv = 15, or 19 with two liquid populations); float64 for CP_FP64
+contexts, float32 for CP_MIXED contexts.
 Loading fails loudly when the library has not been built -- there is no
 fallback path.
 """
@@ -68,6 +69,8 @@ _SIGS = {
     "cp_set_tile": (_I, [_P, _I, _I]),
     "cp_set_property_table": (_I, [_P, _D]),
     "cp_set_drift": (_I, [_P, _I]),
+    "cp_set_bimodal": (_I, [_P, _I]),
+    "cp_nvar": (_I, [_P]),
     "cp_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "cp_mesh_faces": (_I, [_P, _DP, _DP]),
     "cp_time_stage": (_I, [_P, _P, _I, _DP]),
@@ -188,15 +191,26 @@ class Solver:
         import torch
         return torch.float64 if self.precision == CP_FP64 else torch.float32
 
+    @property
+    def nv(self):
+        """Variables per cell: 15, or 19 with two liquid populations."""
+        return self.L.cp_nvar(self.h)
+
+    def set_bimodal(self, on=True):
+        """Two liquid populations (soot-activated in 5..8, homogeneously nucleated in
+        15..18); arrays then hold 19 planes."""
+        self._chk(self.L.cp_set_bimodal(self.h, 1 if on else 0))
+
     def empty(self):
         import torch
-        return torch.empty((NV, self.nr, self.nx), dtype=self.dtype, device="cuda")
+        return torch.empty((self.nv, self.nr, self.nx), dtype=self.dtype, device="cuda")
 
     def _check(self, U):
         import torch
         if isinstance(U, torch.Tensor):
-            if U.dtype != self.dtype or not U.is_cuda or not U.is_contiguous() or U.numel() != NV * self.nx * self.nr:
-                raise ValueError("U must be a contiguous CUDA %s tensor of %d elements" % (self.dtype, NV * self.nx * self.nr))
+            n = self.nv * self.nx * self.nr
+            if U.dtype != self.dtype or not U.is_cuda or not U.is_contiguous() or U.numel() != n:
+                raise ValueError("U must be a contiguous CUDA %s tensor of %d elements" % (self.dtype, n))
 
     def init(self, U=None):
         U = self.empty() if U is None else U

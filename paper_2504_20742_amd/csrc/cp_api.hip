@@ -32,6 +32,7 @@ struct cp_ctx {
     std::vector<double> ax;                         // quasi-1D duct areas at the x faces
     double *ptab = nullptr;                         // water property table (device), or null
     bool drift = false;                             // particles drift against the gas
+    int nv = NVAR;                                  // variables per cell: NVAR, or NVAR_BI (two liquid populations)
     double *rfa_d = nullptr, *invVr_d = nullptr;    // double r-face areas and 1/(r_c dr) for the drift
     std::vector<void *> allocs;                     // device memory owned by the context
     double *inflow = nullptr, *ambient = nullptr, *vol = nullptr;
@@ -440,9 +441,9 @@ int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage,
 {
     hipError_t e;
     if (c->precision == CP_FP64)
-        e = launch_stage<double>(stage_args<double>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, s);
+        e = launch_stage<double>(stage_args<double>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, c->nv, s);
     else
-        e = launch_stage<float>(stage_args<float>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, s);
+        e = launch_stage<float>(stage_args<float>(c, Uin, Un, Uout, stage, dt, dt_dev), c->tx, c->ty, c->nv, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("stage launch: ") + hipGetErrorString(e));
     if (c->drift) {
         auto drift = [&](auto *tag) {
@@ -470,9 +471,9 @@ int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage,
     if (!src) return CP_OK;
     if (c->qmode == CP_Q_SURROGATE) return surrogate_any(c, Uin, Uout, stage, dt, dt_dev, s);
     if (c->precision == CP_FP64)
-        e = launch_source_fix<double>(fix_args<double>(c, Uin, Uout, stage, dt, dt_dev), c->plane, s);
+        e = launch_source_fix<double>(fix_args<double>(c, Uin, Uout, stage, dt, dt_dev), c->plane, c->nv, s);
     else
-        e = launch_source_fix<float>(fix_args<float>(c, Uin, Uout, stage, dt, dt_dev), c->plane, s);
+        e = launch_source_fix<float>(fix_args<float>(c, Uin, Uout, stage, dt, dt_dev), c->plane, c->nv, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("source launch: ") + hipGetErrorString(e));
     return CP_OK;
 }
@@ -517,6 +518,11 @@ int check_flag(cp_ctx *c)
 int autotune(cp_ctx *c, const void *U)
 {
     if (c->tx) return CP_OK;
+    if (c->nv == NVAR_BI) {   // two liquid populations: the one built shape
+        c->tx = 32;
+        c->ty = 8;
+        return CP_OK;
+    }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -637,8 +643,9 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
     const size_t esz = precision == CP_FP64 ? sizeof(double) : sizeof(float);
     c->inflow = dalloc<double>(c, inflow.size());
     c->ambient = dalloc<double>(c, NVAR);
-    c->Ua = dalloc<char>(c, esz * NVAR * c->plane);
-    c->Ub = dalloc<char>(c, esz * NVAR * c->plane);
+    // stage buffers sized for two liquid populations, so that cp_set_bimodal needs no allocation
+    c->Ua = dalloc<char>(c, esz * NVAR_BI * c->plane);
+    c->Ub = dalloc<char>(c, esz * NVAR_BI * c->plane);
     c->dt_d = dalloc<double>(c, 1);
     c->t_d = dalloc<double>(c, 1);
     c->diag_d = dalloc<double>(c, 8);
@@ -683,8 +690,9 @@ void cp_destroy(cp_ctx *c)
 int cp_init(cp_ctx *c, void *U)
 {
     if (!c || !U) return fail(c, CP_EINVAL, "null argument");
-    hipError_t e = c->precision == CP_FP64 ? launch_init<double>((double *)U, c->inflow, c->nx, c->nr, c->stream)
-                                           : launch_init<float>((float *)U, c->inflow, c->nx, c->nr, c->stream);
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_init<double>((double *)U, c->inflow, c->nx, c->nr, c->nv, c->stream)
+                       : launch_init<float>((float *)U, c->inflow, c->nx, c->nr, c->nv, c->stream);
     if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
     return CP_OK;
 }
@@ -709,9 +717,9 @@ int cp_source(cp_ctx *c, const void *U, double dt, void *Q)
     HIPCHK(c, hipMemsetAsync(c->nsub_d, 0, sizeof(unsigned long long), c->stream));
     hipError_t e = c->precision == CP_FP64
                        ? launch_source<double>((const double *)U, (double *)Q, c->plane, c->plane, dt, sp, c->nsub_d,
-                                               c->stream)
+                                               c->nv, c->stream)
                        : launch_source<float>((const float *)U, (float *)Q, c->plane, c->plane, dt, sp, c->nsub_d,
-                                              c->stream);
+                                              c->nv, c->stream);
     if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
     if (c->qmode == CP_Q_SURROGATE && sp.enabled)
         return c->precision == CP_FP64 ? surrogate_source<double>(c, U, dt, Q) : surrogate_source<float>(c, U, dt, Q);
@@ -832,9 +840,11 @@ int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
 int cp_set_qmode(cp_ctx *c, int qmode)
 {
     if (!c) return CP_EINVAL;
-    if (qmode == CP_Q_SURROGATE && !c->sur_ready) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
     if (qmode != CP_Q_EXACT && qmode != CP_Q_OFF && qmode != CP_Q_SURROGATE && qmode != CP_Q_EQUILIBRIUM)
         return fail(c, CP_EINVAL, "bad qmode");
+    if (c->nv == NVAR_BI && (qmode == CP_Q_SURROGATE || qmode == CP_Q_EQUILIBRIUM))
+        return fail(c, CP_EUNSUPPORTED, "the surrogate and the equilibrium model have one liquid population");
+    if (qmode == CP_Q_SURROGATE && !c->sur_ready) return fail(c, CP_ESTATE, "no surrogate attached (cp_sur_set)");
     c->qmode = qmode;
     c->sp.equilibrium = qmode == CP_Q_EQUILIBRIUM ? 1 : 0;
     drop_graphs(c);
@@ -846,8 +856,10 @@ int cp_diag(cp_ctx *c, const void *U, double out[8])
     if (!c || !U || !out) return fail(c, CP_EINVAL, "null argument");
     HIPCHK(c, hipMemsetAsync(c->diag_d, 0, 8 * sizeof(double), c->stream));
     hipError_t e = c->precision == CP_FP64
-                       ? launch_diag<double>((const double *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->stream)
-                       : launch_diag<float>((const float *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->stream);
+                       ? launch_diag<double>((const double *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->nv,
+                                             c->stream)
+                       : launch_diag<float>((const float *)U, c->plane, c->nx, c->nr, c->vol, c->diag_d, c->nv,
+                                            c->stream);
     if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
     double h[8];
     unsigned long long ns = 0;
@@ -877,6 +889,7 @@ int cp_sur_features(cp_ctx *c, const void *U, double dt, const float *s_in, floa
 {
     if (!c || !U || !s_in || !F) return fail(c, CP_EINVAL, "null argument");
     if (!(dt > 0.0)) return fail(c, CP_EDT, "dt must be positive");
+    if (c->nv != NVAR) return fail(c, CP_EUNSUPPORTED, "the surrogate's features have one liquid population");
     for (int v = 0; v < NVAR; ++v)
         if (!(s_in[v] > 0.f)) return fail(c, CP_EINVAL, "feature scales must be positive");
     SurNorm nm{};
@@ -893,7 +906,7 @@ int cp_set_tile(cp_ctx *c, int tx, int ty)
     if (!c) return CP_EINVAL;
     if (tx == 0 && ty == 0) {
         c->tx = c->ty = 0;
-    } else if (!tile_supported(tx, ty)) {
+    } else if (!tile_supported(tx, ty) || (c->nv == NVAR_BI && (tx != 32 || ty != 8))) {
         return fail(c, CP_EUNSUPPORTED, "tile shape not built");
     } else {
         c->tx = tx;
@@ -907,10 +920,31 @@ int cp_set_drift(cp_ctx *c, int on)
 {
     if (!c) return CP_EINVAL;
     if (on && c->mesh.geom == CP_GEOM_QUASI1D) return fail(c, CP_EUNSUPPORTED, "no drift in the quasi-1D duct");
+    if (on && c->nv == NVAR_BI) return fail(c, CP_EUNSUPPORTED, "drift is defined for one liquid population");
     c->drift = on != 0;
     drop_graphs(c);
     return CP_OK;
 }
+
+int cp_set_bimodal(cp_ctx *c, int on)
+{
+    if (!c) return CP_EINVAL;
+    if (on) {
+        if (c->mesh.geom == CP_GEOM_QUASI1D) return fail(c, CP_EUNSUPPORTED, "no particles in the quasi-1D duct");
+        if (c->drift) return fail(c, CP_EUNSUPPORTED, "drift is defined for one liquid population");
+        if (c->qmode == CP_Q_SURROGATE || c->qmode == CP_Q_EQUILIBRIUM)
+            return fail(c, CP_EUNSUPPORTED, "the surrogate and the equilibrium model have one liquid population");
+    }
+    const int nv = on ? NVAR_BI : NVAR;
+    if (nv != c->nv) {
+        c->nv = nv;
+        c->tx = c->ty = 0;   // the tile is chosen again for the new variable count
+        drop_graphs(c);
+    }
+    return CP_OK;
+}
+
+int cp_nvar(const cp_ctx *c) { return c ? c->nv : CP_EINVAL; }
 
 int cp_set_property_table(cp_ctx *c, double h)
 {
@@ -964,11 +998,11 @@ int cp_time_stage(cp_ctx *c, void *U, int reps, double *ms)
             if (c->precision == CP_FP64) {
                 StageArgs<double> a = stage_args<double>(c, in[st], U, out[st], st, dt, nullptr);
                 a.sp.enabled = 0;   // keep the active list untouched
-                e = launch_stage<double>(a, c->tx, c->ty, c->stream);
+                e = launch_stage<double>(a, c->tx, c->ty, c->nv, c->stream);
             } else {
                 StageArgs<float> a = stage_args<float>(c, in[st], U, out[st], st, dt, nullptr);
                 a.sp.enabled = 0;
-                e = launch_stage<float>(a, c->tx, c->ty, c->stream);
+                e = launch_stage<float>(a, c->tx, c->ty, c->nv, c->stream);
             }
             if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
         }

@@ -122,10 +122,11 @@ hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int
                              int max_rows, float *Y, hipStream_t s);
 void mlp_dims(const cp_mlp *n, int *n_in, int *n_out);
 
-// launchers (cp_kernels.hip)
-template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s);
+// launchers (cp_kernels.hip); nv: variables per cell (NVAR, or NVAR_BI with two
+// liquid populations, which has the 32 x 8 stage tile only)
+template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, int nv, hipStream_t s);
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
-template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s);
+template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, int nv, hipStream_t s);
 template <class R> hipError_t launch_drift(const DriftArgs<R> &a, hipStream_t s);
 hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
 // dt = cfl * min(block_min[0..n)), t += dt (t nullable)
@@ -140,10 +141,10 @@ hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
                                      hipStream_t s);
 hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s);
 template <class R> hipError_t launch_source(const R *U, R *Q, long n, long plane, double dt, const SourceParams &sp,
-                                            unsigned long long *nsub, hipStream_t s);
-template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, hipStream_t s);
+                                            unsigned long long *nsub, int nv, hipStream_t s);
+template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, int nv, hipStream_t s);
 template <class R> hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol,
-                                          double *out, hipStream_t s);
+                                          double *out, int nv, hipStream_t s);
 // normalisation of the learned source (feature / target transforms, envelope)
 struct SurNorm {
     float s_in[15];            // feature v = asinh(U_v / s_in[v]) for the 15 state variables

@@ -110,6 +110,7 @@ template <class R>
 __device__ __forceinline__ R fetch(const R *U, long plane, const BcInfo &b, int code, int v)
 {
     if (code >= 0) return U[v * plane + code];
+    if (v >= NVAR) return R(0);   // the inflow and the far field carry no homogeneous droplets
     if (code == kAmbient) return (R)b.ambient[v];
     return (R)b.inflow[(-1 - code) * NVAR + v];
 }
@@ -139,7 +140,7 @@ template <class R, int TX, int TY> struct Tile {
     R sl[5][NR];                 // slopes of one direction (x, then r); the scalars' x slopes
     R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF];
                                  // the scalars' r slopes during the scalar phase, [5][NR]
-    int nonzero[2];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
+    int nonzero[3];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
     __device__ R (*face())[NF] { return reinterpret_cast<R(*)[NF]>(fbuf); }
     __device__ R (*rslope())[NR] { return reinterpret_cast<R(*)[NR]>(fbuf); }
 };
@@ -290,8 +291,9 @@ __device__ __forceinline__ int xcd_band(int b, int nb)
 // One fused SSP-RK3 stage on the TX x TY tile whose first cell is (i0, j0).
 // DUCT: the quasi-1D duct (one row, x faces of the duct areas, no r faces, wall
 // force on axial momentum), a separate instantiation so that the axisymmetric and
-// planar kernels carry none of its code.
-template <class R, int TX, int TY, bool DUCT = false>
+// planar kernels carry none of its code.  NV: variables per cell, NVAR or NVAR_BI
+// (two liquid populations: the passive scalars go in three groups, 5 + 5 + 4).
+template <class R, int TX, int TY, bool DUCT = false, int NV = NVAR>
 __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0, Tile<R, TX, TY> &t)
 {
     using TileT = Tile<R, TX, TY>;
@@ -310,7 +312,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     const bool inner = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= nx && j0 + TY + 2 <= nr;
     R(*face)[TileT::NF] = t.face();
 
-    if (tid == 0) t.nonzero[0] = t.nonzero[1] = 0;
+    if (tid == 0) t.nonzero[0] = t.nonzero[1] = t.nonzero[2] = 0;
     // phase 1: gas primitives of tile + halo
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
@@ -382,7 +384,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         face[5][f] = fm;
     }
     __syncthreads();
-    R res[NVAR];
+    R res[NV];
     R Fm0 = R(0), Fm1 = R(0), Fm2 = R(0), Fm3 = R(0), kd0 = R(0), kd1 = R(0), kd2 = R(0), kd3 = R(0);
     const R idx = valid ? m.inv_dx[i] : R(0);
     if (valid) {
@@ -453,9 +455,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // and zero fluxes, so its slope and flux work is skipped: the result is the same
     // zero (the stage output is bit-identical).
     const R Tcell = valid ? t.T[l] : R(0);
+    constexpr int NG = (NV - 5 + 4) / 5;
     #pragma unroll
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < NG; ++g) {
         const int s0 = 5 + 5 * g;
+        const int ng = NV - s0 < 5 ? NV - s0 : 5;   // scalars in this group
         __syncthreads();
         int nz = 0;
         if (inner) {
@@ -464,6 +468,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
+                    if (k >= ng) continue;
                     const R u = ld_plane(a.Uin, a.plane, s0 + k, code);
                     nz |= (u != R(0)) << k;
                     scalar_slot(t, k)[e] = per_mass(u, rho, ir);
@@ -475,6 +480,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
+                    if (k >= ng) continue;
                     const R u = fetch(a.Uin, a.plane, bc, code, s0 + k);
                     nz |= (u != R(0)) << k;
                     scalar_slot(t, k)[e] = per_mass(u, rho, ir);
@@ -505,6 +511,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
             #pragma unroll
             for (int k = 0; k < 5; ++k) {
+                if (k >= ng) continue;
                 if (!(live & (1 << k))) {
                     res[s0 + k] = R(0);
                     continue;
@@ -530,7 +537,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     bool bad = false;
     if (a.stage < 0) {
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
             a.Uout[v * a.plane + c] = res[v];
             bad |= !isfinite(res[v]);
         }
@@ -539,21 +546,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         // every load of the cell's old states is issued before the first store (the
         // compiler cannot rule out that Uout aliases them, and would otherwise wait
         // for each load in turn)
-        R ui[NVAR], un[NVAR];
+        R ui[NV], un[NV];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
+        for (int v = 0; v < NV; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
         if (a.stage > 0) {
             #pragma unroll
-            for (int v = 0; v < NVAR; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
+            for (int v = 0; v < NV; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
         }
         bool act = false;
-        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], ui[5], ui[9], Tcell))) {
-            double Ug[NVAR];
+        // liquid number of the cell for the pre-filter: either population
+        R Mliq = ui[5];
+        if constexpr (NV == NVAR_BI) Mliq = ui[15] > Mliq ? ui[15] : Mliq;
+        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], Mliq, ui[9], Tcell))) {
+            double Ug[NV];
             #pragma unroll
-            for (int v = 0; v < NVAR; ++v) Ug[v] = (v <= 5 || v == 9) ? (double)ui[v] : 0.0;
+            for (int v = 0; v < NV; ++v) Ug[v] = (v <= 5 || v == 9 || v == 15) ? (double)ui[v] : 0.0;
             CellThermo th;
             cell_thermo(Ug, th);
-            act = !source_inactive(Ug, th.T);
+            act = !source_inactive<NV>(Ug, th.T);
         }
         // append the wavefront's active cells with one atomic
         const unsigned long long mask = __ballot(act);
@@ -568,7 +578,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
         }
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const R L = res[v];
             R out;
             if (a.stage == 0) {
@@ -585,18 +595,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
 }
 
 // FP32: registers held to 80 per lane (6 wavefronts per SIMD), which is what the
-// LDS tile allows for 256-thread tiles; FP64 is held to three by both.
+// LDS tile allows for 256-thread tiles; FP64 is held to three by both.  The
+// 19-variable kernel (two liquid populations) is left free, so that it does not spill.
 #define CP_STAGE_WAVES __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1)))
 
-template <class R, int TX, int TY, bool DUCT = false>
-__global__ void __launch_bounds__(TX *TY) CP_STAGE_WAVES k_stage(StageArgs<R> a)
+template <class R, int TX, int TY, bool DUCT = false, int NV = NVAR>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && NV == NVAR ? 6 : 1)))
+k_stage(StageArgs<R> a)
 {
     __shared__ Tile<R, TX, TY> t;
     // surrogate counters of the previous stage, consumed by now (saves a launch)
     if (a.sur_cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sur_fold_counts(a.sur_cnt, a.sur_tot);
     const int gx = gridDim.x;
     const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
-    stage_tile<R, TX, TY, DUCT>(a, (tb % gx) * TX, (tb / gx) * TY, t);
+    stage_tile<R, TX, TY, DUCT, NV>(a, (tb % gx) * TX, (tb / gx) * TY, t);
 }
 
 // Batched operating points: workgroup b takes work item b (XCD-banded) of a list of
@@ -616,7 +628,8 @@ __global__ void __launch_bounds__(TX *TY) CP_STAGE_WAVES k_stage_batch(const Sta
 // Phase-change source of the listed cells: U^(s) += b dt Q(U^(s-1), dt), b the
 // weight of L in the stage (1, 1/4, 2/3).  Q is evaluated in FP64.  Clears the
 // list counter of the next stage.
-template <class R> __device__ __forceinline__ void source_fix_body(const SourceFixArgs<R> &a, int bx, int nbx)
+template <class R, int NV = NVAR>
+__device__ __forceinline__ void source_fix_body(const SourceFixArgs<R> &a, int bx, int nbx)
 {
     const int n = (int)min((long)*a.count, a.plane);
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
@@ -625,15 +638,15 @@ template <class R> __device__ __forceinline__ void source_fix_body(const SourceF
     bool bad = false;
     for (int k = bx * blockDim.x + threadIdx.x; k < n; k += nbx * blockDim.x) {
         const long c = a.list[k];
-        double Ud[NVAR], Q[NVAR];
+        double Ud[NV], Q[NV];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
-        ns += source_integrate(Ud, dt, a.sp, Q);
-        R uo[NVAR];   // all loads before the stores (possible aliasing serialises them)
+        for (int v = 0; v < NV; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
+        ns += source_integrate<NV>(Ud, dt, a.sp, Q);
+        R uo[NV];   // all loads before the stores (possible aliasing serialises them)
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) uo[v] = a.Uout[v * a.plane + c];
+        for (int v = 0; v < NV; ++v) uo[v] = a.Uout[v * a.plane + c];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const R out = uo[v] + (R)(b * dt * Q[v]);
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
@@ -649,13 +662,13 @@ template <class R> __device__ __forceinline__ void source_fix_body(const SourceF
 // the mesh, so they are spread over as many compute units as possible.
 // A workgroup with no listed cell leaves at once, before any of the source code
 // is fetched (most stages of a jet have no source-active cell at all).
-template <class R> __global__ void __launch_bounds__(64) k_source_fix(SourceFixArgs<R> a)
+template <class R, int NV = NVAR> __global__ void __launch_bounds__(64) k_source_fix(SourceFixArgs<R> a)
 {
     if ((long)blockIdx.x * blockDim.x >= min((long)*a.count, a.plane)) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
         return;
     }
-    source_fix_body(a, blockIdx.x, gridDim.x);
+    source_fix_body<R, NV>(a, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ drift
@@ -1303,19 +1316,19 @@ __global__ void __launch_bounds__(256) k_cfl_finalize_blocks(const double *bm, i
 __global__ void k_acc_reset(unsigned long long *acc) { *acc = 0x7FF0000000000000ull; }
 
 // ------------------------------------------------------------------ source
-template <class R>
+template <class R, int NV = NVAR>
 __global__ void __launch_bounds__(256) k_source(const R *U, R *Q, long n, long plane, double dt, SourceParams sp,
                                                 unsigned long long *nsub)
 {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int ns = 0;
     if (c < n) {
-        double Ud[NVAR], Qd[NVAR];
+        double Ud[NV], Qd[NV];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
-        ns = source_integrate(Ud, dt, sp, Qd);
+        for (int v = 0; v < NV; ++v) Ud[v] = (double)U[v * plane + c];
+        ns = source_integrate<NV>(Ud, dt, sp, Qd);
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Q[v * plane + c] = (R)Qd[v];
+        for (int v = 0; v < NV; ++v) Q[v * plane + c] = (R)Qd[v];
     }
     for (int o = 32; o > 0; o >>= 1) ns += __shfl_xor(ns, o, 64);
     if ((threadIdx.x & 63) == 0 && ns) atomicAdd(nsub, (unsigned long long)ns);
@@ -1323,7 +1336,7 @@ __global__ void __launch_bounds__(256) k_source(const R *U, R *Q, long n, long p
 
 // ------------------------------------------------------------------ init
 template <class R>
-__global__ void __launch_bounds__(256) k_init(R *U, const double *inflow, int nx, int nr)
+__global__ void __launch_bounds__(256) k_init(R *U, const double *inflow, int nx, int nr, int nv)
 {
     const long n = (long)nx * nr;
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1331,27 +1344,29 @@ __global__ void __launch_bounds__(256) k_init(R *U, const double *inflow, int nx
     const int j = (int)(c / nx);
     #pragma unroll
     for (int v = 0; v < NVAR; ++v) U[v * n + c] = (R)inflow[j * NVAR + v];
+    for (int v = NVAR; v < nv; ++v) U[v * n + c] = R(0);   // no homogeneous droplets yet
 }
 
 // ------------------------------------------------------------------ diagnostics
 template <class R>
-__global__ void __launch_bounds__(256) k_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out)
+__global__ void __launch_bounds__(256) k_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out,
+                                              int nv)
 {
     const long n = (long)nx * nr;
     double w = 0.0, ice = 0.0, gas = 0.0, act = 0.0, lnS = -__builtin_huge_val();
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
-        double Ud[NVAR];
+        double Ud[NVAR_BI];
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
+        for (int v = 0; v < NVAR_BI; ++v) Ud[v] = v < nv ? (double)U[v * plane + c] : 0.0;
         const double V = vol[c];
-        w += V * (Ud[4] + kFourThirdsPi * (kRhoL * Ud[8] + kRhoS * Ud[12]));
+        w += V * (Ud[4] + kFourThirdsPi * (kRhoL * (Ud[8] + Ud[18]) + kRhoS * Ud[12]));
         ice += V * Ud[9];
         gas += V * Ud[0];
         CellThermo th;
         cell_thermo(Ud, th);
         double pv = fmax(Ud[4] * kRv * th.T, kPvFloor);
         lnS = fmax(lnS, log(pv) - ln_psat(kSonW, th.T));
-        act += source_inactive(Ud, th.T) ? 0.0 : 1.0;
+        act += source_inactive<NVAR_BI>(Ud, th.T) ? 0.0 : 1.0;
     }
     for (int o = 32; o > 0; o >>= 1) {
         w += __shfl_xor(w, o, 64);
@@ -1384,17 +1399,23 @@ bool tile_supported(int tx, int ty)
     return false;
 }
 
-template <class R, int TX, int TY, bool DUCT = false>
+template <class R, int TX, int TY, bool DUCT = false, int NV = NVAR>
 static hipError_t stage_launch(const StageArgs<R> &a, hipStream_t s)
 {
     dim3 grid((a.bc.nx + TX - 1) / TX, (a.bc.nr + TY - 1) / TY);
-    hipLaunchKernelGGL((k_stage<R, TX, TY, DUCT>), grid, dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_stage<R, TX, TY, DUCT, NV>), grid, dim3(TX * TY), 0, s, a);
     return hipGetLastError();
 }
 
-// The duct (one row) always takes its own 64 x 4 instantiation.
-template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, hipStream_t s)
+// The duct (one row) always takes its own 64 x 4 instantiation; two liquid
+// populations (nv = NVAR_BI) the 32 x 8 one.
+template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty, int nv, hipStream_t s)
 {
+    if (nv == NVAR_BI) {
+        if (a.bc.geom == kGeomQuasi1D || tx != 32 || ty != 8) return hipErrorInvalidValue;
+        return stage_launch<R, 32, 8, false, NVAR_BI>(a, s);
+    }
+    if (nv != NVAR) return hipErrorInvalidValue;
     if (a.bc.geom == kGeomQuasi1D) return stage_launch<R, 64, 4, true>(a, s);
     if (tx == 32 && ty == 8) return stage_launch<R, 32, 8>(a, s);
     if (tx == 16 && ty == 16) return stage_launch<R, 16, 16>(a, s);
@@ -1456,12 +1477,17 @@ template <class R> hipError_t launch_drift(const DriftArgs<R> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, hipStream_t s)
+template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, int nv, hipStream_t s)
 {
     // enough one-wavefront workgroups for every CU; the list length is only known
     // on the device, so the workgroups stride over it
     int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 512));
-    hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(64), 0, s, a);
+    if (nv == NVAR_BI)
+        hipLaunchKernelGGL((k_source_fix<R, NVAR_BI>), dim3(blocks), dim3(64), 0, s, a);
+    else if (nv == NVAR)
+        hipLaunchKernelGGL((k_source_fix<R>), dim3(blocks), dim3(64), 0, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1533,46 +1559,54 @@ hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s)
 
 template <class R>
 hipError_t launch_source(const R *U, R *Q, long n, long plane, double dt, const SourceParams &sp,
-                         unsigned long long *nsub, hipStream_t s)
+                         unsigned long long *nsub, int nv, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_source<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, Q, n, plane, dt, sp, nsub);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (nv == NVAR_BI)
+        hipLaunchKernelGGL((k_source<R, NVAR_BI>), grid, dim3(256), 0, s, U, Q, n, plane, dt, sp, nsub);
+    else if (nv == NVAR)
+        hipLaunchKernelGGL((k_source<R>), grid, dim3(256), 0, s, U, Q, n, plane, dt, sp, nsub);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, hipStream_t s)
+template <class R> hipError_t launch_init(R *U, const double *inflow, int nx, int nr, int nv, hipStream_t s)
 {
     const long n = (long)nx * nr;
-    hipLaunchKernelGGL((k_init<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, inflow, nx, nr);
+    if (nv != NVAR && nv != NVAR_BI) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_init<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, inflow, nx, nr, nv);
     return hipGetLastError();
 }
 
 template <class R>
-hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out, hipStream_t s)
+hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol, double *out, int nv, hipStream_t s)
 {
     const long n = (long)nx * nr;
+    if (nv != NVAR && nv != NVAR_BI) return hipErrorInvalidValue;
     int blocks = (int)std::min<long>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL((k_diag<R>), dim3(blocks), dim3(256), 0, s, U, plane, nx, nr, vol, out);
+    hipLaunchKernelGGL((k_diag<R>), dim3(blocks), dim3(256), 0, s, U, plane, nx, nr, vol, out, nv);
     return hipGetLastError();
 }
 
 #define CP_INSTANTIATE(R)                                                                                   \
-    template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, hipStream_t);                        \
+    template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, int, hipStream_t);                   \
     template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
     template hipError_t launch_sur_gate<R>(const SurArgs<R> &, long, hipStream_t);                           \
     template hipError_t launch_sur_finish<R>(const SurArgs<R> &, const SourceParams &, int *,                 \
                                              unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
-    template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, hipStream_t);                   \
+    template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, int, hipStream_t);              \
     template hipError_t launch_drift<R>(const DriftArgs<R> &, hipStream_t);                                  \
     template hipError_t launch_stage_batch<R>(const StageArgs<R> *, const int *, const int *, int, int, int,   \
                                               hipStream_t);                                                   \
     template hipError_t launch_source_fix_batch<R>(const SourceFixArgs<R> *, int, long, hipStream_t);        \
     template hipError_t launch_cfl_batch<R>(const CflArgs<R> *, int, long, hipStream_t);                     \
     template hipError_t launch_source<R>(const R *, R *, long, long, double, const SourceParams &,           \
-                                         unsigned long long *, hipStream_t);                                  \
-    template hipError_t launch_init<R>(R *, const double *, int, int, hipStream_t);                           \
-    template hipError_t launch_diag<R>(const R *, long, int, int, const double *, double *, hipStream_t);
+                                         unsigned long long *, int, hipStream_t);                             \
+    template hipError_t launch_init<R>(R *, const double *, int, int, int, hipStream_t);                      \
+    template hipError_t launch_diag<R>(const R *, long, int, int, const double *, double *, int, hipStream_t);
 
 CP_INSTANTIATE(double)
 CP_INSTANTIATE(float)

@@ -12,6 +12,9 @@
 namespace cp {
 
 constexpr int NVAR = 15;
+// With two liquid populations (Sec. 2.2) the homogeneously nucleated droplets take
+// four more variables, 15..18; the soot-activated ones keep 5..8.
+constexpr int NVAR_BI = 19;
 
 // -------------------------------------------------------------- constants
 // Calorically perfect carrier: dry-air pseudo-component (78/21/1 % N2/O2/Ar of the
@@ -226,19 +229,28 @@ __device__ __forceinline__ void cell_thermo(const double *U, CellThermo &c)
     c.p = c.rho * c.Rm * c.T;
 }
 
-struct Rates {
-    double dM[4], dN[4], act, mdot_f, Gl, Gs;
-    bool gone_l, gone_s;   // droplets / crystals left without mass (r20 below 1e-10 m)
+// Liquid moments of population pop: all droplets (one population) or the
+// soot-activated ones in 5..8; the homogeneously nucleated ones in 15..18.
+__device__ __forceinline__ constexpr int liq_base(int pop) { return pop ? 15 : 5; }
+
+template <int NP> struct Rates {
+    double dM[NP][4], dN[4], act, mdot_f, Gl[NP], Gs;
+    double F[NP][4];         // moments each liquid population loses to freezing
+    bool gone_l[NP], gone_s; // droplets / crystals left without mass (r20 below 1e-10 m)
 };
 
 // One evaluation of nucleation (Eq. 3-11), growth (Eq. 16, 21), freezing
-// (Eq. 12-15) and moment rates (Eq. 21); h bounds the activation rate.
+// (Eq. 12-15) and moment rates (Eq. 21) for NP liquid populations; h bounds the
+// activation rate.  With two populations the soot-activated droplets (population 0)
+// gain the activation rate and freeze by the homogeneous and immersion rates, the
+// homogeneously nucleated ones (population 1) gain the homogeneous rate and freeze
+// by the homogeneous rate alone (immersion needs a soot core).
+template <int NP>
 __device__ inline void phase_rates(const double *U, double h, const SourceParams &sp, const CellThermo &th,
-                                   Rates &r)
+                                   Rates<NP> &r)
 {
     const double T = th.T;
     const double rv = U[4];
-    const double M0 = U[5], M1 = U[6], M2 = U[7], M3 = U[8];
     const double N0 = U[9], N1 = U[10], N2 = U[11];
     const double Ns = U[13], Na = U[14];
 
@@ -253,7 +265,9 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
     const double lam = th.cpm * mu / kPr;
     const double lbar = 1.5 * mu * sqrt(th.Rm * T) / th.p;
 
-    double Jl = 0.0, rc = 0.0;
+    double J[NP], rc = 0.0;
+    #pragma unroll
+    for (int pop = 0; pop < NP; ++pop) J[pop] = 0.0;
     r.act = 0.0;
     if (lnSl > 0.0 && rv > 0.0) {
         rc = 2.0 * sig / (kRhoL * kRv * T * lnSl);                      // Eq. 3
@@ -262,79 +276,103 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
         const double phi = 2.0 * kQc * kGv / ((kGv + 1.0) * kCpv)
                            * (hfg * hfg / (kRv * T * T) - hfg / T);     // Eq. 5
         const double inv1p = 1.0 / (1.0 + phi);
-        Jl = K * exp(-x) * inv1p;
+        const double Jhom = K * exp(-x) * inv1p;
         if (Ns > Na) {                                                  // Eq. 10 on free soot
             double Jh = K * exp(-sp.f_theta * x) * inv1p;
             r.act = fmin(Jh, (Ns - Na) / h);
         }
-        Jl += r.act;
+        if constexpr (NP == 1) {
+            J[0] = Jhom;
+            J[0] += r.act;
+        } else {
+            J[0] = r.act;
+            J[1] = Jhom;
+        }
     }
 
-    r.Gl = 0.0;
     r.Gs = 0.0;
-    const bool liq = pop_valid(M0, M2, M3);
     const bool ice = pop_valid(N0, N2, U[12]);
-    r.gone_l = M0 > kNmin && !liq;
     r.gone_s = N0 > kNmin && !ice;
-    if (liq) {
-        double r20 = sqrt(M2 / M0);
-        double Ts = prop_tsat(sp, false, lnpv, T);
-        double dT = Ts - T;
-        double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
-                                          : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
-        r.Gl = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
-    }
     if (ice) {
         double r20 = sqrt(N2 / N0);
         double Ts = prop_tsat(sp, true, lnpv, T);
         r.Gs = young_G(lam, Ts - T, r20, kRhoS, hsg, young_nu(Ts, hsg), lbar);
     }
 
-    double F[4] = {0.0, 0.0, 0.0, 0.0};
     r.mdot_f = 0.0;
-    if (T < kTref && liq) {
-        double l2 = log(M2 / M0), l3 = log(M3 / M0);
-        double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
-        double lrg = 0.5 * l2 - s2;
-        double daw = 1.0 - exp(prop_lnp(sp, true, T) - lw);
-        daw = fmin(fmax(daw, 0.26), 0.34);
-        double lg = -906.7 + 8502.0 * daw - 26924.0 * daw * daw + 29180.0 * daw * daw * daw;
-        double Jf = 1.0e6 * exp(lg * 2.302585092994046) + sp.het_freeze * Ns;   // Eq. 12 + 14
-        double c = Jf * kFourThirdsPi;
-        F[0] = c * M3;
-        F[1] = c * M0 * exp(4.0 * lrg + 8.0 * s2);
-        F[2] = c * M0 * exp(5.0 * lrg + 12.5 * s2);
-        F[3] = c * M0 * exp(6.0 * lrg + 18.0 * s2);
-        r.mdot_f = kRhoL * kFourThirdsPi * F[3];
+    #pragma unroll
+    for (int pop = 0; pop < NP; ++pop) {
+        const double *M = U + liq_base(pop);
+        const double M0 = M[0], M1 = M[1], M2 = M[2], M3 = M[3];
+        const bool liq = pop_valid(M0, M2, M3);
+        r.gone_l[pop] = M0 > kNmin && !liq;
+        r.Gl[pop] = 0.0;
+        if (liq) {
+            double r20 = sqrt(M2 / M0);
+            double Ts = prop_tsat(sp, false, lnpv, T);
+            double dT = Ts - T;
+            double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
+                                              : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+            r.Gl[pop] = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
+        }
+        double *F = r.F[pop];
+        F[0] = F[1] = F[2] = F[3] = 0.0;
+        if (T < kTref && liq) {
+            double l2 = log(M2 / M0), l3 = log(M3 / M0);
+            double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
+            double lrg = 0.5 * l2 - s2;
+            double daw = 1.0 - exp(prop_lnp(sp, true, T) - lw);
+            daw = fmin(fmax(daw, 0.26), 0.34);
+            double lg = -906.7 + 8502.0 * daw - 26924.0 * daw * daw + 29180.0 * daw * daw * daw;
+            double Jf = 1.0e6 * exp(lg * 2.302585092994046);                           // Eq. 12
+            if (pop == 0) Jf += sp.het_freeze * Ns;                                      // Eq. 14
+            double c = Jf * kFourThirdsPi;
+            F[0] = c * M3;
+            F[1] = c * M0 * exp(4.0 * lrg + 8.0 * s2);
+            F[2] = c * M0 * exp(5.0 * lrg + 12.5 * s2);
+            F[3] = c * M0 * exp(6.0 * lrg + 18.0 * s2);
+            r.mdot_f += kRhoL * kFourThirdsPi * F[3];
+        }
+        const double Mm[3] = {M0, M1, M2};
+        double rk = 1.0;
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double gl = k ? k * Mm[k - 1] * r.Gl[pop] : 0.0;
+            r.dM[pop][k] = gl + J[pop] * rk - F[k];
+            rk *= rc;
+        }
     }
-
-    const double Mm[3] = {M0, M1, M2};
     const double Nm[3] = {N0, N1, N2};
-    double rk = 1.0;
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double gl = k ? k * Mm[k - 1] * r.Gl : 0.0;
         double gs = k ? k * Nm[k - 1] * r.Gs : 0.0;
-        r.dM[k] = gl + Jl * rk - F[k];
-        r.dN[k] = gs + sp.ice_ratio[k] * F[k];
-        rk *= rc;
+        double Ft = r.F[0][k];
+        if constexpr (NP == 2) Ft += r.F[1][k];
+        r.dN[k] = gs + sp.ice_ratio[k] * Ft;
     }
 }
 
 // Source vector from moment rates (Eq. 25-26 exchange): water exact to rounding.
-__device__ __forceinline__ void exchange(const CellThermo &th, const double *dM, const double *dN, double act,
+template <int NP>
+__device__ __forceinline__ void exchange(const CellThermo &th, const double (*dM)[4], const double *dN, double act,
                                          double mdot_f, double *S)
 {
     #pragma unroll
-    for (int k = 0; k < 4; ++k) { S[5 + k] = dM[k]; S[9 + k] = dN[k]; }
+    for (int k = 0; k < 4; ++k) {
+        S[5 + k] = dM[0][k];
+        S[9 + k] = dN[k];
+        if constexpr (NP == 2) S[15 + k] = dM[1][k];
+    }
     S[13] = 0.0;
     S[14] = act;
-    S[4] = -kFourThirdsPi * (kRhoL * S[8] + kRhoS * S[12]);
+    double liq3 = S[8];
+    if constexpr (NP == 2) liq3 += S[18];
+    S[4] = -kFourThirdsPi * (kRhoL * liq3 + kRhoS * S[12]);
     S[0] = S[4];
     S[1] = S[4] * th.u;
     S[2] = S[4] * th.v;
     const double T = th.T;
-    const double ml = kFourThirdsPi * kRhoL * S[8] + mdot_f;
+    const double ml = kFourThirdsPi * kRhoL * liq3 + mdot_f;
     const double ms = kFourThirdsPi * kRhoS * S[12] - mdot_f;
     const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
     const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
@@ -345,9 +383,11 @@ __device__ __forceinline__ void exchange(const CellThermo &th, const double *dM,
 
 // True when every phase-change rate vanishes identically at U (subsaturated
 // vapour, no droplets, no crystals): Q = 0 exactly, no sub-cycling needed.
-__device__ __forceinline__ bool source_inactive(const double *U, double T)
+template <int NV = NVAR> __device__ __forceinline__ bool source_inactive(const double *U, double T)
 {
     if (U[5] > kNmin || U[9] > kNmin) return false;
+    if constexpr (NV == NVAR_BI)
+        if (U[15] > kNmin) return false;
     if (!(U[4] > 0.0)) return true;
     double pv = fmax(U[4] * kRv * T, kPvFloor);
     return !(log(pv) - ln_psat(kSonW, T) > 0.0);
@@ -498,30 +538,39 @@ __device__ inline int source_equilibrium(const double *U, double dt, const Sourc
     return 1;
 }
 
+// Components whose depletion bounds the sub-step and the positivity scaling:
+// vapour, liquid and ice moments.
+__device__ __forceinline__ constexpr bool depletable(int c) { return (c >= 4 && c <= 12) || (c >= 15 && c <= 18); }
+
 // Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
 // scaling, complete evaporation / sublimation and the mu1 realisability clamp
-// (or by the equilibrium model when selected).  Returns the number of sub-steps
-// (0 when the cell is inactive).
+// (or by the equilibrium model when selected), for NV = NVAR (one liquid
+// population) or NVAR_BI (two).  Returns the number of sub-steps (0 when the cell
+// is inactive).
+template <int NV = NVAR>
 __device__ inline int source_integrate(const double *U0, double dt, const SourceParams &sp, double *Q)
 {
+    constexpr int NP = NV == NVAR_BI ? 2 : 1;
     #pragma unroll
-    for (int v = 0; v < NVAR; ++v) Q[v] = 0.0;
+    for (int v = 0; v < NV; ++v) Q[v] = 0.0;
     if (!sp.enabled) return 0;
-    if (sp.equilibrium) return source_equilibrium(U0, dt, sp, Q);
+    if constexpr (NV == NVAR)
+        if (sp.equilibrium) return source_equilibrium(U0, dt, sp, Q);
     CellThermo th;
     cell_thermo(U0, th);
-    if (source_inactive(U0, th.T)) return 0;
+    if (source_inactive<NV>(U0, th.T)) return 0;
 
-    double U[NVAR];
+    double U[NV];
     #pragma unroll
-    for (int v = 0; v < NVAR; ++v) U[v] = U0[v];
-    Rates r;
-    double S[NVAR];
-    phase_rates(U, dt, sp, th, r);
-    exchange(th, r.dM, r.dN, r.act, r.mdot_f, S);
+    for (int v = 0; v < NV; ++v) U[v] = U0[v];
+    Rates<NP> r;
+    double S[NV];
+    phase_rates<NP>(U, dt, sp, th, r);
+    exchange<NP>(th, r.dM, r.dN, r.act, r.mdot_f, S);
     double tau = __builtin_huge_val();
-    for (int c = 4; c <= 12; ++c)
-        if (S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
+    #pragma unroll
+    for (int c = 4; c < NV; ++c)
+        if (depletable(c) && S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
     int nsub = 1;
     if (tau < __builtin_huge_val()) {
         double want = ceil(dt / (kSubSafety * tau));
@@ -531,40 +580,62 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     const double h = dt / nsub;
     for (int s = 0; s < nsub; ++s) {
         if (s > 0) cell_thermo(U, th);
-        phase_rates(U, h, sp, th, r);
+        phase_rates<NP>(U, h, sp, th, r);
         double act = r.act, mdf = r.mdot_f;
-        bool el = false, es = false;
-        if (r.gone_l || (r.Gl < 0.0 && U[8] + h * r.dM[3] <= 0.0)) {
-            el = true;
-            #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                r.dM[k] = -U[5 + k] / h;
-                r.dN[k] = k ? k * U[8 + k] * r.Gs : 0.0;
+        bool el[NP], es = false, any_el = false;
+        #pragma unroll
+        for (int pop = 0; pop < NP; ++pop) {
+            const int b = liq_base(pop);
+            el[pop] = r.gone_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * r.dM[pop][3] <= 0.0);
+            if (el[pop]) {
+                // the whole population evaporates within the sub-step: none of it
+                // freezes; soot-activated droplets release their soot
+                #pragma unroll
+                for (int k = 0; k < 4; ++k) r.dM[pop][k] = -U[b + k] / h;
+                if (pop == 0) act = -U[14] / h;
+                any_el = true;
             }
+        }
+        if (any_el) {
+            // the crystals keep their growth and the freezing of a surviving population
             mdf = 0.0;
-            act = -U[14] / h;
+            #pragma unroll
+            for (int k = 0; k < 4; ++k) r.dN[k] = k ? k * U[8 + k] * r.Gs : 0.0;
+            #pragma unroll
+            for (int pop = 0; pop < NP; ++pop) {
+                if (el[pop]) continue;
+                #pragma unroll
+                for (int k = 0; k < 4; ++k) r.dN[k] += sp.ice_ratio[k] * r.F[pop][k];
+                mdf += kRhoL * kFourThirdsPi * r.F[pop][3];
+            }
         }
         if (r.gone_s || (r.Gs < 0.0 && U[12] + h * r.dN[3] <= 0.0)) {
             es = true;
             #pragma unroll
             for (int k = 0; k < 4; ++k) r.dN[k] = -U[9 + k] / h;
         }
-        exchange(th, r.dM, r.dN, act, mdf, S);
+        exchange<NP>(th, r.dM, r.dN, act, mdf, S);
         // positivity scaling; components of an evaporating population reach zero at
         // theta = 1 exactly and do not take part
         double theta = 1.0;
-        for (int c = 4; c <= 12; ++c) {
-            const bool skip = (el && c >= 5 && c <= 8) || (es && c >= 9);
+        #pragma unroll
+        for (int c = 4; c < NV; ++c) {
+            if (!depletable(c)) continue;
+            bool skip = (el[0] && c >= 5 && c <= 8) || (es && c >= 9 && c <= 12);
+            if constexpr (NP == 2) skip = skip || (el[1] && c >= 15);
             if (!skip && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
         }
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) U[v] = U[v] + theta * h * S[v];
+        for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];
         if (theta == 1.0) {
-            if (el) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if (el[0]) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if constexpr (NP == 2)
+                if (el[1]) { U[15] = U[16] = U[17] = U[18] = 0.0; }
             if (es) { U[9] = U[10] = U[11] = U[12] = 0.0; }
         }
         #pragma unroll
-        for (int b = 5; b <= 9; b += 4) {
+        for (int set = 0; set < NP + 1; ++set) {
+            const int b = set == 0 ? 5 : (set == 1 ? 9 : 15);
             if (pop_valid(U[b], U[b + 2], U[b + 3])) {
                 // Hoelder interval for mu1; an empty interval collapses to its upper end
                 double hi = sqrt(U[b] * U[b + 2]);
@@ -574,7 +645,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
         }
     }
     #pragma unroll
-    for (int v = 0; v < NVAR; ++v) Q[v] = (U[v] - U0[v]) / dt;
+    for (int v = 0; v < NV; ++v) Q[v] = (U[v] - U0[v]) / dt;
     return nsub;
 }
 

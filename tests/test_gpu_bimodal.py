@@ -1,0 +1,186 @@
+"""Two liquid populations (cp_set_bimodal, the bimodal moments of Sec. 2.2) on the
+GPU against the FP64 oracle's two-population model.
+
+* residual on a state holding both populations: 1e-10 of each variable's size
+  (the residual parity bar), the second set included;
+* the source on 20000 random realisable cells with both populations, end states
+  U + dt Q within 1e-9 of |U| + |dt Q| (the source parity bar), at the
+  production step and at a stiff one;
+* 200 FP64 steps of the source-active jet: per-variable relative L2 <= 1e-9 (the
+  FP64 gate), and the diagnostics' water total (both populations) as the oracle's;
+* the mixed path after 300 steps: gas state <= 1e-4, ice mu0 <= 2e-2 (the mixed
+  gates);
+* without soot the GPU's two-population run is its one-population run with the
+  liquid in 15..18 (to 1e-12);
+* the switches that have one liquid population refuse it.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_20742_amd import inputs
+from tests.test_gpu_parity import _cells, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_20742_amd import binding
+    binding.load()
+    return binding
+
+
+def _oracle(orc, m, c):
+    o = orc.Oracle(m, c)
+    o.set_bimodal(True)
+    return o
+
+
+def _solver(B, m, c, prec=None):
+    s = B.Solver(m, c, B.CP_FP64 if prec is None else prec)
+    s.set_bimodal(True)
+    assert s.nv == 19
+    return s
+
+
+@pytest.fixture(scope="module")
+def state(orc):
+    """The source-active jet after 150 two-population oracle steps: both droplet
+    populations and crystals exist."""
+    m, c = inputs.sa1(2)
+    o = _oracle(orc, m, c)
+    U = o.init()
+    o.run(U, 150)
+    assert (U[5] > 1.0).sum() > 50 and (U[15] > 1.0).sum() > 20 and (U[9] > 1.0).sum() > 10
+    return m, c, U
+
+
+def test_bimodal_residual(B, orc, state):
+    m, c, U = state
+    o = _oracle(orc, m, c)
+    s = _solver(B, m, c)
+    R = host(s.residual(dev(U)))
+    Ro = o.residual(U)
+    assert R.shape == (19,) + U.shape[1:]
+    for v in range(19):
+        scale = np.abs(Ro[v]).max() + 1e-300
+        err = np.abs(R[v] - Ro[v]).max() / scale
+        assert err < 1e-10, (v, err)
+    s.close()
+
+
+def test_bimodal_source_random_states(B, orc):
+    nx, nr = 200, 100
+    n = nx * nr
+    U15 = _cells(orc, n, seed=31)
+    hom = inputs.random_cells(n, seed=32)["liq"]
+    U = np.concatenate([U15, hom]).reshape(19, nr, nx)
+    m, c = inputs.mesh(nx, nr), inputs.case()
+    o = _oracle(orc, m, c)
+    s = _solver(B, m, c)
+    for dt, tol in ((1e-7, 1e-9), (1e-5, 1e-6)):
+        Qo = o.source(U, dt)
+        Q = host(s.source(dev(U), dt))
+        err = np.abs(dt * (Q - Qo)) / (np.abs(U) + np.abs(dt * Qo) + 1e-300)
+        active = np.any(Qo[15:19] != 0, axis=0).sum()
+        print("two populations, dt %.0e: %d cells with a homogeneous-droplet source, max rel error %.2e"
+              % (dt, active, err.max()))
+        assert active > 1000
+        assert err.max() <= tol, dt
+    s.close()
+
+
+def test_bimodal_200_steps_fp64(B, orc):
+    m, c = inputs.sa1(1)
+    o = _oracle(orc, m, c)
+    Uo = o.init()
+    to = o.run(Uo, 200)
+    s = _solver(B, m, c)
+    U = s.init()
+    t = s.step_n(U, 200)
+    assert t == pytest.approx(to, rel=1e-12)
+    Ug = host(U)
+    e = rel_l2(Ug, Uo)
+    print("two populations, 200 FP64 steps: max per-variable rel L2 %.2e; homogeneous number %.3e"
+          % (e.max(), Uo[15].sum()))
+    assert Uo[15].max() > 0 and Uo[5].max() > 0
+    assert (e <= 1e-9).all(), e
+    wg, wo = s.diag(U)["water"], o.diag(Uo)["water"]
+    assert wg == pytest.approx(wo, rel=1e-9)
+    s.close()
+
+
+def test_bimodal_mixed(B, orc):
+    steps = 300
+    m, c = inputs.sa1(1)
+    o = _oracle(orc, m, c)
+    Uo = o.init()
+    o.run(Uo, steps)
+    s = _solver(B, m, c, B.CP_MIXED)
+    U = s.init()
+    s.step_n(U, steps)
+    Ug = host(U)
+    gas = max(rel_l2(Ug[[0, 3, 4]], Uo[[0, 3, 4]]).max(),
+              np.sqrt(np.sum((Ug[1:3] - Uo[1:3]) ** 2) / np.sum(Uo[1:3] ** 2)))
+    ice = rel_l2(Ug[9:10], Uo[9:10])[0]
+    hom = rel_l2(Ug[15:16], Uo[15:16])[0]
+    print("mixed, two populations, vs FP64 oracle after %d steps: gas %.2e, ice mu0 %.2e, "
+          "homogeneous droplet mu0 %.2e" % (steps, gas, ice, hom))
+    assert gas <= 1e-4 and ice <= 2e-2
+    s.close()
+
+
+def test_bimodal_no_soot_is_one_population(B):
+    m, c = inputs.sa1(1, n_soot=0.0)
+    s1 = B.Solver(m, c)
+    U1 = s1.init()
+    s1.step_n(U1, 150)
+    s2 = _solver(B, m, c)
+    U2 = s2.init()
+    s2.step_n(U2, 150)
+    A, Bb = host(U1), host(U2)
+    assert A[5].max() > 0
+    assert np.all(Bb[5:9] == 0.0)
+    keep = [0, 1, 2, 3, 4, 9, 10, 11, 12, 13, 14]
+    e1 = rel_l2(Bb[15:19], A[5:9])
+    e2 = rel_l2(Bb[keep], A[keep])
+    print("no soot: two-population run vs one-population run, max rel L2 %.2e / %.2e" % (e1.max(), e2.max()))
+    assert (e1 <= 1e-12).all() and (e2 <= 1e-12).all()
+    s1.close()
+    s2.close()
+
+
+def test_bimodal_refusals(B):
+    m, c = inputs.sa1(1)
+    s = B.Solver(m, c)
+    s.set_drift(True)
+    with pytest.raises(B.ContrailError) as e:
+        s.set_bimodal(True)
+    assert e.value.code == B.CP_EUNSUPPORTED
+    s.set_drift(False)
+    s.set_qmode(B.CP_Q_EQUILIBRIUM)
+    with pytest.raises(B.ContrailError) as e:
+        s.set_bimodal(True)
+    assert e.value.code == B.CP_EUNSUPPORTED
+    s.set_qmode(B.CP_Q_EXACT)
+    s.set_bimodal(True)
+    for call in (lambda: s.set_drift(True), lambda: s.set_qmode(B.CP_Q_EQUILIBRIUM),
+                 lambda: s.set_tile(16, 16)):
+        with pytest.raises(B.ContrailError) as e:
+            call()
+        assert e.value.code == B.CP_EUNSUPPORTED
+    s.set_tile(32, 8)
+    s.set_bimodal(False)
+    assert s.nv == 15
+    s.close()
+    md = inputs.mesh(16, 1, geom=inputs.GEOM_QUASI1D,
+                     bc=(inputs.BC_INFLOW, inputs.BC_COPY, inputs.BC_WALL, inputs.BC_WALL))
+    md["area_x"] = np.ones(17)
+    d = B.Solver(md, inputs.case(phase_change=0))
+    with pytest.raises(B.ContrailError) as e:
+        d.set_bimodal(True)
+    assert e.value.code == B.CP_EUNSUPPORTED
+    d.close()
