@@ -641,7 +641,7 @@ __device__ __forceinline__ void source_fix_body(const SourceFixArgs<R> &a, int b
         double Ud[NV], Q[NV];
         #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)a.Uin[v * a.plane + c];
-        ns += source_integrate<NV>(Ud, dt, a.sp, Q);
+        ns += source_integrate_nv<NV>(Ud, dt, a.sp, Q);
         R uo[NV];   // all loads before the stores (possible aliasing serialises them)
         #pragma unroll
         for (int v = 0; v < NV; ++v) uo[v] = a.Uout[v * a.plane + c];
@@ -1326,7 +1326,7 @@ __global__ void __launch_bounds__(256) k_source(const R *U, R *Q, long n, long p
         double Ud[NV], Qd[NV];
         #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)U[v * plane + c];
-        ns = source_integrate<NV>(Ud, dt, sp, Qd);
+        ns = source_integrate_nv<NV>(Ud, dt, sp, Qd);
         #pragma unroll
         for (int v = 0; v < NV; ++v) Q[v * plane + c] = (R)Qd[v];
     }

@@ -229,25 +229,146 @@ __device__ __forceinline__ void cell_thermo(const double *U, CellThermo &c)
     c.p = c.rho * c.Rm * c.T;
 }
 
-// Liquid moments of population pop: all droplets (one population) or the
-// soot-activated ones in 5..8; the homogeneously nucleated ones in 15..18.
+struct Rates {
+    double dM[4], dN[4], act, mdot_f, Gl, Gs;
+    bool gone_l, gone_s;   // droplets / crystals left without mass (r20 below 1e-10 m)
+};
+
+// One evaluation of nucleation (Eq. 3-11), growth (Eq. 16, 21), freezing
+// (Eq. 12-15) and moment rates (Eq. 21); h bounds the activation rate.
+__device__ inline void phase_rates(const double *U, double h, const SourceParams &sp, const CellThermo &th,
+                                   Rates &r)
+{
+    const double T = th.T;
+    const double rv = U[4];
+    const double M0 = U[5], M1 = U[6], M2 = U[7], M3 = U[8];
+    const double N0 = U[9], N1 = U[10], N2 = U[11];
+    const double Ns = U[13], Na = U[14];
+
+    double pv = fmax(rv * kRv * T, kPvFloor);
+    const double lnpv = log(pv);
+    const double lw = prop_lnp(sp, false, T);
+    const double lnSl = lnpv - lw;
+    const double sig = prop_sigma(sp, T);
+    const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+    const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+    const double mu = sutherland<double>(T);
+    const double lam = th.cpm * mu / kPr;
+    const double lbar = 1.5 * mu * sqrt(th.Rm * T) / th.p;
+
+    double Jl = 0.0, rc = 0.0;
+    r.act = 0.0;
+    if (lnSl > 0.0 && rv > 0.0) {
+        rc = 2.0 * sig / (kRhoL * kRv * T * lnSl);                      // Eq. 3
+        const double x = kFourThirdsPi * sig * rc * rc / (kKb * T);     // dG*/kT
+        const double K = sp.cnt_const * sqrt(sig) * rv * rv;            // Eq. 4
+        const double phi = 2.0 * kQc * kGv / ((kGv + 1.0) * kCpv)
+                           * (hfg * hfg / (kRv * T * T) - hfg / T);     // Eq. 5
+        const double inv1p = 1.0 / (1.0 + phi);
+        Jl = K * exp(-x) * inv1p;
+        if (Ns > Na) {                                                  // Eq. 10 on free soot
+            double Jh = K * exp(-sp.f_theta * x) * inv1p;
+            r.act = fmin(Jh, (Ns - Na) / h);
+        }
+        Jl += r.act;
+    }
+
+    r.Gl = 0.0;
+    r.Gs = 0.0;
+    const bool liq = pop_valid(M0, M2, M3);
+    const bool ice = pop_valid(N0, N2, U[12]);
+    r.gone_l = M0 > kNmin && !liq;
+    r.gone_s = N0 > kNmin && !ice;
+    if (liq) {
+        double r20 = sqrt(M2 / M0);
+        double Ts = prop_tsat(sp, false, lnpv, T);
+        double dT = Ts - T;
+        double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
+                                          : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+        r.Gl = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
+    }
+    if (ice) {
+        double r20 = sqrt(N2 / N0);
+        double Ts = prop_tsat(sp, true, lnpv, T);
+        r.Gs = young_G(lam, Ts - T, r20, kRhoS, hsg, young_nu(Ts, hsg), lbar);
+    }
+
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    r.mdot_f = 0.0;
+    if (T < kTref && liq) {
+        double l2 = log(M2 / M0), l3 = log(M3 / M0);
+        double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
+        double lrg = 0.5 * l2 - s2;
+        double daw = 1.0 - exp(prop_lnp(sp, true, T) - lw);
+        daw = fmin(fmax(daw, 0.26), 0.34);
+        double lg = -906.7 + 8502.0 * daw - 26924.0 * daw * daw + 29180.0 * daw * daw * daw;
+        double Jf = 1.0e6 * exp(lg * 2.302585092994046) + sp.het_freeze * Ns;   // Eq. 12 + 14
+        double c = Jf * kFourThirdsPi;
+        F[0] = c * M3;
+        F[1] = c * M0 * exp(4.0 * lrg + 8.0 * s2);
+        F[2] = c * M0 * exp(5.0 * lrg + 12.5 * s2);
+        F[3] = c * M0 * exp(6.0 * lrg + 18.0 * s2);
+        r.mdot_f = kRhoL * kFourThirdsPi * F[3];
+    }
+
+    const double Mm[3] = {M0, M1, M2};
+    const double Nm[3] = {N0, N1, N2};
+    double rk = 1.0;
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double gl = k ? k * Mm[k - 1] * r.Gl : 0.0;
+        double gs = k ? k * Nm[k - 1] * r.Gs : 0.0;
+        r.dM[k] = gl + Jl * rk - F[k];
+        r.dN[k] = gs + sp.ice_ratio[k] * F[k];
+        rk *= rc;
+    }
+}
+
+// Source vector from moment rates (Eq. 25-26 exchange): water exact to rounding.
+__device__ __forceinline__ void exchange(const CellThermo &th, const double *dM, const double *dN, double act,
+                                         double mdot_f, double *S)
+{
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) { S[5 + k] = dM[k]; S[9 + k] = dN[k]; }
+    S[13] = 0.0;
+    S[14] = act;
+    S[4] = -kFourThirdsPi * (kRhoL * S[8] + kRhoS * S[12]);
+    S[0] = S[4];
+    S[1] = S[4] * th.u;
+    S[2] = S[4] * th.v;
+    const double T = th.T;
+    const double ml = kFourThirdsPi * kRhoL * S[8] + mdot_f;
+    const double ms = kFourThirdsPi * kRhoS * S[12] - mdot_f;
+    const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
+    const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
+    const double hv = kLv0 + kCpv * (T - kTref);
+    const double ke = 0.5 * (th.u * th.u + th.v * th.v);
+    S[3] = -ml * (hv - hfg + ke) - ms * (hv - hsg + ke) + mdot_f * (hsg - hfg);
+}
+
+
+// Two liquid populations (the bimodal moments of Sec. 2.2): the soot-activated
+// droplets in 5..8 (population 0), the homogeneously nucleated ones in 15..18
+// (population 1).  The one-population functions above are kept as their own code:
+// folding them into these templates (NP = 1) made the table-driven source 7 %
+// slower on the GPU.
 __device__ __forceinline__ constexpr int liq_base(int pop) { return pop ? 15 : 5; }
 
-template <int NP> struct Rates {
+template <int NP> struct RatesN {
     double dM[NP][4], dN[4], act, mdot_f, Gl[NP], Gs;
     double F[NP][4];         // moments each liquid population loses to freezing
     bool gone_l[NP], gone_s; // droplets / crystals left without mass (r20 below 1e-10 m)
 };
 
 // One evaluation of nucleation (Eq. 3-11), growth (Eq. 16, 21), freezing
-// (Eq. 12-15) and moment rates (Eq. 21) for NP liquid populations; h bounds the
-// activation rate.  With two populations the soot-activated droplets (population 0)
+// (Eq. 12-15) and moment rates (Eq. 21) for NP liquid populations (used with NP = 2);
+// h bounds the activation rate.  The soot-activated droplets (population 0)
 // gain the activation rate and freeze by the homogeneous and immersion rates, the
 // homogeneously nucleated ones (population 1) gain the homogeneous rate and freeze
 // by the homogeneous rate alone (immersion needs a soot core).
 template <int NP>
-__device__ inline void phase_rates(const double *U, double h, const SourceParams &sp, const CellThermo &th,
-                                   Rates<NP> &r)
+__device__ inline void phase_rates_n(const double *U, double h, const SourceParams &sp, const CellThermo &th,
+                                     RatesN<NP> &r)
 {
     const double T = th.T;
     const double rv = U[4];
@@ -290,6 +411,23 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
         }
     }
 
+    // growth (Eq. 16, 21) of each droplet population, then of the crystals
+    bool liq[NP];
+    #pragma unroll
+    for (int pop = 0; pop < NP; ++pop) {
+        const double *M = U + liq_base(pop);
+        liq[pop] = pop_valid(M[0], M[2], M[3]);
+        r.gone_l[pop] = M[0] > kNmin && !liq[pop];
+        r.Gl[pop] = 0.0;
+        if (liq[pop]) {
+            double r20 = sqrt(M[2] / M[0]);
+            double Ts = prop_tsat(sp, false, lnpv, T);
+            double dT = Ts - T;
+            double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
+                                              : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+            r.Gl[pop] = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
+        }
+    }
     r.Gs = 0.0;
     const bool ice = pop_valid(N0, N2, U[12]);
     r.gone_s = N0 > kNmin && !ice;
@@ -299,25 +437,15 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
         r.Gs = young_G(lam, Ts - T, r20, kRhoS, hsg, young_nu(Ts, hsg), lbar);
     }
 
+    // freezing (Eq. 12-15) and the moment rates (Eq. 21) of each droplet population
     r.mdot_f = 0.0;
     #pragma unroll
     for (int pop = 0; pop < NP; ++pop) {
         const double *M = U + liq_base(pop);
         const double M0 = M[0], M1 = M[1], M2 = M[2], M3 = M[3];
-        const bool liq = pop_valid(M0, M2, M3);
-        r.gone_l[pop] = M0 > kNmin && !liq;
-        r.Gl[pop] = 0.0;
-        if (liq) {
-            double r20 = sqrt(M2 / M0);
-            double Ts = prop_tsat(sp, false, lnpv, T);
-            double dT = Ts - T;
-            double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
-                                              : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
-            r.Gl[pop] = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
-        }
         double *F = r.F[pop];
         F[0] = F[1] = F[2] = F[3] = 0.0;
-        if (T < kTref && liq) {
+        if (T < kTref && liq[pop]) {
             double l2 = log(M2 / M0), l3 = log(M3 / M0);
             double s2 = fmax(2.0 / 3.0 * l3 - l2, 0.0);
             double lrg = 0.5 * l2 - s2;
@@ -354,8 +482,8 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
 
 // Source vector from moment rates (Eq. 25-26 exchange): water exact to rounding.
 template <int NP>
-__device__ __forceinline__ void exchange(const CellThermo &th, const double (*dM)[4], const double *dN, double act,
-                                         double mdot_f, double *S)
+__device__ __forceinline__ void exchange_n(const CellThermo &th, const double (*dM)[4], const double *dN, double act,
+                                           double mdot_f, double *S)
 {
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -538,24 +666,101 @@ __device__ inline int source_equilibrium(const double *U, double dt, const Sourc
     return 1;
 }
 
+// Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
+// scaling, complete evaporation / sublimation and the mu1 realisability clamp
+// (or by the equilibrium model when selected).  Returns the number of sub-steps
+// (0 when the cell is inactive).
+__device__ inline int source_integrate(const double *U0, double dt, const SourceParams &sp, double *Q)
+{
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Q[v] = 0.0;
+    if (!sp.enabled) return 0;
+    if (sp.equilibrium) return source_equilibrium(U0, dt, sp, Q);
+    CellThermo th;
+    cell_thermo(U0, th);
+    if (source_inactive(U0, th.T)) return 0;
+
+    double U[NVAR];
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) U[v] = U0[v];
+    Rates r;
+    double S[NVAR];
+    phase_rates(U, dt, sp, th, r);
+    exchange(th, r.dM, r.dN, r.act, r.mdot_f, S);
+    double tau = __builtin_huge_val();
+    for (int c = 4; c <= 12; ++c)
+        if (S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
+    int nsub = 1;
+    if (tau < __builtin_huge_val()) {
+        double want = ceil(dt / (kSubSafety * tau));
+        if (want > (double)sp.n_sub_max) nsub = sp.n_sub_max;
+        else if (want > 1.0) nsub = (int)want;
+    }
+    const double h = dt / nsub;
+    for (int s = 0; s < nsub; ++s) {
+        if (s > 0) cell_thermo(U, th);
+        phase_rates(U, h, sp, th, r);
+        double act = r.act, mdf = r.mdot_f;
+        bool el = false, es = false;
+        if (r.gone_l || (r.Gl < 0.0 && U[8] + h * r.dM[3] <= 0.0)) {
+            el = true;
+            #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.dM[k] = -U[5 + k] / h;
+                r.dN[k] = k ? k * U[8 + k] * r.Gs : 0.0;
+            }
+            mdf = 0.0;
+            act = -U[14] / h;
+        }
+        if (r.gone_s || (r.Gs < 0.0 && U[12] + h * r.dN[3] <= 0.0)) {
+            es = true;
+            #pragma unroll
+            for (int k = 0; k < 4; ++k) r.dN[k] = -U[9 + k] / h;
+        }
+        exchange(th, r.dM, r.dN, act, mdf, S);
+        // positivity scaling; components of an evaporating population reach zero at
+        // theta = 1 exactly and do not take part
+        double theta = 1.0;
+        for (int c = 4; c <= 12; ++c) {
+            const bool skip = (el && c >= 5 && c <= 8) || (es && c >= 9);
+            if (!skip && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+        }
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) U[v] = U[v] + theta * h * S[v];
+        if (theta == 1.0) {
+            if (el) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
+            if (es) { U[9] = U[10] = U[11] = U[12] = 0.0; }
+        }
+        #pragma unroll
+        for (int b = 5; b <= 9; b += 4) {
+            if (pop_valid(U[b], U[b + 2], U[b + 3])) {
+                // Hoelder interval for mu1; an empty interval collapses to its upper end
+                double hi = sqrt(U[b] * U[b + 2]);
+                double lo = fmin(U[b + 2] * U[b + 2] / U[b + 3], hi);
+                U[b + 1] = fmin(fmax(U[b + 1], lo), hi);
+            }
+        }
+    }
+    #pragma unroll
+    for (int v = 0; v < NVAR; ++v) Q[v] = (U[v] - U0[v]) / dt;
+    return nsub;
+}
+
+
 // Components whose depletion bounds the sub-step and the positivity scaling:
 // vapour, liquid and ice moments.
 __device__ __forceinline__ constexpr bool depletable(int c) { return (c >= 4 && c <= 12) || (c >= 15 && c <= 18); }
 
-// Q(U, dt) = (Phi_dt(U) - U) / dt by explicit sub-cycling with positivity
-// scaling, complete evaporation / sublimation and the mu1 realisability clamp
-// (or by the equilibrium model when selected), for NV = NVAR (one liquid
-// population) or NVAR_BI (two).  Returns the number of sub-steps (0 when the cell
-// is inactive).
-template <int NV = NVAR>
-__device__ inline int source_integrate(const double *U0, double dt, const SourceParams &sp, double *Q)
+// The same integration with two liquid populations (NV = NVAR_BI): each population
+// has its own complete-evaporation rule, positivity exclusion and mu1 clamp; the
+// crystals keep the freezing of a population that survives the sub-step.
+template <int NV>
+__device__ inline int source_integrate_n(const double *U0, double dt, const SourceParams &sp, double *Q)
 {
     constexpr int NP = NV == NVAR_BI ? 2 : 1;
     #pragma unroll
     for (int v = 0; v < NV; ++v) Q[v] = 0.0;
     if (!sp.enabled) return 0;
-    if constexpr (NV == NVAR)
-        if (sp.equilibrium) return source_equilibrium(U0, dt, sp, Q);
     CellThermo th;
     cell_thermo(U0, th);
     if (source_inactive<NV>(U0, th.T)) return 0;
@@ -563,10 +768,10 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     double U[NV];
     #pragma unroll
     for (int v = 0; v < NV; ++v) U[v] = U0[v];
-    Rates<NP> r;
+    RatesN<NP> r;
     double S[NV];
-    phase_rates<NP>(U, dt, sp, th, r);
-    exchange<NP>(th, r.dM, r.dN, r.act, r.mdot_f, S);
+    phase_rates_n<NP>(U, dt, sp, th, r);
+    exchange_n<NP>(th, r.dM, r.dN, r.act, r.mdot_f, S);
     double tau = __builtin_huge_val();
     #pragma unroll
     for (int c = 4; c < NV; ++c)
@@ -580,7 +785,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     const double h = dt / nsub;
     for (int s = 0; s < nsub; ++s) {
         if (s > 0) cell_thermo(U, th);
-        phase_rates<NP>(U, h, sp, th, r);
+        phase_rates_n<NP>(U, h, sp, th, r);
         double act = r.act, mdf = r.mdot_f;
         bool el[NP], es = false, any_el = false;
         #pragma unroll
@@ -601,12 +806,14 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
             mdf = 0.0;
             #pragma unroll
             for (int k = 0; k < 4; ++k) r.dN[k] = k ? k * U[8 + k] * r.Gs : 0.0;
-            #pragma unroll
-            for (int pop = 0; pop < NP; ++pop) {
-                if (el[pop]) continue;
+            if constexpr (NP == 2) {   // with one population nothing survives
                 #pragma unroll
-                for (int k = 0; k < 4; ++k) r.dN[k] += sp.ice_ratio[k] * r.F[pop][k];
-                mdf += kRhoL * kFourThirdsPi * r.F[pop][3];
+                for (int pop = 0; pop < NP; ++pop) {
+                    if (el[pop]) continue;
+                    #pragma unroll
+                    for (int k = 0; k < 4; ++k) r.dN[k] += sp.ice_ratio[k] * r.F[pop][k];
+                    mdf += kRhoL * kFourThirdsPi * r.F[pop][3];
+                }
             }
         }
         if (r.gone_s || (r.Gs < 0.0 && U[12] + h * r.dN[3] <= 0.0)) {
@@ -614,7 +821,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
             #pragma unroll
             for (int k = 0; k < 4; ++k) r.dN[k] = -U[9 + k] / h;
         }
-        exchange<NP>(th, r.dM, r.dN, act, mdf, S);
+        exchange_n<NP>(th, r.dM, r.dN, act, mdf, S);
         // positivity scaling; components of an evaporating population reach zero at
         // theta = 1 exactly and do not take part
         double theta = 1.0;
@@ -647,6 +854,14 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     #pragma unroll
     for (int v = 0; v < NV; ++v) Q[v] = (U[v] - U0[v]) / dt;
     return nsub;
+}
+
+// Q(U, dt) for NV variables per cell: NVAR (one liquid population) or NVAR_BI (two).
+template <int NV> __device__ __forceinline__ int source_integrate_nv(const double *U0, double dt,
+                                                                      const SourceParams &sp, double *Q)
+{
+    if constexpr (NV == NVAR) return source_integrate(U0, dt, sp, Q);
+    else return source_integrate_n<NV>(U0, dt, sp, Q);
 }
 
 // ======================================================================
