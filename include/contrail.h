@@ -163,11 +163,14 @@ int cp_step_n(cp_ctx *ctx, void *U, int n, double *t_host);
  * condensate changes only once supersaturated over liquid.  Particle numbers are
  * kept (new condensate sits on the soot, or on 0.1 um particles without soot), each
  * population monodisperse at its mean-mass radius.  Computed in FP64 for both
- * precisions.  Errors: CP_EINVAL for an unknown mode, CP_ESTATE (see above).       */
+ * precisions.  Errors: CP_EINVAL for an unknown mode, CP_ESTATE (see above),
+ * CP_EUNSUPPORTED for CP_Q_SURROGATE or CP_Q_EQUILIBRIUM with two liquid
+ * populations (cp_set_bimodal).                                                  */
 int cp_set_qmode(cp_ctx *ctx, int qmode);
 
 /* Diagnostics (synchronises): out[0] total water mass per radian
- * (vapour + 4pi/3 (rho_l M3 + rho_s N3), Eq. 25-26), out[1] max ln S_l (Eq. 1),
+ * (vapour + 4pi/3 (rho_l M3 + rho_s N3), Eq. 25-26, both liquid populations with
+ * cp_set_bimodal), out[1] max ln S_l (Eq. 1),
  * out[2] total ice number, out[3] gas mass, out[4] cells with an active source,
  * out[5] sub-steps of the exact source since the last cp_source call (that call
  * and every later step included), out[6] and out[7] running
@@ -184,7 +187,8 @@ int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
  * moment k crosses a face with w(r20) M_k, upwind in its sign (the moment set
  * stays realisable).  Soot stays with the gas.  Applied
  * in every stage (and cp_residual) by a pass after the stage kernel, in FP64.
- * Off by default.  Errors: CP_EUNSUPPORTED in the quasi-1D duct.                   */
+ * Off by default.  Errors: CP_EUNSUPPORTED in the quasi-1D duct and with two
+ * liquid populations (cp_set_bimodal).                                           */
 int cp_set_drift(cp_ctx *ctx, int on);
 
 /* Water properties of the phase-change source (ln p_sat over liquid and ice, the
@@ -219,7 +223,8 @@ int cp_set_bimodal(cp_ctx *ctx, int on);
 int cp_nvar(const cp_ctx *ctx);
 
 /* Tile shape of the stage kernel: (tx, ty) from the built set, or (0, 0) to run the
- * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built.     */
+ * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built (with
+ * two liquid populations only 32 x 8 is built).                                  */
 int cp_set_tile(cp_ctx *ctx, int tx, int ty);
 int cp_get_tile(const cp_ctx *ctx, int *tx, int *ty);
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcontrail.so")
-SOURCES = ["cp_kernels.hip", "cp_api.hip", "cp_batch.hip", "cp_mlp.hip"]
+SOURCES = ["cp_kernels.hip", "cp_api.hip", "cp_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
