@@ -107,6 +107,33 @@ def config4(seed=0, nplumes=64):
     return out
 
 
+def particle_fields(nr, nx, seed=0, frac=0.05):
+    """Seeded particle moments per m^3 on a random fraction of the cells of an
+    nr x nx mesh: soot-activated droplets, homogeneously nucleated droplets and
+    crystals, each from lognormal draws (N, r_g, sigma_g), so every set is
+    realisable.  Returned as arrays of shape (4, nr, nx)."""
+    g = _rng(seed)
+    n = nr * nx
+
+    def lognormal_moments(has, lo, hi):
+        N = np.where(has, 10.0 ** g.uniform(6.0, 11.0, n), 0.0)
+        rg = 10.0 ** g.uniform(lo, hi, n)
+        sg = g.uniform(1.05, 1.8, n)
+        s2 = np.log(sg) ** 2
+        return np.stack([N * np.exp(k * np.log(rg) + 0.5 * k * k * s2) for k in range(4)]).reshape(4, nr, nx)
+
+    het = lognormal_moments(g.uniform(size=n) < frac, -7.5, -6.3)
+    hom = lognormal_moments(g.uniform(size=n) < frac, -8.5, -7.0)
+    ice = lognormal_moments(g.uniform(size=n) < 0.5 * frac, -7.0, -6.0)
+    return het, hom, ice
+
+
+def velocity_noise(nr, nx, seed=0, amp=5.0):
+    """Seeded uniform noise in [-amp, amp] (m/s) on an nr x nx mesh, to stir a
+    state that is uniform along x so that every face carries a flux."""
+    return _rng(seed).uniform(-amp, amp, (nr, nx))
+
+
 def random_cells(n, seed=0, active=True):
     """Primitive cell states (rho, u, v, p, Y, mu-moments per mass, soot) spanning the
     paper's regimes; returned as a dict of arrays.  Moments come from lognormal draws

@@ -12,7 +12,10 @@ GPU against the FP64 oracle's two-population model.
   gates);
 * without soot the GPU's two-population run is its one-population run with the
   liquid in 15..18 (to 1e-12);
-* the switches that have one liquid population refuse it.
+* the switches that have one liquid population refuse it;
+* at the full 2048 x 512 size (the benchmark's launch configuration), seeded with
+  both populations: residual and every cell's source;
+* with the property tables: 200 FP64 steps against the oracle's own table.
 """
 import numpy as np
 import pytest
@@ -184,3 +187,60 @@ def test_bimodal_refusals(B):
         d.set_bimodal(True)
     assert e.value.code == B.CP_EUNSUPPORTED
     d.close()
+
+
+def test_bimodal_full_size(B, orc):
+    """The source-active production jet at its full 2048 x 512 size in the launch
+    configuration the benchmark times (32 x 8 tile), seeded with droplets of both
+    populations and crystals on 5 % of the cells and stirred by a seeded radial
+    velocity of a few m/s: the residual over the whole mesh
+    (1e-10 of each variable's size) and the source of every cell (1e-9 of
+    |U| + |dt Q|)."""
+    m, c = inputs.sa2(0)
+    o = _oracle(orc, m, c)
+    U = o.init()
+    het, hom, ice = inputs.particle_fields(m["nr"], m["nx"], seed=41)
+    U[5:9] += het
+    U[15:19] += hom
+    U[9:13] += ice
+    # a radial velocity of a few m/s everywhere: the initial jet is uniform along x,
+    # so without it the density residual is a cancellation at rounding level
+    U[2] += U[0] * inputs.velocity_noise(m["nr"], m["nx"], seed=43)
+    s = _solver(B, m, c)
+    Ud = dev(U)
+    R = host(s.residual(Ud))
+    Ro = o.residual(U)
+    for v in range(19):
+        scale = np.abs(Ro[v]).max() + 1e-300
+        err = np.abs(R[v] - Ro[v]).max() / scale
+        assert err < 1e-10, (v, err)
+    dt = 3e-8
+    Q = host(s.source(Ud, dt))
+    Qo = o.source(U, dt)
+    active = np.any(Qo != 0, axis=0)
+    assert active.sum() > 20000 and np.any(Qo[15:19] != 0)
+    assert np.array_equal(active, np.any(Q != 0, axis=0))
+    err = np.abs(dt * (Q - Qo)) / (np.abs(U) + np.abs(dt * Qo) + 1e-300)
+    print("full size, two populations: residual within 1e-10; source on %d active cells, max rel error %.2e"
+          % (active.sum(), err.max()))
+    assert err.max() <= 1e-9
+    s.close()
+
+
+def test_bimodal_with_property_tables(B, orc):
+    """Two liquid populations with the 0.25 K property tables: 200 FP64 steps of the
+    source-active jet against the oracle reading its own table (the FP64 gate)."""
+    m, c = inputs.sa1(2)
+    o = _oracle(orc, m, c)
+    o.set_property_table(0.25)
+    Uo = o.init()
+    to = o.run(Uo, 200)
+    s = _solver(B, m, c)
+    s.set_property_table(0.25)
+    U = s.init()
+    t = s.step_n(U, 200)
+    assert t == pytest.approx(to, rel=1e-12)
+    e = rel_l2(host(U), Uo)
+    print("two populations with tables, 200 FP64 steps: max per-variable rel L2 %.2e" % e.max())
+    assert (e <= 1e-9).all(), e
+    s.close()
