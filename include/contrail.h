@@ -293,9 +293,9 @@ const char *cp_mlp_error_string(const cp_mlp *mlp);
 /* Attach a trained 17 -> 256 -> 256 -> 15 network as the source of a context
  * (CP_Q_SURROGATE).  The context takes a copy of the weights at this call, packed for
  * its fused inference kernel: later training or destruction of the network does not
- * affect it (attach again to update).  norm: n_norm = 117 host floats in the order
+ * affect it (attach again to update).  norm: n_norm = 118 host floats in the order
  *   s_in[15], mu_in[17], sd_in[17], lo[17], hi[17], mu_out[15], sd_out[15],
- *   lnS_gate, lnS_lo, lnS_hi, df_max
+ *   lnS_gate, lnS_lo, lnS_hi, df_max, df_max_ice
  * Features of an active cell: f_v = asinh(U_v / s_in[v]) for the 15 state variables,
  * ln dt, log10 max(N_soot, 1), standardised with (mu_in, sd_in).  The network takes
  * the cell when every standardised feature lies in [lo, hi] and ln S_l in
@@ -307,14 +307,16 @@ const char *cp_mlp_error_string(const cp_mlp *mlp);
  * -(4 pi/3)(rho_l Q_M3 + rho_s Q_N3) (water conserved, Eq. 25-26), gas mass and
  * momentum follow the vapour, the gas energy loses the condensate enthalpy, the soot
  * number is unchanged.  A network cell falls back to the exact source when any
- * predicted increment exceeds df_max in magnitude, when a particle population is not
+ * predicted increment exceeds df_max in magnitude (df_max_ice for the crystal
+ * moments 9..12: freezing is what the network reproduces least well, its rate
+ * changing by orders of magnitude per kelvin), when a particle population is not
  * realizable after the update (neither empty nor positive, log-convex moments with a
  * mean radius in [0.1 nm, 1 mm]) or when its vapour would turn negative.
  * The context allocates 17 bf16 feature values and 15 floats of network output per
  * cell plus the packed weights (150 KB); the hidden activations never leave the
  * workgroup.  Attaching drops the captured step and leaves a context that was in
  * CP_Q_SURROGATE in CP_Q_EXACT: select CP_Q_SURROGATE again afterwards.
- * Errors: CP_EINVAL (null, n_norm != 117, network not 17 -> 15), CP_EUNSUPPORTED
+ * Errors: CP_EINVAL (null, n_norm != 118, network not 17 -> 15), CP_EUNSUPPORTED
  * (hidden width other than 256), CP_ENOMEM, CP_EHIP.                               */
 int cp_sur_set(cp_ctx *ctx, cp_mlp *mlp, const float *norm, int n_norm);
 

@@ -154,6 +154,7 @@ struct SurNorm {
     float lnS_gate;            // exact source where |ln S_l| < lnS_gate (nucleation onset)
     float lnS_lo, lnS_hi;      // ln S_l range of the training set (part of the envelope)
     float df_max;              // trust bound on every predicted feature increment
+    float df_max_ice;          // tighter bound on the crystal moments' increments
 };
 
 template <class R> struct SurArgs {

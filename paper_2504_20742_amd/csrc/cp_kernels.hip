@@ -859,7 +859,8 @@ __device__ __forceinline__ bool sur_population_ok(double m0, double m1, double m
 // follow the vapour, the gas energy loses the enthalpy of the condensed water (the
 // freezing enthalpy cancels between the two condensates) and the soot number is
 // unchanged.  Returns false (the cell takes the exact source) when a predicted
-// increment leaves the trust bound df_max, a population is not realizable after
+// increment leaves the trust bound df_max (df_max_ice for the crystal moments, whose
+// freezing source the network reproduces least well), a population is not realizable after
 // the update, the vapour would turn negative or a value is not finite.
 template <class R>
 __device__ __forceinline__ bool sur_decode(const SurArgs<R> &a, int k, const double *Ud, double dt, double *Q)
@@ -871,7 +872,7 @@ __device__ __forceinline__ bool sur_decode(const SurArgs<R> &a, int k, const dou
         if (v == 13) continue;
         const double s = (double)a.nm.s_in[v];
         const double df = (double)(a.Y[(long)k * 15 + v] * a.nm.sd_out[v] + a.nm.mu_out[v]);
-        trust = trust && fabs(df) <= (double)a.nm.df_max;
+        trust = trust && fabs(df) <= (double)((v >= 9 && v <= 12) ? a.nm.df_max_ice : a.nm.df_max);
         const double f1 = fmax(asinh(Ud[v] / s) + df, 0.0);
         Un[v] = s * sinh(f1);
         Q[v] = (Un[v] - Ud[v]) / dt;

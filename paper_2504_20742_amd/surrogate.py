@@ -3,11 +3,13 @@
 Builds the training set from the solver itself (exact sub-cycled source of the
 GPU library on source-active runs), fits the normalisation and the training
 envelope, trains the 17 -> 256 -> 256 -> 15 network with the library's own
-MFMA forward/backward and Adam kernels, and packs the 116-float normalisation
+MFMA forward/backward and Adam kernels, and packs the 118-float normalisation
 block that ``cp_sur_set`` takes.
 
 In the step the library only trusts a prediction whose every feature increment
-stays within df_max (a log-scale change of about that size per step) and whose
+stays within df_max (a log-scale change of about that size per step), whose crystal
+moments change by at most df_max_ice (freezing is what the network reproduces least
+well: a few accepted freezing predictions carried the whole ice error) and whose
 particle populations stay realizable; other cells take the exact source.
 
 Features of a cell (computed on the device by ``cp_sur_features``, the same code
@@ -33,7 +35,7 @@ S_IN = np.array([1.0, 100.0, 1.0, 1.0e5, 1.0e-3,
                  1.0, 1.0e-9, 1.0e-18, 1.0e-27,
                  1.0, 1.0], dtype=np.float32)
 N_IN, N_OUT = 17, 15
-N_NORM = 15 + 4 * 17 + 2 * 15 + 4
+N_NORM = 15 + 4 * 17 + 2 * 15 + 5
 
 
 class Dataset:
@@ -116,7 +118,7 @@ def collect(binding, cases, snapshots, every, dt_factors=(0.5, 1.0, 2.0), lnS_ga
 class Norm:
     """Feature/target standardisation and the training envelope."""
 
-    def __init__(self, data, lnS_gate=0.05, df_max=0.5):
+    def __init__(self, data, lnS_gate=0.05, df_max=0.2, df_max_ice=0.01):
         import torch
         X, D = data.X.double(), data.D.double()
         self.s_in = S_IN.copy()
@@ -135,13 +137,15 @@ class Norm:
             self.sd_out[v] = sdv if sdv > 1e-12 else 1.0
         self.lnS_gate = lnS_gate
         self.df_max = df_max
+        self.df_max_ice = df_max_ice
         self.lnS_lo = float(data.lnS.min())
         self.lnS_hi = float(data.lnS.max())
 
     def pack(self):
-        """The 117 floats of cp_sur_set, in the order the library reads them."""
+        """The 118 floats of cp_sur_set, in the order the library reads them."""
         out = np.concatenate([self.s_in, self.mu_in, self.sd_in, self.lo, self.hi, self.mu_out, self.sd_out,
-                              [self.lnS_gate, self.lnS_lo, self.lnS_hi, self.df_max]]).astype(np.float32)
+                              [self.lnS_gate, self.lnS_lo, self.lnS_hi, self.df_max,
+                               self.df_max_ice]]).astype(np.float32)
         assert out.size == N_NORM
         return out
 
@@ -250,11 +254,11 @@ def increment_errors(net, norm, data, chunk=65536):
 
 
 def build(binding, cases, snapshots=40, every=20, epochs=30, lnS_gate=0.05, seed=0, val_frac=0.05, max_rows=None,
-          batch=4096, lr=2e-3, df_max=0.5, log=None):
+          batch=4096, lr=2e-3, df_max=0.2, df_max_ice=0.01, log=None):
     """Collect, fit the normalisation, train.  Returns (network, Norm, report)."""
     data = collect(binding, cases, snapshots, every, lnS_gate=lnS_gate, max_rows=max_rows, seed=seed, log=log)
     tr, va = data.split(val_frac, seed)
-    norm = Norm(tr, lnS_gate, df_max)
+    norm = Norm(tr, lnS_gate, df_max, df_max_ice)
     net, hist = train(binding, tr, norm, epochs=epochs, batch=batch, lr=lr, seed=seed, val_set=va, log=log)
     rep = {"rows": len(data), "train_rows": len(tr), "val_rows": len(va), "epochs": epochs,
            "first_val_loss": hist[0][2], "final_train_loss": hist[-1][1], "final_val_loss": hist[-1][2],

@@ -9,9 +9,10 @@ feeds the step, and what it gains.
   cells by construction of the closure, exact cells by the exact exchange), the
   soot number is untouched, inactive cells stay exactly zero.
 * A mixed-precision run with the surrogate in the step is compared with the FP64
-  oracle on the gas state, ice number and water mass; the errors are printed and
-  held to the bounds measured for this network (regression guards), next to the
-  mixed path with the exact source.
+  oracle on the gas state, ice number and water mass, next to the mixed path with
+  the exact source: the mixed gates hold (gas 1e-4, ice mu0 2e-2) with the network
+  taking some of the cells (the trust bounds df_max = 0.2, df_max_ice = 0.01 keep it
+  to the few cells where it is reliable).
 * Gain: step time of the mixed path with the exact source over the same path
   with the surrogate, on a source-active jet; any value is a valid outcome.
 """
@@ -154,10 +155,10 @@ def test_surrogate_run_against_oracle(B, orc, trained):
     print("after %d steps vs FP64 oracle: %s" % (steps, res))
     assert res["exact"]["ice"] <= 2e-2
     assert res["surrogate"]["net"] > 0
-    # regression guards for the trained network (the 2e-2 ice gate is reported, see print)
-    assert res["surrogate"]["gas"] <= 1e-2
-    assert res["surrogate"]["water"] <= 1e-2
-    assert res["surrogate"]["ice"] <= 1.0
+    # the mixed gates, and water to the exact path's level
+    assert res["surrogate"]["gas"] <= 1e-4
+    assert res["surrogate"]["ice"] <= 2e-2
+    assert res["surrogate"]["water"] <= 1e-4
 
 
 def test_surrogate_gain(B, S):

@@ -24,13 +24,13 @@ def test_norm_block_layout():
     d = _data()
     nm = S.Norm(d, lnS_gate=0.05)
     p = nm.pack()
-    assert p.dtype == np.float32 and p.size == S.N_NORM == 117
+    assert p.dtype == np.float32 and p.size == S.N_NORM == 118
     o = 0
     for name, k in (("s_in", 15), ("mu_in", 17), ("sd_in", 17), ("lo", 17), ("hi", 17), ("mu_out", 15),
                     ("sd_out", 15)):
         assert np.allclose(p[o:o + k], getattr(nm, name)), name
         o += k
-    assert np.allclose(p[o:], [0.05, float(d.lnS.min()), float(d.lnS.max()), 0.5])
+    assert np.allclose(p[o:], [0.05, float(d.lnS.min()), float(d.lnS.max()), 0.2, 0.01])
 
 
 def test_norm_statistics_and_envelope():
