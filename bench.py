@@ -318,8 +318,27 @@ def cpu_baseline(inputs, seconds_target=15.0):
         if el > seconds_target or n >= 50:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": m["nx"] * m["nr"] * n / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d SSP-RK3 steps of the 2048x512 workload (FP64 C oracle, OpenMP over rows, %.1f s)" % (n, el)}
+    out = {"value": m["nx"] * m["nr"] * n / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": "%d SSP-RK3 steps of the 2048x512 workload (FP64 C oracle, OpenMP over rows, %.1f s)" % (n, el)}
+    # the same oracle on one thread (one step), and the host CPU
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        o.run(U, 1)
+        out["value_1_thread"] = m["nx"] * m["nr"] / (time.perf_counter() - t0)
+        gomp.omp_set_num_threads(cores)
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                out["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return out
 
 
 def main():
