@@ -456,11 +456,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // zero (the stage output is bit-identical).
     const R Tcell = valid ? t.T[l] : R(0);
     constexpr int NG = (NV - 5 + 4) / 5;
+    int prev_live = 1;   // the primitives are still being read before the first group
     #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int s0 = 5 + 5 * g;
         const int ng = NV - s0 < 5 ? NV - s0 : 5;   // scalars in this group
-        __syncthreads();
+        // the slots are free once every thread is done with the previous group's
+        // faces; a group with nothing live read none of them
+        if (prev_live) __syncthreads();
         int nz = 0;
         if (inner) {
             for (int e = tid; e < NE; e += NT) {
@@ -489,19 +492,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         }
         if (nz) atomicOr(&t.nonzero[g], nz);
         __syncthreads();
-        const int live = t.nonzero[g];   // block-uniform
+        const int live = __builtin_amdgcn_readfirstlane(t.nonzero[g]);   // block-uniform
+        prev_live = live;
         R(*srs)[NRG] = t.rslope();   // r slopes in the free face buffer
-        for (int r = tid; r < NRG; r += NT) {
-            const int le = ext_of_ring<TX, TY>(r);
-            #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                if (!(live & (1 << k))) continue;
-                const R *ph = scalar_slot(t, k);
-                t.sl[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
-                srs[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
+        if (live) {   // a group with nothing live has zero slopes and fluxes: no slope pass, no barrier
+            for (int r = tid; r < NRG; r += NT) {
+                const int le = ext_of_ring<TX, TY>(r);
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    if (!(live & (1 << k))) continue;
+                    const R *ph = scalar_slot(t, k);
+                    t.sl[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
+                    srs[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
         if (valid) {
             R aw = R(0), ae = R(0), iv = R(0);
             if (q1d) {
