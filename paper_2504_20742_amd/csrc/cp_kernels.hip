@@ -4,10 +4,10 @@
 // cells; the tile plus a 2-cell halo is staged in LDS as gas primitives (the
 // MUSCL stencil of Sec. 3.2 is 2 cells wide), so every primitive, viscosity and
 // eddy viscosity is computed once per tile cell.  The ten per-mass scalars
-// (moments and soot numbers; the vapour travels with the gas) then go through the
-// freed primitive arrays five at a time, upwinded with the Roe mass flux; a scalar
-// that is zero on the whole tile is skipped.  The RK combination is fused into the
-// epilogue, so a stage
+// (moments and soot numbers; the vapour travels with the gas; fourteen with two
+// liquid populations) then go through the freed primitive arrays five at a time,
+// upwinded with the Roe mass flux; a scalar that is zero on the whole tile is
+// skipped.  The RK combination is fused into the epilogue, so a stage
 // reads U^(s-1) (+ U^n) and writes U^(s) once: a coalesced structure-of-arrays
 // stream.  Cells where the phase-change source (Sec. 2.2) can act are appended to
 // a compacted list; k_source_fix integrates the stiff source for those cells
