@@ -15,7 +15,8 @@ What fixes the two-population model without comparing it with itself:
 * immersion freezing needs a soot core: homogeneous droplets freeze like a
   one-population liquid whose immersion freezing is switched off;
 * total water is conserved; the extra moments are transported exactly like the
-  first liquid set.
+  first liquid set;
+* only the soot-activated droplets' complete evaporation releases activated soot.
 """
 import math
 
@@ -232,3 +233,32 @@ def test_bimodal_refuses_one_population_models(orc):
         o.set_drift(True)
     o.set_bimodal(False)
     assert o.nv == 15
+
+
+def test_only_soot_activated_evaporation_releases_soot(orc):
+    """Complete evaporation (R43): when the homogeneous droplets evaporate and the
+    soot-activated ones survive, the activated soot stays activated; when the
+    soot-activated droplets evaporate completely, their soot is released (N_act -> 0)
+    even while homogeneous droplets survive."""
+    m, c = inputs.sa0()
+    o = _bi(orc, m, c)
+    T, p = 262.0, 23800.0
+    L = orc.lib()
+    pv = 0.5 * math.exp(L.or_ln_psat_liq(T))
+    Y = pv / 461.52 / (pv / 461.52 + (p - pv) / 287.0)
+    small = _lognormal(1e9, 1e-8, 1.2)      # evaporates within dt
+    large = _lognormal(1e8, 5e-6, 1.2)      # survives
+    na = 1e8
+    dt = 1e-3
+    # homogeneous small, soot-activated large
+    U = _split(_cell(orc, T=T, p=p, Y=Y, liq=large, ns=1e12, na=na), None, hom=small)
+    Q, _ = o.source_cell(U, dt)
+    E = U + dt * Q
+    assert abs(E[18]) <= 1e-15 * U[18] and E[8] > 0.5 * U[8]
+    assert E[14] == pytest.approx(U[14], rel=1e-12)
+    # soot-activated small, homogeneous large
+    U = _split(_cell(orc, T=T, p=p, Y=Y, liq=small, ns=1e12, na=na), None, hom=large)
+    Q, _ = o.source_cell(U, dt)
+    E = U + dt * Q
+    assert abs(E[8]) <= 1e-15 * U[8] and E[18] > 0.5 * U[18]
+    assert abs(E[14]) <= 1e-12 * U[14]
