@@ -152,10 +152,12 @@ static double tsat_newton(int ice, double lnpv, double T_start)
 double or_tsat_liq(double pv, double T_start) { return tsat_newton(0, log(pv), T_start); }
 double or_tsat_ice(double pv, double T_start) { return tsat_newton(1, log(pv), T_start); }
 
-/* IAPWS (1994) surface tension of water, extrapolated below 273.15 K.           */
+/* IAPWS (1994) surface tension of water, extrapolated below 273.15 K; it vanishes
+ * at the critical point and stays zero above it (no liquid surface there).      */
 double or_sigma_lg(double T)
 {
     double tau = 1.0 - T / 647.096;
+    if (!(tau > 0.0)) return 0.0;
     return 0.2358 * pow(tau, 1.256) * (1.0 - 0.625 * tau);
 }
 

@@ -143,7 +143,8 @@ __device__ __forceinline__ double t_sat(const Sonntag &s, double lnpv, double T)
 
 __device__ __forceinline__ double surface_tension(double T)
 {
-    double tau = 1.0 - T / 647.096;              // IAPWS 1994
+    double tau = 1.0 - T / 647.096;              // IAPWS 1994; zero at and above the critical point
+    if (!(tau > 0.0)) return 0.0;
     return 0.2358 * pow(tau, 1.256) * (1.0 - 0.625 * tau);
 }
 

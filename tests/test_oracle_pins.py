@@ -79,6 +79,25 @@ def test_surface_tension_iapws_table(orc):
         assert abs(L.or_sigma_lg(T) - g["value"]) < g["abs_tol"]
 
 
+def test_surface_tension_vanishes_at_the_critical_point(orc):
+    """The IAPWS 1994 form B tau^1.256 (1 - 0.625 tau), tau = 1 - T/T_c, goes to zero
+    at T_c = 647.096 K continuously and stays zero above (no liquid surface), so the
+    rates of a droplet population carried into gas above T_c stay numbers."""
+    L = orc.lib()
+    Tc = 647.096
+    assert L.or_sigma_lg(Tc) == 0.0 and L.or_sigma_lg(700.0) == 0.0 and L.or_sigma_lg(1000.0) == 0.0
+    for d in (1e-2, 1e-4, 1e-6):
+        tau = d / Tc
+        assert L.or_sigma_lg(Tc - d) == pytest.approx(0.2358 * tau ** 1.256 * (1 - 0.625 * tau), rel=1e-9)
+    # a droplet population in 750 K gas: finite rates and sub-cycled source
+    m, c = inputs.sa0()
+    o = orc.Oracle(m, c)
+    U = _cell(orc, T=750.0, p=23800.0, Y=0.05, liq=_lognormal(1e10, 5e-9, 1.2))
+    S, d = o.rates_cell(U)
+    assert np.isfinite(S).all() and np.isfinite(d["Gl"])
+    assert np.isfinite(o.source_cell(U, 1e-5)[0]).all()
+
+
 # ---------------------------------------------------------------- Eq. 2-5, 8-10
 @pytest.mark.parametrize("T,S", [(220.0, 3.0), (240.0, 12.0), (260.0, 1.5), (300.0, 30.0)])
 def test_critical_radius_is_barrier_maximum(orc, T, S):
