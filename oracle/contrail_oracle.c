@@ -245,11 +245,15 @@ static double prop_sigma(const or_ctx *cx, double T)
     return or_sigma_lg(T);
 }
 
-/* Saturation temperature at ln p_v: with a table, the same four Newton steps in
- * x = 1/T from the gas temperature on the expanded ln p_sat, whose slope in x is
- * -T^2 d(ln p_sat)/dT.                                                            */
+/* Saturation temperature at ln p_v: four Newton steps in x = 1/T from the gas
+ * temperature, or from 373.15 K in hotter gas (the upper end of the Sonntag fits:
+ * beyond it the extrapolated ln p_sat bends and the steps can settle on a spurious
+ * root above the gas temperature); with a table on the expanded ln p_sat, whose
+ * slope in x is -T^2 d(ln p_sat)/dT.                                              */
+static const double T_SAT_START_MAX = 373.15;
 static double prop_tsat(const or_ctx *cx, int ice, double lnpv, double T_start)
 {
+    if (T_start > T_SAT_START_MAX) T_start = T_SAT_START_MAX;
     if (!cx->ptab) return tsat_newton(ice, lnpv, T_start);
     double x = 1.0 / T_start;
     for (int it = 0; it < 4; ++it) {
@@ -654,9 +658,12 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
     double S[NV];
     phase_change_rates(cx, U, dt, &r);
     exchange_terms(U, (const double(*)[4])r.dM, r.dN, npop, r.act, r.mdot_f, S);
+    /* depletion time scales and positivity scaling protect the components that are
+     * not negative already (transport of sharp fields can leave a moment slightly
+     * negative; no scaling of the step restores it) */
     double tau = HUGE_VAL;
     for (int c = 4; c < NV; ++c)
-        if (depletable(c) && S[c] < 0.0) {
+        if (depletable(c) && U[c] >= 0.0 && S[c] < 0.0) {
             double t = U[c] / (-S[c]);
             if (t < tau) tau = t;
         }
@@ -703,7 +710,7 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         for (int c = 4; c < NV; ++c) {
             if (!depletable(c)) continue;
             if ((evap_l[0] && c >= 5 && c <= 8) || (evap_s && c >= 9 && c <= 12) || (evap_l[1] && c >= 15)) continue;
-            if (S[c] < 0.0) {
+            if (U[c] >= 0.0 && S[c] < 0.0) {
                 double t = U[c] / (-h * S[c]);
                 if (t < theta) theta = t;
             }

@@ -176,10 +176,13 @@ __device__ __forceinline__ double prop_sigma(const SourceParams &sp, double T)
     return surface_tension(T);
 }
 
-// T_sat: with a table the same four Newton steps in x = 1/T on the expanded
-// ln p_sat (slope in x: -T^2 d ln p_sat / dT).
+// T_sat: four Newton steps in x = 1/T from the gas temperature, or from 373.15 K in
+// hotter gas (the upper end of the Sonntag fits, beyond which the extrapolated
+// ln p_sat bends and the steps can settle on a spurious root); with a table the same
+// steps on the expanded ln p_sat (slope in x: -T^2 d ln p_sat / dT).
 __device__ __forceinline__ double prop_tsat(const SourceParams &sp, bool ice, double lnpv, double T)
 {
+    T = fmin(T, 373.15);
     if (!sp.ptab) return t_sat(ice ? kSonI : kSonW, lnpv, T);
     double x = 1.0 / T;
     #pragma unroll
@@ -690,7 +693,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
     exchange(th, r.dM, r.dN, r.act, r.mdot_f, S);
     double tau = __builtin_huge_val();
     for (int c = 4; c <= 12; ++c)
-        if (S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
+        if (U[c] >= 0.0 && S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));   // a negative component cannot be protected
     int nsub = 1;
     if (tau < __builtin_huge_val()) {
         double want = ceil(dt / (kSubSafety * tau));
@@ -724,7 +727,7 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
         double theta = 1.0;
         for (int c = 4; c <= 12; ++c) {
             const bool skip = (el && c >= 5 && c <= 8) || (es && c >= 9);
-            if (!skip && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+            if (!skip && U[c] >= 0.0 && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
         }
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) U[v] = U[v] + theta * h * S[v];
@@ -776,7 +779,7 @@ __device__ inline int source_integrate_n(const double *U0, double dt, const Sour
     double tau = __builtin_huge_val();
     #pragma unroll
     for (int c = 4; c < NV; ++c)
-        if (depletable(c) && S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
+        if (depletable(c) && U[c] >= 0.0 && S[c] < 0.0) tau = fmin(tau, U[c] / (-S[c]));
     int nsub = 1;
     if (tau < __builtin_huge_val()) {
         double want = ceil(dt / (kSubSafety * tau));
@@ -831,7 +834,7 @@ __device__ inline int source_integrate_n(const double *U0, double dt, const Sour
             if (!depletable(c)) continue;
             bool skip = (el[0] && c >= 5 && c <= 8) || (es && c >= 9 && c <= 12);
             if constexpr (NP == 2) skip = skip || (el[1] && c >= 15);
-            if (!skip && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+            if (!skip && U[c] >= 0.0 && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
         }
         #pragma unroll
         for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];

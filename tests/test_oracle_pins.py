@@ -281,6 +281,34 @@ def test_water_conserved_per_cell(orc):
     assert worst < 1e-12
 
 
+def test_negative_moment_left_out_of_the_positivity_scaling(orc):
+    """R29: the positivity scaling of a sub-step limits the components that are not
+    negative already.  A moment left slightly negative by transport (here mu1 of an
+    evaporating population) is left out: the step stays a scaled explicit step,
+    0 <= theta <= 1, so every non-negative component stays non-negative and the gas
+    moves no further than the plain explicit step would take it (mu1 itself is then
+    brought back into its Hoelder bounds by the realisability clamp)."""
+    m, c = inputs.sa0()
+    o = orc.Oracle(m, c)
+    T, p = 262.0, 23800.0
+    L = orc.lib()
+    pv = 0.7 * math.exp(L.or_ln_psat_liq(T))
+    Y = pv / 461.52 / (pv / 461.52 + (p - pv) / 287.0)
+    U = _cell(orc, T=T, p=p, Y=Y, liq=_lognormal(1e9, 3e-7, 1.3), ice=_lognormal(1e7, 4e-7, 1.2))
+    U[6] = -0.01 * U[6]
+    S, d = o.rates_cell(U)
+    assert S[6] < 0.0 and d["Gl"] < 0.0
+    dt = 1e-5
+    Q, _ = o.source_cell(U, dt)
+    E = U + dt * Q
+    assert np.isfinite(Q).all()
+    for v in (4, 5, 7, 8, 9, 10, 11, 12):
+        assert E[v] >= -1e-14 * abs(U[v]), v
+    g = slice(0, 5)
+    assert np.all(np.abs(dt * Q[g]) <= np.abs(dt * S[g]) * 1.0000001 + 1e-14 * np.abs(U[g]) + 1e-300)
+    assert E[5] * E[7] >= E[6] ** 2 * (1 - 1e-9) and E[6] > 0.0
+
+
 def test_no_soot_no_heterogeneous(orc):
     """P18 (Sec. 4.3, hydrogen case): without soot there is no heterogeneous nucleation
     and nothing activates."""
