@@ -225,3 +225,37 @@ def test_full_size_sampled_parity(B, orc):
     Ug = host(U)
     assert t == pytest.approx(to, rel=1e-13)
     assert (rel_l2(Ug, Uo) <= 1e-11).all()
+
+
+@pytest.mark.parametrize("mode", ["kinetic", "equilibrium", "drift", "tables"])
+@pytest.mark.parametrize("shape", [(33, 17), (130, 9)])
+def test_seeded_particles_all_models(B, orc, mode, shape):
+    """The source-active jet on ragged meshes with droplets and crystals seeded on
+    30 % of the cells (sharp, random particle fields, some of them in the hot core):
+    every model variant, 25 FP64 steps against the oracle within the FP64 gate."""
+    m, c = inputs.sa1(2)
+    m = dict(m, nx=shape[0], nr=shape[1])
+    o = orc.Oracle(m, c)
+    s = B.Solver(m, c)
+    if mode == "equilibrium":
+        o.set_equilibrium(True)
+        s.set_qmode(B.CP_Q_EQUILIBRIUM)
+    elif mode == "drift":
+        o.set_drift(True)
+        s.set_drift(True)
+    elif mode == "tables":
+        o.set_property_table(0.25)
+        s.set_property_table(0.25)
+    U0 = o.init()
+    het, _, ice = inputs.particle_fields(shape[1], shape[0], seed=52, frac=0.3)
+    U0[5:9] += het
+    U0[9:13] += ice
+    Uo = U0.copy()
+    to = o.run(Uo, 25)
+    U = dev(U0)
+    t = s.step_n(U, 25)
+    e = rel_l2(host(U), Uo)
+    assert np.isfinite(Uo).all()
+    assert t == pytest.approx(to, rel=1e-12)
+    assert (e <= 1e-9).all(), (mode, e)
+    s.close()
