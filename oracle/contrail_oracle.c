@@ -61,7 +61,9 @@ static const double COND_COEF = 1.0;             /* q_c                         
 static const double YOUNG_ALPHA = 11.0;          /* Sec. 2.2 growth kinetics      */
 static const double N_MIN = 1.0;                 /* number floor [1/m^3]         */
 static const double SUB_SAFETY = 0.2;            /* sub-step / depletion time     */
-static const double PV_FLOOR = 1.0e-3;           /* Pa, floor of p_v in ln S     */
+/* Pa, floor of p_v in ln S: below the ice saturation pressure at 150 K (6e-6 Pa),
+ * the cold end of the property range, so a cell without vapour is subsaturated. */
+static const double PV_FLOOR = 1.0e-9;
 static const double R_MIN = 1.0e-10;             /* m: smaller r20 = evaporated   */
 static const double PI = 3.14159265358979323846;
 

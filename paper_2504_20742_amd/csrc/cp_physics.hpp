@@ -32,7 +32,10 @@ constexpr double kPr = 0.71, kPrT = 0.9, kPrV = 1.0, kSct = 0.7;
 constexpr double kMu0 = 1.716e-5, kSuth = 110.4;
 constexpr double kD0 = 2.11e-5, kDexp = 1.94, kP0 = 101325.0;
 constexpr double kQc = 1.0, kYoungA = 11.0;
-constexpr double kNmin = 1.0, kSubSafety = 0.2, kPvFloor = 1.0e-3;
+constexpr double kNmin = 1.0, kSubSafety = 0.2;
+// floor of p_v [Pa] under the logarithm: below p_sat over ice at 150 K (6e-6 Pa), the
+// cold end of the property range, so a cell without vapour never reads as supersaturated
+constexpr double kPvFloor = 1.0e-9;
 constexpr double kRmin2 = 1.0e-20, kRmin3 = 1.0e-30;   // (1e-10 m)^2, (1e-10 m)^3
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kFourThirdsPi = 4.0 / 3.0 * kPi;

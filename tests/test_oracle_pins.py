@@ -309,6 +309,24 @@ def test_negative_moment_left_out_of_the_positivity_scaling(orc):
     assert E[5] * E[7] >= E[6] ** 2 * (1 - 1e-9) and E[6] > 0.0
 
 
+@pytest.mark.parametrize("T", [150.0, 157.0, 165.0, 171.0, 200.0, 260.0, 400.0, 700.0])
+def test_cell_without_vapour_is_subsaturated(orc, T):
+    """Eq. 1 with no vapour: the saturation ratios over water and ice are below one at
+    every temperature of the property range (the floor that keeps ln p_v finite sits
+    below p_sat over ice at 150 K), so crystals and droplets can only shrink, and a
+    stiff source step from a vapour-free cold cell leaves the vapour non-negative."""
+    m, c = inputs.sa0()
+    o = orc.Oracle(m, c)
+    U = _cell(orc, T=T, p=23800.0, Y=0.0, liq=_lognormal(1e9, 3e-7, 1.3),
+              ice=_lognormal(1e9, 4e-7, 1.2), ns=1e12, na=1e9)
+    S, d = o.rates_cell(U)
+    assert d["lnSl"] < 0.0 and d["lnSi"] < 0.0
+    assert d["Gs"] <= 0.0 and d["Gl"] <= 0.0
+    assert S[4] >= 0.0
+    Q, _ = o.source_cell(U, 1e-4)
+    assert np.isfinite(Q).all() and U[4] + 1e-4 * Q[4] >= 0.0
+
+
 def test_no_soot_no_heterogeneous(orc):
     """P18 (Sec. 4.3, hydrogen case): without soot there is no heterogeneous nucleation
     and nothing activates."""
