@@ -683,9 +683,10 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         int evap_l[2] = {0, 0}, evap_s = 0;
         for (int pop = 0; pop < npop; ++pop) {
             const int b = liq_base(pop);
-            if (r.stale_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * dM[pop][3] <= 0.0)) {
-                /* all droplets of the population evaporate within the sub-step: none of
-                 * them freezes; soot-activated ones release their soot */
+            if (r.stale_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * (3.0 * U[b + 2] * r.Gl[pop]) <= 0.0)) {
+                /* evaporation alone (the growth term of mu3, not the freezing sink) would
+                 * empty the population within the sub-step: all droplets evaporate, none
+                 * of them freezes; soot-activated ones release their soot */
                 evap_l[pop] = 1;
                 for (int k = 0; k < 4; ++k) dM[pop][k] = -U[b + k] / h;
                 if (pop == 0) act = -U[14] / h;

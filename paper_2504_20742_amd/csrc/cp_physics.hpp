@@ -709,7 +709,9 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
         phase_rates(U, h, sp, th, r);
         double act = r.act, mdf = r.mdot_f;
         bool el = false, es = false;
-        if (r.gone_l || (r.Gl < 0.0 && U[8] + h * r.dM[3] <= 0.0)) {
+        // evaporation alone (the growth term of mu3, not the freezing sink) empties the
+        // droplets within the sub-step
+        if (r.gone_l || (r.Gl < 0.0 && U[8] + h * (3.0 * U[7] * r.Gl) <= 0.0)) {
             el = true;
             #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -798,10 +800,11 @@ __device__ inline int source_integrate_n(const double *U0, double dt, const Sour
         #pragma unroll
         for (int pop = 0; pop < NP; ++pop) {
             const int b = liq_base(pop);
-            el[pop] = r.gone_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * r.dM[pop][3] <= 0.0);
+            el[pop] = r.gone_l[pop] || (r.Gl[pop] < 0.0 && U[b + 3] + h * (3.0 * U[b + 2] * r.Gl[pop]) <= 0.0);
             if (el[pop]) {
-                // the whole population evaporates within the sub-step: none of it
-                // freezes; soot-activated droplets release their soot
+                // evaporation alone (the growth term of mu3, not the freezing sink)
+                // empties the population within the sub-step: none of it freezes;
+                // soot-activated droplets release their soot
                 #pragma unroll
                 for (int k = 0; k < 4; ++k) r.dM[pop][k] = -U[b + k] / h;
                 if (pop == 0) act = -U[14] / h;

@@ -157,3 +157,36 @@ def random_cells(n, seed=0, active=True):
     ns = np.where(g.uniform(size=n) < 0.7, 10.0 ** g.uniform(10.0, 14.0, n), 0.0)
     na = ns * g.uniform(0.0, 1.0, n) * (g.uniform(size=n) < 0.5)
     return dict(T=T, p=p, Y=Y, u=u, v=v, liq=liq, ice=ice, n_soot=ns, n_act=na)
+
+
+def extreme_cells(n, seed=0):
+    """Primitive cell states over the whole range the source accepts, for stress
+    parity: 150 to 700 K (the property range), 5 to 100 kPa, vapour mass fractions
+    from 1e-6 to 0.3 with one cell in ten holding no vapour at all, and droplets
+    (two sets: soot-activated and homogeneous), crystals and soot with lognormal
+    moments from 1 nm to 10 um and up to 1e13 per m^3.  The condensed mass of each
+    set is capped at 5 % of p / (287 T) so that the gas stays the carrier.  Returned
+    as a dict of arrays like random_cells, plus the second droplet set as 'hom'."""
+    g = _rng(seed)
+    T = g.uniform(150.0, 700.0, n)
+    p = 10.0 ** g.uniform(np.log10(5e3), 5.0, n)
+    Y = np.where(g.uniform(size=n) < 0.1, 0.0, 10.0 ** g.uniform(-6.0, -0.5, n))
+    u = g.uniform(-50.0, 500.0, n)
+    v = g.uniform(-50.0, 50.0, n)
+    mu3_cap = 0.05 * p / (287.0 * T) / (4.0 / 3.0 * np.pi * 1000.0)
+
+    def lognormal_moments(has, lg_rmax):
+        N = np.where(has, 10.0 ** g.uniform(0.0, 13.0, n), 0.0)
+        rg = 10.0 ** g.uniform(-9.0, lg_rmax, n)
+        sg = g.uniform(1.01, 2.2, n)
+        s2 = np.log(sg) ** 2
+        M = np.stack([N * np.exp(k * np.log(rg) + 0.5 * k * k * s2) for k in range(4)])
+        scale = np.minimum(1.0, mu3_cap / np.maximum(M[3], 1e-300))
+        return M * scale
+
+    liq = lognormal_moments(g.uniform(size=n) < 0.6, -5.0)
+    ice = lognormal_moments(g.uniform(size=n) < 0.5, -5.0)
+    hom = lognormal_moments(g.uniform(size=n) < 0.5, -6.0)
+    ns = np.where(g.uniform(size=n) < 0.7, 10.0 ** g.uniform(8.0, 14.0, n), 0.0)
+    na = np.minimum(ns, liq[0]) * g.uniform(0.0, 1.0, n) * (g.uniform(size=n) < 0.5)
+    return dict(T=T, p=p, Y=Y, u=u, v=v, liq=liq, ice=ice, hom=hom, n_soot=ns, n_act=na)
