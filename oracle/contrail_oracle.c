@@ -708,17 +708,21 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
         }
         exchange_terms(U, (const double(*)[4])dM, dN, npop, act, mdf, S);
         /* positivity scaling; an evaporating population reaches zero at theta = 1 by
-         * construction and is left out of the minimum */
+         * construction and is left out of the minimum.  The component that sets
+         * theta < 1 (the first of equals) reaches zero: it is set to zero exactly
+         * rather than left at the rounding residue of its update.                    */
         double theta = 1.0;
+        int czero = -1;
         for (int c = 4; c < NV; ++c) {
             if (!depletable(c)) continue;
             if ((evap_l[0] && c >= 5 && c <= 8) || (evap_s && c >= 9 && c <= 12) || (evap_l[1] && c >= 15)) continue;
             if (U[c] >= 0.0 && S[c] < 0.0) {
                 double t = U[c] / (-h * S[c]);
-                if (t < theta) theta = t;
+                if (t < theta) { theta = t; czero = c; }
             }
         }
         for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];
+        if (czero >= 0) U[czero] = 0.0;
         if (theta == 1.0) {
             if (evap_l[0]) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
             if (evap_l[1]) { U[15] = U[16] = U[17] = U[18] = 0.0; }

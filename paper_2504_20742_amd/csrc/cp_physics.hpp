@@ -729,13 +729,19 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
         exchange(th, r.dM, r.dN, act, mdf, S);
         // positivity scaling; components of an evaporating population reach zero at
         // theta = 1 exactly and do not take part
+        // the component that sets theta < 1 (the first of equals) is set to zero
+        // exactly, not left at the rounding residue of its update
         double theta = 1.0;
+        int cz = -1;
         for (int c = 4; c <= 12; ++c) {
             const bool skip = (el && c >= 5 && c <= 8) || (es && c >= 9);
-            if (!skip && U[c] >= 0.0 && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+            if (!skip && U[c] >= 0.0 && S[c] < 0.0) {
+                const double t = U[c] / (-h * S[c]);
+                if (t < theta) { theta = t; cz = c; }
+            }
         }
         #pragma unroll
-        for (int v = 0; v < NVAR; ++v) U[v] = U[v] + theta * h * S[v];
+        for (int v = 0; v < NVAR; ++v) U[v] = v == cz ? 0.0 : U[v] + theta * h * S[v];
         if (theta == 1.0) {
             if (el) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
             if (es) { U[9] = U[10] = U[11] = U[12] = 0.0; }
@@ -835,15 +841,19 @@ __device__ inline int source_integrate_n(const double *U0, double dt, const Sour
         // positivity scaling; components of an evaporating population reach zero at
         // theta = 1 exactly and do not take part
         double theta = 1.0;
+        int cz = -1;
         #pragma unroll
         for (int c = 4; c < NV; ++c) {
             if (!depletable(c)) continue;
             bool skip = (el[0] && c >= 5 && c <= 8) || (es && c >= 9 && c <= 12);
             if constexpr (NP == 2) skip = skip || (el[1] && c >= 15);
-            if (!skip && U[c] >= 0.0 && S[c] < 0.0) theta = fmin(theta, U[c] / (-h * S[c]));
+            if (!skip && U[c] >= 0.0 && S[c] < 0.0) {
+                const double t = U[c] / (-h * S[c]);
+                if (t < theta) { theta = t; cz = c; }
+            }
         }
         #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = U[v] + theta * h * S[v];
+        for (int v = 0; v < NV; ++v) U[v] = v == cz ? 0.0 : U[v] + theta * h * S[v];
         if (theta == 1.0) {
             if (el[0]) { U[5] = U[6] = U[7] = U[8] = 0.0; U[14] = 0.0; }
             if constexpr (NP == 2)

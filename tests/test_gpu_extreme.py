@@ -8,13 +8,15 @@ at two stiff ones (1e-5 and 1e-4 s, where the sub-cycling hits its cap).
 At these states a few cells are ill-conditioned: a change of the input in its last
 bits moves a branch of the stiff integration (an evaporation test, the sub-step
 count, the positivity scaling) and with it the result.  The test finds them with
-the oracle itself, by running it again on two inputs perturbed by 1e-15 relative;
-a cell where the oracle disagrees with itself beyond a tenth of the bar is exempt
+the oracle itself, by running it again on four inputs perturbed by 1e-15 and 1e-13
+relative (a cell whose result moves by a tenth of the bar under them has a condition
+number above 1e5 at the stiff steps); such a cell is exempt
 from the element-wise comparison (their number is bounded).  Every other cell must
 match the oracle within the bar, on the end state U + dt Q relative to |U| + |dt Q|
 plus 1e-12 of the variable's largest size.  Every cell, exempt or not, must come out
-finite, with non-negative vapour and particle moments, and with its water (vapour +
-droplets + crystals) conserved to 1e-9.
+finite, with non-negative vapour and particle moments (to 1e-12 of the cell's water
+for the vapour, of the variable's size before and after for the moments), and with
+its water (vapour + droplets + crystals) conserved to 1e-9.
 """
 import math
 
@@ -88,7 +90,7 @@ def test_source_over_the_whole_state_range(B, orc, mode):
         o.set_bimodal(True)
         s.set_bimodal(True)
     g = np.random.default_rng(7)
-    perturbed = [U * (1.0 + 1e-15 * g.standard_normal(U.shape)) for _ in range(2)]
+    perturbed = [U * (1.0 + eps * g.standard_normal(U.shape)) for eps in (1e-15, 1e-15, 1e-13, 1e-13)]
     Ud = dev(U)
     for dt, bar in BAR.items():
         Qo = o.source(U, dt)
@@ -100,13 +102,27 @@ def test_source_over_the_whole_state_range(B, orc, mode):
         Q = host(s.source(Ud, dt))
         E = U + dt * Q
         assert np.isfinite(E).all(), (mode, dt)
-        for v in list(range(4, 13)) + list(range(15, nv)):
-            assert (E[v] >= -1e-12 * np.abs(U[v]) - 1e-300).all(), (mode, dt, v)
         w0 = _water(U)
+        # non-negative up to rounding: a sub-step cut by the positivity scaling takes
+        # its limiting component to zero only up to the rounding of that update, whose
+        # size is set by the value before it (for the vapour: at most the cell's water)
+        for v in list(range(4, 13)) + list(range(15, nv)):
+            ref = w0 if v == 4 else np.abs(U[v]) + np.abs(Eo[v])
+            low = E[v] < -1e-12 * ref - 1e-300
+            if low.any():
+                k = np.argmax(np.where(low, -E[v] / (ref + 1e-300), 0.0))
+                print("%s dt %.0e var %d: %d cells below zero, worst %.3e (U %.3e, oracle %.3e, "
+                      "water %.3e)" % (mode, dt, v, low.sum(), E[v].flat[k], U[v].flat[k],
+                                       Eo[v].flat[k], w0.flat[k]))
+            assert not low.any(), (mode, dt, v)
         assert (np.abs(_water(E) - w0) <= 1e-9 * w0 + 1e-300).all(), (mode, dt)
         err = _err(U, E, Eo, dt, Q, Qo)
         print("%s dt %.0e: %d active cells, %d exempt (ill-conditioned), max rel error elsewhere %.2e"
               % (mode, dt, np.any(Qo != 0, axis=0).sum(), exempt.sum(), err[~exempt].max()))
         assert exempt.sum() <= 0.005 * exempt.size
+        if err[~exempt].max() > bar:
+            k = np.argmax(np.where(exempt, 0.0, err))
+            j, i = np.unravel_index(k, err.shape)
+            print("worst cell (%d, %d):\n U %s\n E %s\n oracle %s" % (j, i, U[:, j, i], E[:, j, i], Eo[:, j, i]))
         assert err[~exempt].max() <= bar, (mode, dt)
     s.close()

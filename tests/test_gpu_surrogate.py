@@ -16,6 +16,7 @@ feeds the step, and what it gains.
 * Gain: step time of the mixed path with the exact source over the same path
   with the surrogate, on a source-active jet; any value is a valid outcome.
 """
+import copy
 import time
 
 import numpy as np
@@ -96,8 +97,19 @@ def _state(B, seed, steps):
     return s, U
 
 
+def _open_norm(norm):
+    """The same normalisation with the trust bounds opened to 2 in feature space, so
+    that the network, not the exact fallback, takes the gated cells: the closure and
+    the weight snapshot hold whatever the network predicts."""
+    wide = copy.copy(norm)
+    wide.df_max = 2.0
+    wide.df_max_ice = 2.0
+    return wide
+
+
 def test_surrogate_source_closure(B, trained):
     net, norm, _ = trained
+    norm = _open_norm(norm)
     s, U = _state(B, 2, 300)
     dt = s.cfl_dt(U)
     Qx = s.source(U, dt).cpu().numpy().reshape(15, -1)
@@ -197,6 +209,7 @@ def test_attach_snapshots_the_weights(B, trained):
     """cp_sur_set copies the weights: training the network afterwards leaves the
     context's source unchanged until it is attached again."""
     net, norm, _ = trained
+    norm = _open_norm(norm)
     s, U = _state(B, 2, 300)   # a state with network cells (see the closure test)
     dt = s.cfl_dt(U)
     s.sur_set(net, norm.pack())
