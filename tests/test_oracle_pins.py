@@ -360,6 +360,32 @@ def test_fast_freezing_is_not_complete_evaporation(orc):
     assert E[4] - U[4] < 1e-3 * liq
 
 
+def test_positivity_scaling_single_substep(orc):
+    """R24/R29 with one sub-step allowed: when the vapour would be used up by ice
+    growth within the step, the whole update is scaled by theta = U_v / (-dt S_v),
+    every component moves by theta dt S, and the vapour, the component that set
+    theta, ends at exactly zero (not at the rounding residue of U_v + theta dt S_v)."""
+    m, c = inputs.sa0()
+    c = dict(c, n_sub_max=1)
+    o = orc.Oracle(m, c)
+    L = orc.lib()
+    T, p = 215.0, 23800.0
+    pv = 1.5 * math.exp(L.or_ln_psat_ice(T))
+    Y = pv / 461.52 / (pv / 461.52 + (p - pv) / 287.0)
+    U = _cell(orc, T=T, p=p, Y=Y, ice=_lognormal(1e12, 2e-6, 1.2))
+    dt = 1e-3
+    S, d = o.rates_cell(U, dt)
+    assert d["Gs"] > 0.0 and S[4] < 0.0
+    theta = U[4] / (-dt * S[4])
+    assert 0.0 < theta < 1.0
+    Q, n = o.source_cell(U, dt)
+    assert n == 1
+    E = U + dt * Q
+    assert E[4] == 0.0
+    for v in (0, 3, 9, 10, 11, 12):
+        assert E[v] - U[v] == pytest.approx(theta * dt * S[v], rel=1e-9, abs=1e-12 * abs(U[v])), v
+
+
 def test_no_soot_no_heterogeneous(orc):
     """P18 (Sec. 4.3, hydrogen case): without soot there is no heterogeneous nucleation
     and nothing activates."""
