@@ -191,45 +191,60 @@ def train_surrogate(binding, inputs, log):
     return net, norm, rep
 
 
-def run_source_active(binding, inputs, steps, warmup, trained):
+ACTIVE_PATHS = ("fp64", "mixed", "mixed_surrogate", "mixed_tables", "mixed_drift", "mixed_equilibrium",
+                "fp64_bimodal", "mixed_bimodal")
+
+
+def run_source_active(binding, inputs, steps, warmup, trained, which=ACTIVE_PATHS):
     """Source-active jet on the production mesh: FP64, mixed exact, mixed + surrogate,
     mixed with tabulated water properties, mixed with particle drift, the mixed path
     with the equilibrium comparison model, and two liquid populations in FP64 and
-    mixed."""
+    mixed (`which` selects a subset; errors are reported against the FP64 path of the
+    same model when it ran)."""
     import torch
-    net, norm, rep = trained
     m, c = inputs.sa2(0)
     res = {}
-    res["fp64"] = run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True)
-    res["mixed"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True)
-    res["mixed_surrogate"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, sur=(net, norm.pack()),
-                                      keep=True)
-    # water properties from 0.25 K tables read by second-order Taylor expansion
-    res["mixed_tables"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, table_h=0.25)
-    # droplets and crystals drifting against the gas (a model extension: its change
-    # against the FP64 path without drift is the drift's own effect)
-    res["mixed_drift"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, drift=True)
-    # the paper's comparison model (a different model: no error against the kinetics)
-    res["mixed_equilibrium"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
-                                        qmode=binding.CP_Q_EQUILIBRIUM)
-    # two liquid populations (19 variables): the mixed path against the FP64 path of
-    # the same model
-    res["fp64_bimodal"] = run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True, bimodal=True)
-    res["mixed_bimodal"] = run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, bimodal=True)
-    res["mixed_bimodal"]["error_vs_fp64_bimodal"] = rel_errors(res["mixed_bimodal"].pop("U"),
-                                                              res["fp64_bimodal"].pop("U"))
-    Uref = res["fp64"].pop("U")
-    for k in ("mixed", "mixed_surrogate", "mixed_tables", "mixed_drift"):
-        res[k]["error_vs_fp64"] = rel_errors(res[k].pop("U"), Uref)
-    del Uref
+    runs = {
+        "fp64": lambda: run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True),
+        "mixed": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True),
+        "mixed_surrogate": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
+                                            sur=(trained[0], trained[1].pack()), keep=True),
+        # water properties from 0.25 K tables read by second-order Taylor expansion
+        "mixed_tables": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, table_h=0.25),
+        # droplets and crystals drifting against the gas (a model extension: its change
+        # against the FP64 path without drift is the drift's own effect)
+        "mixed_drift": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, drift=True),
+        # the paper's comparison model (a different model: no error against the kinetics)
+        "mixed_equilibrium": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup,
+                                              qmode=binding.CP_Q_EQUILIBRIUM),
+        # two liquid populations (19 variables): the mixed path against the FP64 path of
+        # the same model
+        "fp64_bimodal": lambda: run_path(binding, m, c, binding.CP_FP64, steps, warmup, keep=True, bimodal=True),
+        "mixed_bimodal": lambda: run_path(binding, m, c, binding.CP_MIXED, steps, warmup, keep=True, bimodal=True),
+    }
+    for k in ACTIVE_PATHS:
+        if k in which:
+            res[k] = runs[k]()
+    if "mixed_bimodal" in res and "fp64_bimodal" in res:
+        res["mixed_bimodal"]["error_vs_fp64_bimodal"] = rel_errors(res["mixed_bimodal"]["U"],
+                                                                  res["fp64_bimodal"]["U"])
+    if "fp64" in res:
+        for k in ("mixed", "mixed_surrogate", "mixed_tables", "mixed_drift"):
+            if k in res:
+                res[k]["error_vs_fp64"] = rel_errors(res[k]["U"], res["fp64"]["U"])
+    for d in res.values():
+        d.pop("U", None)
     torch.cuda.empty_cache()
     out = {k: {kk: v for kk, v in d.items() if kk not in ("esz", "cells", "wall_s")} for k, d in res.items()}
-    out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
-    if res["mixed"].get("condensed_water_per_rad"):
+    if "mixed" in res and "mixed_surrogate" in res:
+        out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
+    if "mixed" in res and "mixed_equilibrium" in res and res["mixed"].get("condensed_water_per_rad"):
         out["equilibrium_over_kinetic_condensed_water"] = (res["mixed_equilibrium"].get("condensed_water_per_rad", 0.0)
                                                            / res["mixed"]["condensed_water_per_rad"])
-    out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": rep["seconds"],
-                                 "val_loss": rep["final_val_loss"]}
+    if trained is not None:
+        rep = trained[2]
+        out["surrogate_training"] = {"rows": rep["rows"], "epochs": rep["epochs"], "seconds": rep["seconds"],
+                                     "val_loss": rep["final_val_loss"]}
     out["steps"] = steps
     out["warmup"] = warmup
     return out
@@ -351,6 +366,8 @@ def main():
     ap.add_argument("--paths", default="fp64,mixed,mixed_surrogate")
     ap.add_argument("--active-steps", type=int, default=100, help="timed steps of the source-active jet (0: skip)")
     ap.add_argument("--active-warmup", type=int, default=200)
+    ap.add_argument("--active-paths", default=",".join(ACTIVE_PATHS),
+                    help="source-active paths to run (comma-separated subset of %s)" % ",".join(ACTIVE_PATHS))
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
     ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
     ap.add_argument("--tile", default="", help="stage tile of the production-jet paths, e.g. 32x8 (default: autotuned)")
@@ -378,12 +395,16 @@ def main():
     paths = [p for p in a.paths.split(",") if p]
     active = None
     trained = None
-    if a.active_steps > 0 or "mixed_surrogate" in paths:
+    active_paths = [p for p in a.active_paths.split(",") if p]
+    for p in active_paths:
+        if p not in ACTIVE_PATHS:
+            ap.error("unknown source-active path %r" % p)
+    if (a.active_steps > 0 and "mixed_surrogate" in active_paths) or "mixed_surrogate" in paths:
         trained = train_surrogate(binding, inputs, log)
-    if a.active_steps > 0:
-        log("bench: source-active jet 2048x512, 3 paths x (%d warmup + %d timed steps)"
-            % (a.active_warmup, a.active_steps))
-        active = run_source_active(binding, inputs, a.active_steps, a.active_warmup, trained)
+    if a.active_steps > 0 and active_paths:
+        log("bench: source-active jet 2048x512, paths %s, %d warmup + %d timed steps each"
+            % (",".join(active_paths), a.active_warmup, a.active_steps))
+        active = run_source_active(binding, inputs, a.active_steps, a.active_warmup, trained, active_paths)
     m, c = inputs.config2(0)
     res = {}
     for p in paths:
@@ -404,7 +425,7 @@ def main():
     else:
         mlp = None
     if not res:
-        print(json.dumps({"surrogate_inference": mlp}), flush=True)
+        print(json.dumps({"surrogate_inference": mlp, "source_active_2048x512": active}), flush=True)
         return
     head_name = "mixed_surrogate" if "mixed_surrogate" in res else ("mixed" if "mixed" in res else "fp64")
     head = res[head_name]

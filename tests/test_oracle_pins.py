@@ -167,16 +167,17 @@ def test_koop_rate_range_and_monotone(orc):
     """P21 (Eq. 12): Delta a_w(T) = 1 - p_sat,i/p_sat,w; J grows monotonically over the
     fit range; log10 J at the range ends matches the published polynomial."""
     L = orc.lib()
+    lo, hi = GOLD["koop_log10J_range"]["daw_lo"], GOLD["koop_log10J_range"]["daw_hi"]
     daw = L.or_koop_delta_aw(235.0)
     assert 0.30 < daw < 0.32
-    xs = np.linspace(0.26, 0.34, 81)
+    xs = np.linspace(lo, hi, 81)
     J = np.array([L.or_koop_rate(x) for x in xs])
     assert np.all(np.diff(J) > 0)
     # log10(J/1e6) at the ends of the fit (J in m^-3 s^-1 -> cm^-3 s^-1)
     assert math.log10(L.or_koop_rate(0.30) / 1e6) == pytest.approx(
         -906.7 + 8502 * 0.3 - 26924 * 0.09 + 29180 * 0.027, abs=1e-9)
-    assert L.or_koop_delta_aw(272.0) == 0.26   # clamped at the fit boundary
-    assert L.or_koop_delta_aw(150.0) == 0.34
+    assert L.or_koop_delta_aw(272.0) == lo     # clamped at the fit boundary
+    assert L.or_koop_delta_aw(150.0) == hi
 
 
 # ---------------------------------------------------------------- Eq. 16
