@@ -7,6 +7,12 @@ W1 (n_in x n_h, row-major), b1, W2 (n_h x n_h), b2, W3 (n_h x n_out), b3 -- the
 layout the HIP library uses.  Written as plain matrix products so a reader can
 check forward and backward by eye; the backward pass is pinned by central finite
 differences in the tests.
+
+``forward_bf16`` / ``loss_and_grad_bf16`` are the same passes at the network's
+stated precision (bfloat16 weights and activations, wider accumulation): every
+value the network stores in bfloat16 -- the hidden activations after the GELU, and
+in the backward pass the output error and the two hidden-layer errors -- is rounded
+to bfloat16 at that point, all other arithmetic stays FP64.
 """
 import numpy as np
 
@@ -49,6 +55,48 @@ def forward(theta, X, dims=(17, 256, 15)):
     H2 = gelu(Z2)
     Y = H2 @ W3 + b3
     return Y, (Z1, H1, Z2, H2)
+
+
+def forward_bf16(theta, X, dims=(17, 256, 15)):
+    """Forward pass with the hidden activations rounded to bfloat16 after the GELU.
+    Returns Y and the pre-rounding activations G1, G2 beside Z1, H1, Z2, H2."""
+    W1, b1, W2, b2, W3, b3 = unpack(theta, *dims)
+    Z1 = X @ W1 + b1
+    G1 = gelu(Z1)
+    H1 = bf16_round(G1)
+    Z2 = H1 @ W2 + b2
+    G2 = gelu(Z2)
+    H2 = bf16_round(G2)
+    Y = H2 @ W3 + b3
+    return Y, dict(Z1=Z1, G1=G1, H1=H1, Z2=Z2, G2=G2, H2=H2)
+
+
+def loss_and_grad_bf16(theta, X, T, dims=(17, 256, 15)):
+    """Loss and gradient of the bfloat16 forward pass, with the output error
+    dY = 2 (Y - T) / n and the hidden-layer errors dZ = (dH W^T) GELU'(Z) rounded to
+    bfloat16 as they are formed.  Returns the loss, the flat gradient and every
+    intermediate (pre-rounding values as P*)."""
+    W1, b1, W2, b2, W3, b3 = unpack(theta, *dims)
+    Y, a = forward_bf16(theta, X, dims)
+    n = X.shape[0] * Y.shape[1]
+    L = np.sum((Y - T) ** 2) / n
+    PdY = 2.0 * (Y - T) / n
+    dY = bf16_round(PdY)
+    dW3 = a["H2"].T @ dY
+    db3 = dY.sum(axis=0)
+    A2 = dY @ W3.T
+    PdZ2 = A2 * gelu_grad(a["Z2"])
+    dZ2 = bf16_round(PdZ2)
+    dW2 = a["H1"].T @ dZ2
+    db2 = dZ2.sum(axis=0)
+    A1 = dZ2 @ W2.T
+    PdZ1 = A1 * gelu_grad(a["Z1"])
+    dZ1 = bf16_round(PdZ1)
+    dW1 = X.T @ dZ1
+    db1 = dZ1.sum(axis=0)
+    g = np.concatenate([v.ravel() for v in (dW1, db1, dW2, db2, dW3, db3)])
+    a.update(Y=Y, PdY=PdY, dY=dY, A2=A2, PdZ2=PdZ2, dZ2=dZ2, A1=A1, PdZ1=PdZ1, dZ1=dZ1)
+    return L, g, a
 
 
 def loss(theta, X, T, dims=(17, 256, 15)):

@@ -885,6 +885,8 @@ __device__ __forceinline__ bool sur_decode(const SurArgs<R> &a, int k, const dou
     }
     Q[13] = 0.0;
     trust = trust && sur_population_ok(Un[5], Un[6], Un[7], Un[8]) && sur_population_ok(Un[9], Un[10], Un[11], Un[12]);
+    // at most the soot present can be activated (the soot number is unchanged)
+    trust = trust && Un[14] <= Ud[13] * (1.0 + 1e-12);
     CellThermo th;
     cell_thermo(Ud, th);
     const double ml = kFourThirdsPi * kRhoL * Q[8], ms = kFourThirdsPi * kRhoS * Q[12];

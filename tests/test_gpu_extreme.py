@@ -13,8 +13,9 @@ relative (a cell whose result moves by a tenth of the bar under them has a condi
 number above 1e5 at the stiff steps); such a cell is exempt
 from the element-wise comparison (their number is bounded).  Every other cell must
 match the oracle within the bar, on the end state U + dt Q relative to |U| + |dt Q|
-plus 1e-12 of the variable's largest size (plus, for the vapour, the cell's condensed
-water, whose exchange the vapour source closes).  Every cell, exempt or not, must come out
+plus 1e-12 of the variable's largest size (plus, for the vapour, the condensed water
+the step exchanges, whose rounding the vapour source carries as it closes that
+exchange).  Every cell, exempt or not, must come out
 finite, with non-negative vapour and particle moments (to 1e-12 of the cell's water
 for the vapour, of the variable's size before and after for the moments), and with
 its water (vapour + droplets + crystals) conserved to 1e-9.
@@ -72,9 +73,14 @@ def _err(U, Ea, Eb, dt, Qa, Qb):
     floor = 1e-12 * np.abs(U).max(axis=(1, 2), keepdims=True) + 1e-300
     ref = np.abs(U) + np.abs(dt * Qa) + np.abs(dt * Qb) + floor
     # the vapour source is the negative of the condensate's (Eq. 22-26), so the
-    # vapour's rounding is that of the water exchanged: where droplets freeze into
-    # crystals a tiny vapour change is the difference of two large condensate changes
-    ref[4] += np.abs(_water(U) - U[4])
+    # vapour's rounding is that of the water exchanged over the step: where droplets
+    # freeze into crystals a tiny vapour change is the difference of two large
+    # condensate changes.  The exchanged masses (not the condensate stock) set it.
+    fpi = 4.0 / 3.0 * math.pi
+    liq = np.abs(dt * Qa[8]) + np.abs(dt * Qb[8])
+    if U.shape[0] == 19:
+        liq = liq + np.abs(dt * Qa[18]) + np.abs(dt * Qb[18])
+    ref[4] += fpi * (1000.0 * liq + 917.0 * (np.abs(dt * Qa[12]) + np.abs(dt * Qb[12])))
     return (np.abs(Ea - Eb) / ref).max(axis=0)
 
 

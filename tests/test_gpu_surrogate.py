@@ -132,6 +132,10 @@ def test_surrogate_source_closure(B, trained):
     scale = np.abs(Qs[4]) + c43 * (1000.0 * np.abs(Qs[8]) + 917.0 * np.abs(Qs[12]))
     assert np.all(np.abs(w[changed]) <= 1e-12 * scale[changed] + 1e-300)
     assert np.all(Qs[0, changed] == Qs[4, changed])
+    # network cells activate at most the soot that is there (as the exact source does)
+    Uh0 = U.cpu().numpy().reshape(15, -1)
+    nact = Uh0[14] + dt * Qs[14]
+    assert np.all(nact[changed] <= Uh0[13, changed] * (1.0 + 1e-12))
     # every cell: the water of the updated state equals the water of U to rounding
     Uh = U.cpu().numpy().reshape(15, -1)
     W = Uh[4] + c43 * (1000.0 * Uh[8] + 917.0 * Uh[12])

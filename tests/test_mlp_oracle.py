@@ -90,3 +90,24 @@ def test_forward_on_a_hand_worked_network():
     h = H2[0, 3]
     assert Y[0, 0] == 45 + 240 + 7
     assert Y[0, 1] == 90 - h - 7
+
+
+def test_bf16_passes_are_the_fp64_passes_with_roundings(monkeypatch):
+    """The bfloat16-precision passes are the FP64 passes (pinned above by finite
+    differences) with roundings inserted: with the rounding made the identity they
+    reproduce loss, gradient and output exactly; with it, every stored activation
+    and error is a bfloat16 number."""
+    dims = (5, 7, 3)
+    g = np.random.default_rng(4)
+    theta = mlp.init_params(2, dims) + 0.1 * g.normal(size=mlp.n_params(*dims))
+    X = mlp.bf16_round(g.normal(size=(9, 5)))
+    T = g.normal(size=(9, 3))
+    L, grad, a = mlp.loss_and_grad_bf16(theta, X, T, dims)
+    for k in ("H1", "H2", "dY", "dZ2", "dZ1"):
+        assert np.all(mlp.bf16_round(a[k]) == a[k]), k
+    assert L != mlp.loss(theta, X, T, dims)
+    monkeypatch.setattr(mlp, "bf16_round", lambda x: np.asarray(x, dtype=np.float64))
+    L1, g1, a1 = mlp.loss_and_grad_bf16(theta, X, T, dims)
+    L0, g0 = mlp.loss_and_grad(theta, X, T, dims)
+    assert L1 == L0 and np.array_equal(g1, g0)
+    assert np.array_equal(a1["Y"], mlp.forward(theta, X, dims)[0])
