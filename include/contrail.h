@@ -281,6 +281,17 @@ int cp_mlp_get_params(cp_mlp *mlp, float *host_params);
  * n_in <= 32, n_hidden = 256, n_out <= 16 run all three layers in one fused kernel
  * (activations in LDS); others run layer by layer.                                */
 int cp_mlp_forward(cp_mlp *mlp, const float *X, int rows, float *Y);
+/* cp_mlp_forward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same result as
+ * cp_mlp_forward, with no allocation by the library at any call.  The bf16 input rows,
+ * the packed weights and the biases of a call live in a static device array of
+ * 4.3 MB that each GPU holds until the process ends; every call on a GPU shares it
+ * (each call packs its network's weights again), so calls that overlap on one GPU
+ * race.  Only the fused inference shape (n_in <= 32, 256 hidden units,
+ * n_out <= 16) and at most 65536 rows per call.  Stream-ordered on the network's
+ * stream, no synchronisation.  Errors: CP_EINVAL (null argument, rows outside
+ * [1, 65536]), CP_EUNSUPPORTED (another network shape), CP_EHIP.                  */
+int cp_mlp_forward_static(cp_mlp *mlp, const float *X, int rows, float *Y);
 /* Forward + backward of the MSE loss mean((Y - T)^2) over rows and outputs; the
  * gradient is kept for cp_mlp_adam; *loss_host (nullable) gets the loss,
  * grad_host (nullable, cp_mlp_num_params floats) a host copy of the gradient.

@@ -86,6 +86,7 @@ _SIGS = {
     "cp_mlp_set_params": (_I, [_P, _P]),
     "cp_mlp_get_params": (_I, [_P, _P]),
     "cp_mlp_forward": (_I, [_P, _P, _I, _P]),
+    "cp_mlp_forward_static": (_I, [_P, _P, _I, _P]),
     "cp_mlp_loss_grad": (_I, [_P, _P, _P, _I, _DP, _P]),
     "cp_mlp_adam": (_I, [_P, _D, _D, _D, _D]),
     "cp_mlp_error_string": (ctypes.c_char_p, [_P]),
@@ -412,6 +413,17 @@ class MLP:
         assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous()
         Y = torch.empty((X.shape[0], self.dims[2]), dtype=torch.float32, device="cuda")
         self._chk(self.L.cp_mlp_forward(self.h, X.data_ptr(), int(X.shape[0]), Y.data_ptr()))
+        return Y
+
+    def forward_static(self, X, Y=None):
+        """cp_mlp_forward without any allocation by the library (the call's scratch is
+        a static device array shared by every call on the GPU; at most 65536 rows)."""
+        import torch
+        assert X.dtype == torch.float32 and X.is_cuda and X.is_contiguous()
+        if Y is None:
+            Y = torch.empty((X.shape[0], self.dims[2]), dtype=torch.float32, device="cuda")
+        assert Y.dtype == torch.float32 and Y.is_cuda and Y.is_contiguous()
+        self._chk(self.L.cp_mlp_forward_static(self.h, X.data_ptr(), int(X.shape[0]), Y.data_ptr()))
         return Y
 
     def loss_grad(self, X, T, want_grad=False):

@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -216,6 +217,15 @@ __global__ void __launch_bounds__(256) k_pack_frag(const uint16_t *W, int K, int
         const int k = 32 * kb + 8 * (lane >> 4) + i, n = 16 * nb + (lane & 15);
         dst[e] = (k < K && n < N) ? W[(long)k * N + n] : (uint16_t)0;
     }
+}
+
+// Biases of the fused kernel: b1 (256), b2 (256), b3 (n_out) zero-padded to 16.
+__global__ void __launch_bounds__(256) k_pack_bias(const float *b1, const float *b2, const float *b3, int n_out,
+                                                   float *dst)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 528) return;
+    dst[e] = e < 256 ? b1[e] : e < 512 ? b2[e - 256] : (e - 512 < n_out ? b3[e - 512] : 0.f);
 }
 
 // All three layers for 64-row tiles in one launch (n_in <= 32, n_h = 256,
@@ -481,24 +491,28 @@ int weight_grad(cp_mlp *n, const uint16_t *Aact, int kin, const uint16_t *dZ, in
 namespace cp {
 bool mlp_fusable(const cp_mlp *n) { return n->n_in <= kFusedKin && n->n_h == kFusedNH && n->n_out <= 16; }
 
-int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
+// Weights and biases of a fusable network packed for k_mlp_fused (kernels only, no
+// allocation, no memset).
+int pack_fused(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
 {
-    if (!mlp_fusable(n)) return CP_EUNSUPPORTED;
-    // the network's own stream may still be updating the weights
-    if (s != n->stream && hipStreamSynchronize(n->stream) != hipSuccess) return mfail(n, CP_EHIP, "sync");
     constexpr int NB = kFusedNH / 16, KB = kFusedNH / 32;
     hipLaunchKernelGGL(k_pack_frag, dim3(32), dim3(256), 0, s, n->pb + n->off[0], n->n_in, n->n_h, kFusedKin / 32, NB,
                        w);
     hipLaunchKernelGGL(k_pack_frag, dim3(256), dim3(256), 0, s, n->pb + n->off[2], n->n_h, n->n_h, KB, NB, w + kFusedW1);
     hipLaunchKernelGGL(k_pack_frag, dim3(16), dim3(256), 0, s, n->pb + n->off[4], n->n_h, n->n_out, KB, 1,
                        w + kFusedW1 + kFusedW2);
+    hipLaunchKernelGGL(k_pack_bias, dim3(3), dim3(256), 0, s, n->p + n->off[1], n->p + n->off[3], n->p + n->off[5],
+                       n->n_out, b);
     if (hipGetLastError() != hipSuccess) return mfail(n, CP_EHIP, "weight packing");
-    if (hipMemsetAsync(b, 0, 528 * sizeof(float), s) != hipSuccess ||
-        hipMemcpyAsync(b, n->p + n->off[1], 256 * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(b + 256, n->p + n->off[3], 256 * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(b + 512, n->p + n->off[5], n->n_out * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return mfail(n, CP_EHIP, "bias copy");
     return CP_OK;
+}
+
+int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
+{
+    if (!mlp_fusable(n)) return CP_EUNSUPPORTED;
+    // the network's own stream may still be updating the weights
+    if (s != n->stream && hipStreamSynchronize(n->stream) != hipSuccess) return mfail(n, CP_EHIP, "sync");
+    return pack_fused(n, w, b, s);
 }
 
 hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int n_out, const int *rows_dev,
@@ -515,7 +529,67 @@ void mlp_dims(const cp_mlp *n, int *n_in, int *n_out)
 }
 }  // namespace cp
 
+// ------------------------------------------------ inference without allocation
+// cp_mlp_forward_static keeps everything a call needs beyond its inputs and outputs
+// -- the packed weights, the biases and the bf16 copy of the input rows -- in this
+// device array.  Each GPU holds its own copy for the life of the process; every call
+// on a GPU shares it, so calls that overlap on one GPU race.  Host code reaches the
+// array only through the address hipGetSymbolAddress returns on that device.
+constexpr int kStaticRows = 65536;                                            // rows per call, at most
+constexpr size_t kStaticBOff = (size_t)(kFusedW1 + kFusedW2 + kFusedW3) * 2;  // packed weights first
+constexpr size_t kStaticXOff = kStaticBOff + 2304;                            // 528 biases, 256-aligned
+constexpr size_t kStaticBytes = kStaticXOff + (size_t)kStaticRows * kFusedKin * 2;
+static_assert(kStaticBOff % 256 == 0 && kStaticXOff % 256 == 0, "scratch sections stay 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of the scratch array on the current device, looked up once per device.
+int static_scratch(cp_mlp *n, unsigned char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return mfail(n, CP_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return mfail(n, CP_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return mfail(n, CP_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return CP_OK;
+}
+}  // namespace
+
 extern "C" {
+
+int cp_mlp_forward_static(cp_mlp *n, const float *X, int rows, float *Y)
+{
+    if (!n || !X || !Y) return CP_EINVAL;
+    if (rows < 1 || rows > kStaticRows)
+        return mfail(n, CP_EINVAL, "cp_mlp_forward_static: rows must be in [1, " + std::to_string(kStaticRows) + "]");
+    if (!mlp_fusable(n))
+        return mfail(n, CP_EUNSUPPORTED, "cp_mlp_forward_static: needs n_in <= 32, 256 hidden units, n_out <= 16");
+    unsigned char *sp = nullptr;
+    int r = static_scratch(n, &sp);
+    if (r) return r;
+    uint16_t *w = (uint16_t *)sp;
+    float *b = (float *)(sp + kStaticBOff);
+    uint16_t *xb = (uint16_t *)(sp + kStaticXOff);
+    const long nx = (long)rows * n->n_in;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, n->stream, X, nx, xb);
+    if ((r = pack_fused(n, w, b, n->stream))) return r;
+    const FusedNet fw{w, w + kFusedW1, w + kFusedW1 + kFusedW2, b, b + 256, b + 512};
+    if (mlp_fused_forward(fw, xb, n->n_in, n->n_out, nullptr, rows, Y, n->stream) != hipSuccess)
+        return mfail(n, CP_EHIP, "fused forward");
+    return CP_OK;
+}
 
 int cp_mlp_create(int n_in, int n_hidden, int n_out, void *hip_stream, cp_mlp **out)
 {
