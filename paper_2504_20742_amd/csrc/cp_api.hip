@@ -45,6 +45,8 @@ struct cp_ctx {
     int cfl_nb = 0;
     int *flag_d = nullptr;
     int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
+    unsigned *tmask[3] = {};                        // tile masks of U, Ua, Ub (non-zero scalars)
+    unsigned ghost_bits = 0;                        // non-zero scalars of the inflow / far-field states
     bool sur_ready = false;                         // a network snapshot is attached
     SurNorm nm{};
     int *sur_cnt = nullptr, *sur_cells = nullptr, *fb_list = nullptr;
@@ -314,6 +316,41 @@ BcInfo bcinfo(const cp_ctx *c)
     return b;
 }
 
+// Tile masks of the passive scalars: one per state buffer (the caller's U, and the
+// two stage buffers), for the current tile shape.  Off with the drift, whose pass
+// moves particles after the stage kernel without widening the masks.
+bool masks_on(const cp_ctx *c) { return !c->drift && c->tx > 0 && c->tmask[0]; }
+unsigned *mask_of(const cp_ctx *c, const void *p)
+{
+    return p == c->Ua ? c->tmask[1] : (p == c->Ub ? c->tmask[2] : c->tmask[0]);
+}
+TileMask tile_mask(const cp_ctx *c, const void *Uin, const void *Uout, int stage)
+{
+    TileMask m{};
+    if (!masks_on(c)) return m;
+    m.in = Uin ? mask_of(c, Uin) : nullptr;
+    m.out = stage >= 0 && Uout ? mask_of(c, Uout) : nullptr;
+    m.tx = c->tx;
+    m.ty = c->ty;
+    m.gx = (c->nx + c->tx - 1) / c->tx;
+    m.gy = (c->nr + c->ty - 1) / c->ty;
+    m.nx = c->nx;
+    m.ghost = c->ghost_bits;
+    return m;
+}
+// Masks of the caller's state U (its contents may have changed since the last call).
+int mask_seed(cp_ctx *c, const void *U, hipStream_t s)
+{
+    if (!masks_on(c)) return CP_OK;
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_tile_mask<double>((const double *)U, c->plane, c->nx, c->nr, c->nv, c->tx, c->ty,
+                                                  c->tmask[0], s)
+                       : launch_tile_mask<float>((const float *)U, c->plane, c->nx, c->nr, c->nv, c->tx, c->ty,
+                                                 c->tmask[0], s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("tile mask: ") + hipGetErrorString(e));
+    return CP_OK;
+}
+
 template <class R>
 StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage, double dt,
                         const double *dt_dev)
@@ -338,6 +375,7 @@ StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *
     const bool sur = c->qmode == CP_Q_SURROGATE && c->sur_ready && stage >= 0;
     a.sur_cnt = sur ? c->sur_cnt : nullptr;
     a.sur_tot = c->sur_tot;
+    a.mask = tile_mask(c, Uin, Uout, stage);
     return a;
 }
 
@@ -358,6 +396,7 @@ SourceFixArgs<R> fix_args(const cp_ctx *c, const void *Uin, void *Uout, int stag
     a.sp.enabled = 1;
     a.flag = c->flag_d;
     a.nsub = c->nsub_d;
+    a.mask = tile_mask(c, nullptr, Uout, stage);
     return a;
 }
 
@@ -381,6 +420,7 @@ SurArgs<R> sur_args(const cp_ctx *c, const void *Uin, void *Uout, int stage, dou
     a.nm = c->nm;
     a.flag = c->flag_d;
     a.q_only = 0;
+    a.mask = tile_mask(c, nullptr, Uout, stage);
     return a;
 }
 
@@ -418,6 +458,7 @@ template <class R> int surrogate_source(cp_ctx *c, const void *U, double dt, voi
     a.count = c->src_cnt;
     a.list = c->src_list;
     a.q_only = 1;
+    a.mask = TileMask{};
     if (e == hipSuccess) e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
     if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
@@ -533,7 +574,9 @@ int autotune(cp_ctx *c, const void *U)
     for (auto &sh : tile_list()) {
         c->tx = sh.first;
         c->ty = sh.second;
-        int r = stage_any(c, U, U, c->Ua, -1, 0.0, nullptr, c->stream);
+        int r = mask_seed(c, U, c->stream);
+        if (r) return r;
+        r = stage_any(c, U, U, c->Ua, -1, 0.0, nullptr, c->stream);
         if (r) return r;
         HIPCHK(c, hipEventRecord(e0, c->stream));
         for (int k = 0; k < 6; ++k) {
@@ -617,6 +660,11 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
         else if (r < cs->R_fan) stream_cons(cs->p_amb, cs->T_byp, cs->u_byp, Yb, 0.0, U);
         else for (int v = 0; v < NVAR; ++v) U[v] = amb[v];
     }
+    for (int v = 5; v < NVAR; ++v) {   // scalars a ghost cell can take from a boundary state
+        if (amb[v] != 0.0) c->ghost_bits |= 1u << v;
+        for (int j = 0; j < c->nr; ++j)
+            if (inflow[(size_t)NVAR * j + v] != 0.0) c->ghost_bits |= 1u << v;
+    }
 
     // phase-change constants evaluated once on the host
     const double ct = cos(cs->theta_deg * M_PI / 180.0);
@@ -656,7 +704,10 @@ int cp_create(const cp_mesh *mesh, const cp_case *cs, int precision, void *hip_s
     c->flag_d = dalloc<int>(c, 1);
     c->act_count = dalloc<int>(c, 4);
     c->act_list = dalloc<int>(c, c->plane);
-    if (!c->act_count || !c->act_list ||!c->inflow || !c->ambient || !c->Ua || !c->Ub || !c->dt_d || !c->t_d || !c->diag_d || !c->acc_d || !c->cfl_bm ||
+    // tile masks: enough words for the smallest built tile (16 x 4 cells)
+    const size_t mwords = (size_t)((c->nx + 15) / 16) * ((c->nr + 3) / 4);
+    for (int k = 0; k < 3; ++k) c->tmask[k] = dalloc<unsigned>(c, mwords);
+    if (!c->tmask[0] || !c->tmask[1] || !c->tmask[2] || !c->act_count || !c->act_list || !c->inflow || !c->ambient || !c->Ua || !c->Ub || !c->dt_d || !c->t_d || !c->diag_d || !c->acc_d || !c->cfl_bm ||
         !c->nsub_d || !c->flag_d)
         return bail(CP_ENOMEM);
     if (hipMemcpy(c->inflow, inflow.data(), inflow.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -705,6 +756,8 @@ int cp_residual(cp_ctx *c, const void *U, void *R)
         c->tx = 32;
         c->ty = 8;
     }
+    int r = mask_seed(c, U, c->stream);
+    if (r) return r;
     return stage_any(c, U, U, R, -1, 0.0, nullptr, c->stream);
 }
 
@@ -732,6 +785,7 @@ int cp_step(cp_ctx *c, void *U, double dt)
     if (!(dt > 0.0) || !isfinite(dt)) return fail(c, CP_EDT, "dt must be positive and finite");
     int r = autotune(c, U);
     if (r) return r;
+    if ((r = mask_seed(c, U, c->stream))) return r;
     return enqueue_step(c, U, dt, nullptr, c->stream);
 }
 
@@ -754,7 +808,7 @@ int capture_steps(cp_ctx *c, void *U, int steps, hipGraphExec_t *out)
 {
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int r = 0;
+    int r = mask_seed(c, U, c->cap_stream);   // U may have changed between replays
     for (int k = 0; k < steps && !r; ++k) {
         r = cfl_any(c, U, c->cap_stream);
         if (!r && launch_cfl_finalize_blocks(c->cfl_bm, c->cfl_nb, c->cs.cfl, c->dt_d, c->t_d, c->cap_stream) !=
@@ -988,6 +1042,7 @@ int cp_time_stage(cp_ctx *c, void *U, int reps, double *ms)
     const double dt = 1e-12;
     const void *in[3] = {U, c->Ua, c->Ub};
     void *out[3] = {c->Ua, c->Ub, c->Ua};
+    if ((r = mask_seed(c, U, c->stream))) return r;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1079,6 +1134,8 @@ template <class R> int batch_upload_args(cp_batch *b, void *const *U)
         for (int s = 0; s < 3; ++s) {
             sa[s].push_back(stage_args<R>(c, in[s], U[p], out[s], s, 0.0, b->dt + p));
             fa[s].push_back(fix_args<R>(c, in[s], out[s], s, 0.0, b->dt + p));
+            sa[s].back().mask = TileMask{};   // the batch runs without tile masks
+            fa[s].back().mask = TileMask{};
         }
         CflArgs<R> &a = ca[p];
         a.U = (const R *)U[p];

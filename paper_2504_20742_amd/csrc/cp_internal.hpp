@@ -36,6 +36,21 @@ struct BcInfo {
     const double *ambient;     // 15
 };
 
+// Which passive scalars can be non-zero, per stage tile of the current tile shape:
+// bit v of word (tj * gx + ti) is set when variable v (v >= 5) may be non-zero
+// somewhere in tile (ti, tj).  A stage reads the mask of its input and writes the
+// mask of its output; the kernels that change a stage output afterwards (the
+// phase-change source, the learned source) add the bits of the cells they change.
+// A bit may be set for a variable that is zero (the masks only ever widen), never
+// the other way round.  Null `in`: every scalar may be non-zero.
+struct TileMask {
+    const unsigned *in;
+    unsigned *out;
+    int tx, ty, gx, gy;        // tile shape, tiles per row and per column
+    int nx;                    // cells per row
+    unsigned ghost;            // scalars the boundary states (inflow, far field) can hold
+};
+
 template <class R> struct StageArgs {
     const R *Uin;              // stencil input U^(s-1)
     const R *Un;               // U^n for the RK combination (stages 2, 3)
@@ -54,6 +69,7 @@ template <class R> struct StageArgs {
     int *active_list;          // cells whose phase-change source may be non-zero
     int *sur_cnt;              // surrogate counters folded into sur_tot at launch (or null)
     unsigned long long *sur_tot;
+    TileMask mask;             // non-zero passive scalars of the input / output tiles
 };
 
 // Drift of droplets and crystals (drift-flux reading of the drag law, Eq. 24): a
@@ -86,6 +102,7 @@ template <class R> struct SourceFixArgs {
     SourceParams sp;
     int *flag;
     unsigned long long *nsub;  // running total of sub-steps (or null)
+    TileMask mask;             // mask.out: tile mask of Uout, widened by the cells changed here
 };
 
 template <class R> struct CflArgs {
@@ -173,6 +190,7 @@ template <class R> struct SurArgs {
     SurNorm nm;
     int *flag;
     int q_only;                // write Q itself to Uout (cp_source) instead of adding b dt Q
+    TileMask mask;             // mask.out: tile mask of Uout, widened by the cells changed here
 };
 template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s);
 template <class R>
@@ -180,6 +198,11 @@ hipError_t launch_sur_finish(const SurArgs<R> &a, const SourceParams &sp, int *n
                              long max_cells, hipStream_t s);
 hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s);
 template <class R> hipError_t launch_active_list(const R *U, long plane, int *count, int *list, hipStream_t s);
+// Tile masks of a state: bit v of a tile's word set when variable v >= 5 is non-zero
+// in one of the tile's cells.
+template <class R>
+hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
+                            hipStream_t s);
 template <class R>
 hipError_t launch_sur_features(const R *U, long plane, double dt, const SurNorm &nm, float *F, hipStream_t s);
 

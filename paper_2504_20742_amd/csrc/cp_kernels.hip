@@ -141,6 +141,7 @@ template <class R, int TX, int TY> struct Tile {
     R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF];
                                  // the scalars' r slopes during the scalar phase, [5][NR]
     int nonzero[3];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
+    unsigned omask;              // non-zero passive scalars of the tile's output (bit v: variable v)
     __device__ R (*face())[NF] { return reinterpret_cast<R(*)[NF]>(fbuf); }
     __device__ R (*rslope())[NR] { return reinterpret_cast<R(*)[NR]>(fbuf); }
 };
@@ -288,6 +289,31 @@ __device__ __forceinline__ int xcd_band(int b, int nb)
     return xcd * q + min(xcd, rem) + (b >> 3);
 }
 
+// Bits of a cell's passive scalars (variables 5..NV-1) that are non-zero.
+template <class R, int NV> __device__ __forceinline__ unsigned scalar_bits(const R *x)
+{
+    unsigned b = 0;
+    #pragma unroll
+    for (int v = 5; v < NV; ++v) b |= (x[v] != R(0)) ? (1u << v) : 0u;
+    return b;
+}
+
+// Widen the output tile mask by the non-zero scalars of cell c's new state.
+__device__ __forceinline__ void mask_mark(const TileMask &m, long c, unsigned bits)
+{
+    if (!m.out || !bits) return;
+    const int i = (int)(c % m.nx), j = (int)(c / m.nx);
+    atomicOr(&m.out[(j / m.ty) * m.gx + i / m.tx], bits);
+}
+
+// OR of a value over the wavefront.
+__device__ __forceinline__ unsigned wave_or(unsigned x)
+{
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return x;
+}
+
 // One fused SSP-RK3 stage on the TX x TY tile whose first cell is (i0, j0).
 // DUCT: the quasi-1D duct (one row, x faces of the duct areas, no r faces, wall
 // force on axial momentum), a separate instantiation so that the axisymmetric and
@@ -312,7 +338,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     const bool inner = i0 >= 2 && j0 >= 2 && i0 + TX + 2 <= nx && j0 + TY + 2 <= nr;
     R(*face)[TileT::NF] = t.face();
 
-    if (tid == 0) t.nonzero[0] = t.nonzero[1] = t.nonzero[2] = 0;
+    if (tid == 0) {
+        t.nonzero[0] = t.nonzero[1] = t.nonzero[2] = 0;
+        t.omask = 0;
+    }
     // phase 1: gas primitives of tile + halo
     for (int e = tid; e < NE; e += NT) {
         const int ex = e % EX, ey = e / EX;
@@ -456,11 +485,37 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // zero (the stage output is bit-identical).
     const R Tcell = valid ? t.T[l] : R(0);
     constexpr int NG = (NV - 5 + 4) / 5;
+    // Scalars that can be non-zero in the tile and its halo: the halo lies in the eight
+    // neighbouring tiles, so the OR of their input masks; a ghost cell is a mirror or
+    // copy of a cell of those tiles, or a boundary state (the inflow profile, the
+    // ambient far field), whose scalars are in mask.ghost.  A scalar outside that set
+    // is zero on the whole stencil, and is neither loaded nor transported.
+    unsigned cand = ~0u;
+    if (a.mask.in) {
+        const int ti = i0 / TX, tj = j0 / TY, gx = a.mask.gx, gy = a.mask.gy;
+        cand = inner ? 0u : a.mask.ghost;
+        #pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+            #pragma unroll
+            for (int di = -1; di <= 1; ++di)
+                if (ti + di >= 0 && ti + di < gx && tj + dj >= 0 && tj + dj < gy)
+                    cand |= a.mask.in[(tj + dj) * gx + ti + di];
+        cand = __builtin_amdgcn_readfirstlane(cand);
+    }
     int prev_live = 1;   // the primitives are still being read before the first group
     #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int s0 = 5 + 5 * g;
         const int ng = NV - s0 < 5 ? NV - s0 : 5;   // scalars in this group
+        const unsigned cg = (cand >> s0) & ((1u << ng) - 1u);   // block-uniform
+        if (!cg) {   // nothing in this group can be non-zero here: zero residual, no work
+            if (valid) {
+                #pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    if (k < ng) res[s0 + k] = R(0);
+            }
+            continue;
+        }
         // the slots are free once every thread is done with the previous group's
         // faces; a group with nothing live read none of them
         if (prev_live) __syncthreads();
@@ -471,7 +526,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    if (k >= ng) continue;
+                    if (k >= ng || !(cg & (1u << k))) continue;
                     const R u = ld_plane(a.Uin, a.plane, s0 + k, code);
                     nz |= (u != R(0)) << k;
                     scalar_slot(t, k)[e] = per_mass(u, rho, ir);
@@ -483,7 +538,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    if (k >= ng) continue;
+                    if (k >= ng || !(cg & (1u << k))) continue;
                     const R u = fetch(a.Uin, a.plane, bc, code, s0 + k);
                     nz |= (u != R(0)) << k;
                     scalar_slot(t, k)[e] = per_mass(u, rho, ir);
@@ -533,71 +588,80 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
         }
     }
-    if (!valid) return;
-
     // phase 6: SSP-RK3 combination with the transport residual.  Cells whose
     // phase-change source can be non-zero are appended to the active list; the
     // source kernel adds b dt Q(U^(s-1), dt) to them (the stage is linear in L).
-    const long c = (long)j * nx + i;
-    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
     bool bad = false;
-    if (a.stage < 0) {
-        #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            a.Uout[v * a.plane + c] = res[v];
-            bad |= !isfinite(res[v]);
-        }
-    } else {
-        const R rdt = (R)dt;
-        // every load of the cell's old states is issued before the first store (the
-        // compiler cannot rule out that Uout aliases them, and would otherwise wait
-        // for each load in turn)
-        R ui[NV], un[NV];
-        #pragma unroll
-        for (int v = 0; v < NV; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
-        if (a.stage > 0) {
+    unsigned obits = 0;   // non-zero scalars of the cell's output
+    if (valid) {
+        const long c = (long)j * nx + i;
+        const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+        if (a.stage < 0) {
             #pragma unroll
-            for (int v = 0; v < NV; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
-        }
-        bool act = false;
-        // liquid number of the cell for the pre-filter: either population
-        R Mliq = ui[5];
-        if constexpr (NV == NVAR_BI) Mliq = ui[15] > Mliq ? ui[15] : Mliq;
-        if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], Mliq, ui[9], Tcell))) {
-            double Ug[NV];
+            for (int v = 0; v < NV; ++v) {
+                a.Uout[v * a.plane + c] = res[v];
+                bad |= !isfinite(res[v]);
+            }
+        } else {
+            const R rdt = (R)dt;
+            // every load of the cell's old states is issued before the first store (the
+            // compiler cannot rule out that Uout aliases them, and would otherwise wait
+            // for each load in turn)
+            R ui[NV], un[NV];
             #pragma unroll
-            for (int v = 0; v < NV; ++v) Ug[v] = (v <= 5 || v == 9 || v == 15) ? (double)ui[v] : 0.0;
-            CellThermo th;
-            cell_thermo(Ug, th);
-            act = !source_inactive<NV>(Ug, th.T);
-        }
-        // append the wavefront's active cells with one atomic
-        const unsigned long long mask = __ballot(act);
-        if (mask) {
-            const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(a.active_count, __popcll(mask));
-            base = __shfl(base, leader, 64);
-            if (act) {
-                const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
-                if (slot < a.plane) a.active_list[slot] = (int)c;
+            for (int v = 0; v < NV; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
+            if (a.stage > 0) {
+                #pragma unroll
+                for (int v = 0; v < NV; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
             }
-        }
-        #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const R L = res[v];
-            R out;
-            if (a.stage == 0) {
-                out = ui[v] + rdt * L;
-            } else {
-                out = a.stage == 1 ? R(0.75) * un[v] + R(0.25) * (ui[v] + rdt * L)
-                                   : R(1.0 / 3.0) * un[v] + R(2.0 / 3.0) * (ui[v] + rdt * L);
+            bool act = false;
+            // liquid number of the cell for the pre-filter: either population
+            R Mliq = ui[5];
+            if constexpr (NV == NVAR_BI) Mliq = ui[15] > Mliq ? ui[15] : Mliq;
+            if (a.sp.enabled && !(sizeof(R) == 4 && clearly_inactive<R>(ui[4], Mliq, ui[9], Tcell))) {
+                double Ug[NV];
+                #pragma unroll
+                for (int v = 0; v < NV; ++v) Ug[v] = (v <= 5 || v == 9 || v == 15) ? (double)ui[v] : 0.0;
+                CellThermo th;
+                cell_thermo(Ug, th);
+                act = !source_inactive<NV>(Ug, th.T);
             }
-            st_plane(a.Uout, a.plane, v, (unsigned)c, out);
-            bad |= !isfinite(out);
+            // append the wavefront's active cells with one atomic
+            const unsigned long long mask = __ballot(act);
+            if (mask) {
+                const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(a.active_count, __popcll(mask));
+                base = __shfl(base, leader, 64);
+                if (act) {
+                    const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+                    if (slot < a.plane) a.active_list[slot] = (int)c;
+                }
+            }
+            #pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const R L = res[v];
+                R out;
+                if (a.stage == 0) {
+                    out = ui[v] + rdt * L;
+                } else {
+                    out = a.stage == 1 ? R(0.75) * un[v] + R(0.25) * (ui[v] + rdt * L)
+                                       : R(1.0 / 3.0) * un[v] + R(2.0 / 3.0) * (ui[v] + rdt * L);
+                }
+                st_plane(a.Uout, a.plane, v, (unsigned)c, out);
+                bad |= !isfinite(out);
+                if (v >= 5) obits |= (out != R(0)) ? (1u << v) : 0u;
+            }
         }
     }
     if (bad) atomicOr(a.flag, 1);
+    // the output mask of the tile: OR over its cells, one word written by the tile
+    if (a.mask.out) {
+        obits = wave_or(obits);
+        if ((tid & 63) == 0 && obits) atomicOr(&t.omask, obits);
+        __syncthreads();
+        if (tid == 0) a.mask.out[(j0 / TY) * a.mask.gx + i0 / TX] = t.omask;
+    }
 }
 
 // FP32: registers held to 80 per lane (6 wavefronts per SIMD), which is what the
@@ -612,9 +676,12 @@ k_stage(StageArgs<R> a)
     __shared__ Tile<R, TX, TY> t;
     // surrogate counters of the previous stage, consumed by now (saves a launch)
     if (a.sur_cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) sur_fold_counts(a.sur_cnt, a.sur_tot);
-    const int gx = gridDim.x;
-    const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
-    stage_tile<R, TX, TY, DUCT, NV>(a, (tb % gx) * TX, (tb / gx) * TY, t);
+    // tiles enumerated column by column, so that each XCD's contiguous band holds
+    // whole columns: every XCD then sees the full radial structure of the jet (core,
+    // shear layer, far field) and its share of the boundary tiles
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int tb = xcd_band(blockIdx.y * gx + blockIdx.x, gx * gy);
+    stage_tile<R, TX, TY, DUCT, NV>(a, (tb / gy) * TX, (tb % gy) * TY, t);
 }
 
 // Batched operating points: workgroup b takes work item b (XCD-banded) of a list of
@@ -651,12 +718,15 @@ __device__ __forceinline__ void source_fix_body(const SourceFixArgs<R> &a, int b
         R uo[NV];   // all loads before the stores (possible aliasing serialises them)
         #pragma unroll
         for (int v = 0; v < NV; ++v) uo[v] = a.Uout[v * a.plane + c];
+        unsigned bits = 0;
         #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const R out = uo[v] + (R)(b * dt * Q[v]);
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
+            if (v >= 5) bits |= (out != R(0)) ? (1u << v) : 0u;
         }
+        mask_mark(a.mask, c, bits);
     }
     if (bx == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
     if (bad) atomicOr(a.flag, 1);
@@ -945,12 +1015,15 @@ template <class R> __global__ void __launch_bounds__(64) k_sur_finish(SurArgs<R>
         R uo[NVAR];   // all loads before the stores (possible aliasing serialises them)
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) uo[v] = a.Uout[v * a.plane + c];
+        unsigned bits = 0;
         #pragma unroll
         for (int v = 0; v < NVAR; ++v) {
             const R out = uo[v] + (R)(b * dt * Q[v]);
             a.Uout[v * a.plane + c] = out;
             bad |= !isfinite(out);
+            if (v >= 5) bits |= (out != R(0)) ? (1u << v) : 0u;
         }
+        mask_mark(a.mask, c, bits);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && next_count) *next_count = 0;
     if (bad) atomicOr(a.flag, 1);
@@ -979,6 +1052,29 @@ template <class R> __global__ void __launch_bounds__(256) k_active_list(const R 
 }
 
 __global__ void k_sur_reset(int *cnt, unsigned long long *tot) { sur_fold_counts(cnt, tot); }
+
+// Tile masks of a state (one workgroup per tile of the given shape).
+template <class R>
+__global__ void __launch_bounds__(256) k_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty,
+                                                   unsigned *mask)
+{
+    __shared__ unsigned acc;
+    const int gx = (nx + tx - 1) / tx;
+    const int ti = blockIdx.x % gx, tj = blockIdx.x / gx;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    unsigned bits = 0;
+    for (int e = threadIdx.x; e < tx * ty; e += blockDim.x) {
+        const int i = ti * tx + e % tx, j = tj * ty + e / tx;
+        if (i >= nx || j >= nr) continue;
+        const long c = (long)j * nx + i;
+        for (int v = 5; v < nv; ++v) bits |= (U[v * plane + c] != R(0)) ? (1u << v) : 0u;
+    }
+    bits = wave_or(bits);
+    if ((threadIdx.x & 63) == 0 && bits) atomicOr(&acc, bits);
+    __syncthreads();
+    if (threadIdx.x == 0) mask[blockIdx.x] = acc;
+}
 
 // ------------------------------------------------------------------ CFL
 // Per-cell limit 1/((|u|+c)/dx + (|v|+c)/dr + 2 nu_eff (1/dx^2 + 1/dr^2)), written
@@ -1531,6 +1627,15 @@ template <class R> hipError_t launch_active_list(const R *U, long plane, int *co
     return hipGetLastError();
 }
 
+template <class R>
+hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
+                            hipStream_t s)
+{
+    const int tiles = ((nx + tx - 1) / tx) * ((nr + ty - 1) / ty);
+    hipLaunchKernelGGL((k_tile_mask<R>), dim3(tiles), dim3(256), 0, s, U, plane, nx, nr, nv, tx, ty, mask);
+    return hipGetLastError();
+}
+
 hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sur_reset, dim3(1), dim3(1), 0, s, cnt, tot);
@@ -1605,6 +1710,7 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_sur_finish<R>(const SurArgs<R> &, const SourceParams &, int *,                 \
                                              unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
+    template hipError_t launch_tile_mask<R>(const R *, long, int, int, int, int, int, unsigned *, hipStream_t); \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, int, hipStream_t);              \
     template hipError_t launch_drift<R>(const DriftArgs<R> &, hipStream_t);                                  \
