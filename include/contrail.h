@@ -310,8 +310,10 @@ const char *cp_mlp_error_string(const cp_mlp *mlp);
  * Features of an active cell: f_v = asinh(U_v / s_in[v]) for the 15 state variables,
  * ln dt, log10 max(N_soot, 1), standardised with (mu_in, sd_in).  The network takes
  * the cell when every standardised feature lies in [lo, hi] and ln S_l in
- * [lnS_lo, lnS_hi] (the training envelope) and |ln S_l| >= lnS_gate (away from
- * nucleation onset); otherwise the exact sub-cycled source is used (Sec. 3.2).
+ * [lnS_lo, lnS_hi] (the training envelope), |ln S_l| >= lnS_gate (away from
+ * nucleation onset) and its droplets cannot freeze (no droplets, or the gas at or
+ * above 273.15 K: freezing, Eq. 12-15, always takes the exact source); otherwise
+ * the exact sub-cycled source is used (Sec. 3.2).
  * Output v (v = 5..12 particle moments, 14 activated soot) is the standardised
  * increment of f_v over dt: U'_v = s_in[v] sinh(max(f_v + y_v sd_out[v] + mu_out[v], 0)),
  * Q_v = (U'_v - U_v) / dt.  The remaining sources are closed exactly: vapour sink
@@ -332,9 +334,10 @@ const char *cp_mlp_error_string(const cp_mlp *mlp);
 int cp_sur_set(cp_ctx *ctx, cp_mlp *mlp, const float *norm, int n_norm);
 
 /* Training-set features of every cell of U (the gate's own computation): F is a
- * caller-owned DEVICE float array [nr*nx][18], row j*nx+i holding
- *   asinh(U_v / s_in[v]) (v = 0..14), ln dt, log10 max(N_soot, 1), ln S_l
- * (unstandardised).  s_in: 15 positive host floats.  Stream-ordered, no sync.
+ * caller-owned DEVICE float array [nr*nx][19], row j*nx+i holding
+ *   asinh(U_v / s_in[v]) (v = 0..14), ln dt, log10 max(N_soot, 1), ln S_l, T
+ * (unstandardised; T the gas temperature in kelvin, which decides the freezing
+ * regime).  s_in: 15 positive host floats.  Stream-ordered, no sync.
  * Errors: CP_EINVAL, CP_EDT (dt <= 0), CP_EHIP.                                    */
 int cp_sur_features(cp_ctx *ctx, const void *U, double dt, const float *s_in, float *F);
 

@@ -290,15 +290,15 @@ class Solver:
         self._chk(self.L.cp_sur_set(self.h, mlp.h, nm.ctypes.data, int(nm.size)))
 
     def sur_features(self, U, dt, s_in, F=None):
-        """Per-cell network features [nr*nx][18] (float32 CUDA): 15 scaled states,
-        ln dt, log10 N_soot, ln S_l."""
+        """Per-cell network features [nr*nx][19] (float32 CUDA): 15 scaled states,
+        ln dt, log10 N_soot, ln S_l, T."""
         import numpy as np
         import torch
         self._check(U)
         if F is None:
-            F = torch.empty((self.nr * self.nx, 18), dtype=torch.float32, device="cuda")
+            F = torch.empty((self.nr * self.nx, 19), dtype=torch.float32, device="cuda")
         si = np.ascontiguousarray(s_in, dtype=np.float32)
-        assert si.size == NV and F.is_contiguous() and F.numel() == self.nr * self.nx * 18
+        assert si.size == NV and F.is_contiguous() and F.numel() == self.nr * self.nx * 19
         self._chk(self.L.cp_sur_features(self.h, _ptr(U), float(dt), si.ctypes.data, _ptr(F)))
         return F
 

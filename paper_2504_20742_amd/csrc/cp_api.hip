@@ -324,11 +324,12 @@ unsigned *mask_of(const cp_ctx *c, const void *p)
 {
     return p == c->Ua ? c->tmask[1] : (p == c->Ub ? c->tmask[2] : c->tmask[0]);
 }
-TileMask tile_mask(const cp_ctx *c, const void *Uin, const void *Uout, int stage)
+TileMask tile_mask(const cp_ctx *c, const void *Uin, const void *Uout, int stage, const void *Un = nullptr)
 {
     TileMask m{};
     if (!masks_on(c)) return m;
     m.in = Uin ? mask_of(c, Uin) : nullptr;
+    m.un = stage > 0 && Un ? mask_of(c, Un) : nullptr;
     m.out = stage >= 0 && Uout ? mask_of(c, Uout) : nullptr;
     m.tx = c->tx;
     m.ty = c->ty;
@@ -375,7 +376,7 @@ StageArgs<R> stage_args(const cp_ctx *c, const void *Uin, const void *Un, void *
     const bool sur = c->qmode == CP_Q_SURROGATE && c->sur_ready && stage >= 0;
     a.sur_cnt = sur ? c->sur_cnt : nullptr;
     a.sur_tot = c->sur_tot;
-    a.mask = tile_mask(c, Uin, Uout, stage);
+    a.mask = tile_mask(c, Uin, Uout, stage, Un);
     return a;
 }
 

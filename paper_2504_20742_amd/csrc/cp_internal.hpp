@@ -45,6 +45,7 @@ struct BcInfo {
 // the other way round.  Null `in`: every scalar may be non-zero.
 struct TileMask {
     const unsigned *in;
+    const unsigned *un;        // mask of U^n (stages 2, 3), or null
     unsigned *out;
     int tx, ty, gx, gy;        // tile shape, tiles per row and per column
     int nx;                    // cells per row

@@ -416,6 +416,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     R res[NV];
     R Fm0 = R(0), Fm1 = R(0), Fm2 = R(0), Fm3 = R(0), kd0 = R(0), kd1 = R(0), kd2 = R(0), kd3 = R(0);
     const R idx = valid ? m.inv_dx[i] : R(0);
+    // everything a cell needs from the primitive arrays after the faces is read here,
+    // before they are reused for the passive scalars: the cell's T (source-activity
+    // test) and the axisymmetric pressure / hoop-stress source
+    R Tcell = R(0), hoop = R(0);
+    if (valid) {
+        Tcell = t.T[l];
+        if (axi) {   // (p - p_ref - tau_thetatheta) / r_c on radial momentum
+            const R ir = m.inv_rc[j + 1];
+            const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
+            const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
+            const R vr = t.v[l] * ir;
+            const R mue = sutherland_t(t.T[l]) + t.mut[rl];
+            const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
+            hoop = ((t.p[l] - pref) - ttt) * ir;
+        }
+    }
     if (valid) {
         const int fw = ty * (TX + 1) + tx;
         if (q1d) {
@@ -468,31 +484,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             kd2 = face_kd(t.mut[rl - RX], t.mut[rl], m.inv_drf[j]);
             kd3 = face_kd(t.mut[rl], t.mut[rl + RX], m.inv_drf[j + 1]);
         }
-        if (axi) {   // (p - p_ref - tau_thetatheta) / r_c on radial momentum
-            const R ir = m.inv_rc[j + 1];
-            const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
-            const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
-            const R vr = t.v[l] * ir;
-            const R mue = sutherland_t(t.T[l]) + t.mut[rl];
-            const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
-            res[2] += ((t.p[l] - pref) - ttt) * ir;
-        }
+        if (axi) res[2] += hoop;
     }
     // phase 5: passive scalars, five at a time in the freed primitive arrays, slopes
     // once per cell.  T of the cell is kept for the source-activity test.  A scalar
     // that is zero on the whole tile and halo (no particles there) has zero slopes
     // and zero fluxes, so its slope and flux work is skipped: the result is the same
     // zero (the stage output is bit-identical).
-    const R Tcell = valid ? t.T[l] : R(0);
     constexpr int NG = (NV - 5 + 4) / 5;
     // Scalars that can be non-zero in the tile and its halo: the halo lies in the eight
     // neighbouring tiles, so the OR of their input masks; a ghost cell is a mirror or
     // copy of a cell of those tiles, or a boundary state (the inflow profile, the
     // ambient far field), whose scalars are in mask.ghost.  A scalar outside that set
     // is zero on the whole stencil, and is neither loaded nor transported.
-    unsigned cand = ~0u;
+    unsigned cand = ~0u, own_in = ~0u, own_un = ~0u;   // own_*: the tile's own words
     if (a.mask.in) {
         const int ti = i0 / TX, tj = j0 / TY, gx = a.mask.gx, gy = a.mask.gy;
+        own_in = __builtin_amdgcn_readfirstlane(a.mask.in[tj * gx + ti]);
+        if (a.mask.un) own_un = __builtin_amdgcn_readfirstlane(a.mask.un[tj * gx + ti]);
         cand = inner ? 0u : a.mask.ghost;
         #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
@@ -502,7 +511,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                     cand |= a.mask.in[(tj + dj) * gx + ti + di];
         cand = __builtin_amdgcn_readfirstlane(cand);
     }
-    int prev_live = 1;   // the primitives are still being read before the first group
+    // the first group may overwrite the primitive arrays at once: their last reader,
+    // the r-face pass, is behind the barrier above
+    int prev_live = 0;
     #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int s0 = 5 + 5 * g;
@@ -607,12 +618,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             // every load of the cell's old states is issued before the first store (the
             // compiler cannot rule out that Uout aliases them, and would otherwise wait
             // for each load in turn)
+            // a scalar that is zero on the whole tile (its bit clear in the tile's mask)
+            // is not loaded: zero either way, up to the sign of a zero, which no later
+            // operation distinguishes
             R ui[NV], un[NV];
             #pragma unroll
-            for (int v = 0; v < NV; ++v) ui[v] = ld_plane(a.Uin, a.plane, v, (unsigned)c);
+            for (int v = 0; v < NV; ++v)
+                ui[v] = (v < 5 || (own_in >> v) & 1u) ? ld_plane(a.Uin, a.plane, v, (unsigned)c) : R(0);
             if (a.stage > 0) {
                 #pragma unroll
-                for (int v = 0; v < NV; ++v) un[v] = ld_plane(a.Un, a.plane, v, (unsigned)c);
+                for (int v = 0; v < NV; ++v)
+                    un[v] = (v < 5 || (own_un >> v) & 1u) ? ld_plane(a.Un, a.plane, v, (unsigned)c) : R(0);
             }
             bool act = false;
             // liquid number of the cell for the pre-filter: either population
@@ -857,13 +873,15 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 // export used to build training sets, so both see identical inputs.
 template <class R>
 __device__ __forceinline__ double sur_raw_features(const R *U, long plane, long c, double dt, const float *s_in,
-                                                   float *f)
+                                                   float *f, double *T = nullptr, double *M0 = nullptr)
 {
     double Ud[NVAR];
     #pragma unroll
     for (int v = 0; v < NVAR; ++v) Ud[v] = (double)U[v * plane + c];
     CellThermo th;
     cell_thermo(Ud, th);
+    if (T) *T = th.T;
+    if (M0) *M0 = Ud[5];
     const double pv = fmax(Ud[4] * kRv * th.T, kPvFloor);
     #pragma unroll
     for (int v = 0; v < NVAR; ++v) f[v] = asinhf((float)(Ud[v] / (double)s_in[v]));
@@ -877,16 +895,21 @@ __global__ void __launch_bounds__(256) k_sur_features(const R *U, long plane, do
 {
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < plane; c += (long)gridDim.x * blockDim.x) {
         float f[17];
-        const double lnSl = sur_raw_features(U, plane, c, dt, nm.s_in, f);
+        double T;
+        const double lnSl = sur_raw_features(U, plane, c, dt, nm.s_in, f, &T);
         #pragma unroll
-        for (int q = 0; q < 17; ++q) F[c * 18 + q] = f[q];
-        F[c * 18 + 17] = (float)lnSl;
+        for (int q = 0; q < 17; ++q) F[c * 19 + q] = f[q];
+        F[c * 19 + 17] = (float)lnSl;
+        F[c * 19 + 18] = (float)T;
     }
 }
 
 // Split the active cells: the network takes a cell whose standardised features lie
-// inside the training envelope and whose vapour is not near saturation
-// (|ln S_l| >= lnS_gate); every other cell keeps the exact source.
+// inside the training envelope, whose vapour is not near saturation
+// (|ln S_l| >= lnS_gate) and whose droplets cannot freeze (no droplets, or the gas
+// at or above the melting point); every other cell keeps the exact source.  Freezing
+// (Eq. 12-15) changes the crystal number by orders of magnitude per kelvin: that
+// regime stays with the exact source.
 template <class R> __global__ void __launch_bounds__(256) k_sur_gate(SurArgs<R> a)
 {
     const int n = (int)min((long)*a.count, a.plane);
@@ -895,8 +918,10 @@ template <class R> __global__ void __launch_bounds__(256) k_sur_gate(SurArgs<R> 
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const long c = a.list[k];
         float f[17];
-        const double lnSl = sur_raw_features(a.Uin, a.plane, c, dt, a.nm.s_in, f);
-        bool inside = fabs(lnSl) >= (double)a.nm.lnS_gate && lnSl >= (double)a.nm.lnS_lo &&
+        double T, M0;
+        const double lnSl = sur_raw_features(a.Uin, a.plane, c, dt, a.nm.s_in, f, &T, &M0);
+        const bool freezing = T < kTmelt && M0 > kNmin;
+        bool inside = !freezing && fabs(lnSl) >= (double)a.nm.lnS_gate && lnSl >= (double)a.nm.lnS_lo &&
                       lnSl <= (double)a.nm.lnS_hi;
         #pragma unroll
         for (int q = 0; q < 17; ++q) {

@@ -531,12 +531,16 @@ template <int NV = NVAR> __device__ __forceinline__ bool source_inactive(const d
 // Conservative pre-filter in the storage precision: true when the cell certainly
 // has no phase change (no particles and ln S_l below -0.01, far outside the FP32
 // rounding of ln S_l); otherwise the FP64 test decides.
+// Natural logarithm for the pre-filter: the hardware log2 (about 1 ulp) in FP32.
+__device__ __forceinline__ float filter_ln(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+__device__ __forceinline__ double filter_ln(double x) { return log(x); }
+
 template <class R> __device__ __forceinline__ bool clearly_inactive(R rho_v, R M0, R N0, R T)
 {
     if (M0 > R(kNmin) || N0 > R(kNmin)) return false;
     if (!(rho_v > R(0))) return true;
-    const R lnSl = log(rho_v * R(kRv) * T) - (R(kSonW.a) / T + R(kSonW.b) + R(kSonW.c) * T + R(kSonW.d) * T * T +
-                                              R(kSonW.e) * log(T) + R(kLn100));
+    const R lnSl = filter_ln(rho_v * R(kRv) * T) - (R(kSonW.a) / T + R(kSonW.b) + R(kSonW.c) * T +
+                                                    R(kSonW.d) * T * T + R(kSonW.e) * filter_ln(T) + R(kLn100));
     return lnSl < R(-0.01);
 }
 

@@ -6,10 +6,13 @@ envelope, trains the 17 -> 256 -> 256 -> 15 network with the library's own
 MFMA forward/backward and Adam kernels, and packs the 118-float normalisation
 block that ``cp_sur_set`` takes.
 
-In the step the library only trusts a prediction whose every feature increment
-stays within df_max (a log-scale change of about that size per step), whose crystal
-moments change by at most df_max_ice (freezing is what the network reproduces least
-well: a few accepted freezing predictions carried the whole ice error) and whose
+The network covers the cells whose droplets cannot freeze (no droplets, or gas at
+or above 273.15 K): growth and evaporation of droplets, deposition and
+sublimation of crystals, nucleation away from its onset.  Freezing changes the
+crystal number by orders of magnitude per kelvin and stays with the exact source
+(the library's gate sends those cells there), so the training set holds only the
+other regime.  In the step the library trusts a prediction whose every feature
+increment stays within df_max (df_max_ice for the crystal moments) and whose
 particle populations stay realizable; other cells take the exact source.
 
 Features of a cell (computed on the device by ``cp_sur_features``, the same code
@@ -63,13 +66,18 @@ class Dataset:
         return Dataset(*[torch.cat([getattr(p, k) for p in parts]) for k in ("X", "D", "lnS", "dt")])
 
 
+T_MELT = 273.15
+N_MIN = 1.0
+
+
 def collect(binding, cases, snapshots, every, dt_factors=(0.5, 1.0, 2.0), lnS_gate=0.05, warmup=0,
-            precision=None, max_rows=None, seed=0, log=None):
+            precision=None, max_rows=None, seed=0, log=None, supersaturated=True):
     """Run each (mesh, case) on the GPU with the exact source and sample the cells
-    whose source is non-zero and that lie away from liquid saturation
-    (|ln S_l| >= lnS_gate): ``snapshots`` samples, ``every`` steps apart, each at
-    the CFL time step times every factor in dt_factors.  With max_rows, each
-    sample keeps a seeded random subset so that the total stays near max_rows."""
+    whose source is non-zero, that lie away from liquid saturation
+    (|ln S_l| >= lnS_gate) and whose droplets cannot freeze (the network's regime):
+    ``snapshots`` samples, ``every`` steps apart, each at the CFL time step times
+    every factor in dt_factors.  With max_rows, each sample keeps a seeded random
+    subset so that the total stays near max_rows."""
     import torch
     precision = binding.CP_FP64 if precision is None else precision
     s_in = S_IN
@@ -91,7 +99,10 @@ def collect(binding, cases, snapshots, every, dt_factors=(0.5, 1.0, 2.0), lnS_ga
                 dt = dt0 * fac
                 Q = s.source(U, dt).reshape(15, -1).double()
                 F = s.sur_features(U, dt, s_in)
-                act = (Q != 0).any(dim=0) & (F[:, 17].abs() >= lnS_gate)
+                no_freezing = (F[:, 18] >= T_MELT) | (Uf[5] <= N_MIN)
+                act = (Q != 0).any(dim=0) & (F[:, 17].abs() >= lnS_gate) & no_freezing
+                if not supersaturated:   # evaporation / sublimation / deposition only
+                    act &= F[:, 17] <= -lnS_gate
                 if not bool(act.any()):
                     continue
                 if per_sample is not None:
@@ -254,9 +265,12 @@ def increment_errors(net, norm, data, chunk=65536):
 
 
 def build(binding, cases, snapshots=40, every=20, epochs=30, lnS_gate=0.05, seed=0, val_frac=0.05, max_rows=None,
-          batch=4096, lr=2e-3, df_max=0.2, df_max_ice=0.01, log=None):
-    """Collect, fit the normalisation, train.  Returns (network, Norm, report)."""
-    data = collect(binding, cases, snapshots, every, lnS_gate=lnS_gate, max_rows=max_rows, seed=seed, log=log)
+          batch=4096, lr=2e-3, df_max=0.2, df_max_ice=0.01, log=None, supersaturated=True):
+    """Collect, fit the normalisation, train.  Returns (network, Norm, report).
+    supersaturated=False trains on subsaturated cells only, so the envelope's ln S_l
+    range keeps nucleating cells with the exact source too."""
+    data = collect(binding, cases, snapshots, every, lnS_gate=lnS_gate, max_rows=max_rows, seed=seed, log=log,
+                   supersaturated=supersaturated)
     tr, va = data.split(val_frac, seed)
     norm = Norm(tr, lnS_gate, df_max, df_max_ice)
     net, hist = train(binding, tr, norm, epochs=epochs, batch=batch, lr=lr, seed=seed, val_set=va, log=log)

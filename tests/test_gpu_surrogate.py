@@ -11,10 +11,14 @@ feeds the step, and what it gains.
 * A mixed-precision run with the surrogate in the step is compared with the FP64
   oracle on the gas state, ice number and water mass, next to the mixed path with
   the exact source: the mixed gates hold (gas 1e-4, ice mu0 2e-2) with the network
-  taking some of the cells (the trust bounds df_max = 0.2, df_max_ice = 0.01 keep it
-  to the few cells where it is reliable).
+  taking cells (trust bounds df_max = 0.5, df_max_ice = 0.05 in this test; the
+  library's defaults 0.2 / 0.01 leave it almost no cell).
+* The cells the network takes, one by one, against the exact source of the same
+  cell (the network's judge): bars on vapour, droplet and crystal moments.
 * Gain: step time of the mixed path with the exact source over the same path
-  with the surrogate, on a source-active jet; any value is a valid outcome.
+  with the surrogate, on a source-active jet.  Expected below 1: the exact source's
+  time is set by its stiffest cells (64 sub-steps), freezing cells among them,
+  which stay exact; the network only adds its launches.
 """
 import copy
 import time
@@ -23,6 +27,7 @@ import numpy as np
 import pytest
 
 from paper_2504_20742_amd import inputs
+from paper_2504_20742_amd.surrogate import S_IN
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -78,6 +83,7 @@ def test_features_match_oracle(B, S, orc):
         pv = max(u[4] * 461.52 * T, 1e-9)
         lnS = np.log(pv) - L.or_ln_psat_liq(T)
         assert abs(F[k, 17] - lnS) < 1e-5 * max(1.0, abs(lnS)), (k, F[k, 17], lnS)
+        assert abs(F[k, 18] - T) < 1e-6 * T, (k, F[k, 18], T)
 
 
 def test_training_learns(trained):
@@ -144,8 +150,19 @@ def test_surrogate_source_closure(B, trained):
     s.close()
 
 
+def _test_norm(norm):
+    """The trust bounds of the in-loop tests: 0.5 in feature space, 0.05 for the
+    crystal moments (a sweep on this jet: 0.2 / 0.01 accept no cell; 1 / 0.2 break
+    the ice gate)."""
+    t = copy.copy(norm)
+    t.df_max = 0.5
+    t.df_max_ice = 0.05
+    return t
+
+
 def test_surrogate_run_against_oracle(B, orc, trained):
     net, norm, _ = trained
+    norm = _test_norm(norm)
     steps = 300
     m, c = inputs.sa1(1)
     o = orc.Oracle(m, c)
@@ -163,7 +180,8 @@ def test_surrogate_run_against_oracle(B, orc, trained):
         Ug = U.double().cpu().numpy()
         gas = max(_rel(Ug[0], Uo[0]), _rel(Ug[3], Uo[3]), _rel(Ug[4], Uo[4]),
                   np.sqrt(np.sum((Ug[1:3] - Uo[1:3]) ** 2) / np.sum(Uo[1:3] ** 2)))
-        res[mode] = dict(gas=gas, ice=_rel(Ug[9], Uo[9]), water=abs(d["water"] - o.diag(Uo)["water"]) / o.diag(Uo)["water"],
+        res[mode] = dict(gas=gas, ice=_rel(Ug[9], Uo[9]), liquid=_rel(Ug[5], Uo[5]),
+                         water=abs(d["water"] - o.diag(Uo)["water"]) / o.diag(Uo)["water"],
                          t=t, net=d["surrogate_cells"], fb=d["fallback_cells"])
         s.close()
         assert np.isfinite(Ug).all()
@@ -175,6 +193,48 @@ def test_surrogate_run_against_oracle(B, orc, trained):
     assert res["surrogate"]["gas"] <= 1e-4
     assert res["surrogate"]["ice"] <= 2e-2
     assert res["surrogate"]["water"] <= 1e-4
+
+
+def test_network_cells_against_exact_source(B, trained):
+    """Every cell the network takes (gate and decode accepted), against the exact
+    sub-cycled source of the same cell over the same dt, on the end state U + dt Q:
+    per-variable relative error of vapour, droplet moments and crystal number
+    (relative to the exact end value, floored at the features' physical scale).
+    Bars: median and 95th percentile, stated below."""
+    net, norm, _ = trained
+    norm = _test_norm(norm)
+    errs = {v: [] for v in (4, 5, 6, 7, 8, 9)}
+    for seed in (1, 2, 3):
+      s, U = _state(B, seed, 100)
+      s.sur_set(net, norm.pack())
+      for snap in range(30):       # the network's cells are sporadic: many snapshots
+        s.step_n(U, 10)
+        dt = s.cfl_dt(U)
+        s.set_qmode(B.CP_Q_EXACT)
+        Qx = s.source(U, dt).cpu().numpy().reshape(15, -1)
+        s.set_qmode(B.CP_Q_SURROGATE)
+        Qs = s.source(U, dt).cpu().numpy().reshape(15, -1)
+        Uh = U.cpu().numpy().reshape(15, -1)
+        net_cells = np.any(Qs != Qx, axis=0)
+        for v in errs:
+            Ex, Es = Uh[v] + dt * Qx[v], Uh[v] + dt * Qs[v]
+            # relative to the exact end value, floored at the features' physical scale
+            # (one particle per m^3 for the numbers, a 1 nm radius for the moments)
+            floor = 1e-12 if v == 4 else float(S_IN[v])
+            ref = np.maximum(np.abs(Ex), floor)
+            errs[v].append(np.abs(Es - Ex)[net_cells] / ref[net_cells])
+      s.close()
+    n = sum(len(e) for e in errs[4])
+    stats = {v: (float(np.median(np.concatenate(e))), float(np.percentile(np.concatenate(e), 95)))
+             for v, e in errs.items()}
+    print("network cells %d; median / 95th percentile relative error: %s" % (n, stats))
+    assert n >= 20
+    # measured on 38 cells: vapour 4e-12 / 7e-4, droplet moments 0.10-0.20 / 0.33-0.62,
+    # crystal number 0.023 / 0.043 -- the network's droplet moments are what keeps
+    # the trust bounds tight
+    BARS = {4: (1e-6, 5e-3), 5: (0.35, 1.0), 6: (0.35, 1.0), 7: (0.35, 1.0), 8: (0.35, 1.0), 9: (0.05, 0.15)}
+    for v, (med, p95) in BARS.items():
+        assert stats[v][0] <= med and stats[v][1] <= p95, (v, stats[v])
 
 
 def test_surrogate_gain(B, S):
@@ -204,9 +264,13 @@ def test_surrogate_gain(B, S):
         assert np.isfinite(U.cpu().numpy()).all()
         s.close()
     gain = times["exact"] / times["surrogate"]
-    print("gain %.3f (exact %.3f ms/step, surrogate %.3f ms/step, network/fallback cells %s, train %s)"
-          % (gain, 1e3 * times["exact"], 1e3 * times["surrogate"], fr, rep["final_val_loss"]))
-    assert gain > 0
+    share = fr[0] / max(fr[0] + fr[1], 1.0)
+    print("gain %.3f (exact %.3f ms/step, surrogate %.3f ms/step, network/fallback cells %s, share %.2e, train %s)"
+          % (gain, 1e3 * times["exact"], 1e3 * times["surrogate"], fr, share, rep["final_val_loss"]))
+    # the stated expectation (library defaults): the network takes well under 1 % of
+    # the active cell-stages, and the step is no faster than with the exact source
+    assert share < 0.01
+    assert 0.3 < gain < 1.05
 
 
 def test_attach_snapshots_the_weights(B, trained):
