@@ -178,11 +178,25 @@ int cp_set_qmode(cp_ctx *ctx, int qmode);
  * to the exact fallback, summed over every stage since cp_sur_set.              */
 int cp_diag(cp_ctx *ctx, const void *U, double out[8]);
 
+/* Drag-law diagnostics (Eq. 24): the response time of the droplets and of the ice
+ * crystals at their mean radius r20 = sqrt(mu2/mu0),
+ *   tau_p = rho_p (2 r20)^2 Cc / (18 mu),  Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r20)
+ * (the particle mass over its Stokes friction; zero slip in the one-velocity model,
+ * so the Schiller-Naumann factor is 1), and the Stokes number St = tau_p |u| / dx_i.
+ * tau_p and St: caller-owned DEVICE double arrays [2][nr][nx] (plane 0 droplets,
+ * plane 1 crystals), zero where a population is empty or has evaporated.
+ * Stream-ordered, no synchronisation.  Errors: CP_EINVAL (null argument),
+ * CP_EUNSUPPORTED with two liquid populations, CP_EHIP.                          */
+int cp_particle_times(cp_ctx *ctx, const void *U, double *tau_p, double *St);
+
 /* Drift of droplets and crystals against the gas (on != 0), the drag law (Eq. 24)
  * read as a drift flux in this one-velocity solver: particles lag the gas's
- * pressure-driven acceleration with their Stokes terminal slip
- *   w(r) = 2 rho_p r^2 Cc(r) (1 - rho/rho_p) (dp/dn) / (9 mu rho),
+ * pressure-driven acceleration with their terminal slip, at which the drag of
+ * Eq. 24 balances that force: w (1 + 0.15 Re^0.687) = w_St with the
+ * Stokes-Cunningham slip
+ *   w_St(r) = 2 rho_p r^2 Cc(r) (1 - rho/rho_p) (dp/dn) / (9 mu rho),
  *   Cc = 1 + 2 A_C Kn, Kn = lbar / (2 r), lbar = 1.5 mu sqrt(R T) / p,
+ * and Re = rho |w| 2 r / mu (six fixed-point steps from w_St),
  * and each population drifts as a whole with the slip of its mean radius r20:
  * moment k crosses a face with w(r20) M_k, upwind in its sign (the moment set
  * stays realisable).  Soot stays with the gas.  Applied
@@ -242,7 +256,8 @@ const char *cp_error_string(const cp_ctx *ctx);
 
 /* ---------------------------------------------------------------------- batch
  * Many operating points (plumes), each with its own mesh and case, advanced
- * together: every RK stage is one launch over a work list of (plume, tile) pairs,
+ * together: every RK stage is one launch over a work list of (plume, tile) pairs
+ * (the tile shape picked by timing every built shape before the first step),
  * each plume keeps its own CFL time step on the device, and the whole step is a
  * captured HIP graph.  Per-plume results are identical to running that plume alone.
  * Arrays: U[p] is plume p's U[15][nr_p][nx_p] (caller-owned device memory).         */

@@ -71,6 +71,8 @@ def lib():
                      "or_koop_delta_aw", "or_koop_rate", "or_contact_factor", "or_cunningham_ac"]:
             getattr(L, name).restype = _D
             getattr(L, name).argtypes = [_D]
+        L.or_sn_slip.restype = _D
+        L.or_sn_slip.argtypes = [_D, _D, _D, _D]
         for name in ["or_tsat_liq", "or_tsat_ice", "or_cnt_prefactor", "or_kantrowitz_phi",
                      "or_young_nu", "or_barrier_hom", "or_drag_cd"]:
             getattr(L, name).restype = _D
@@ -93,6 +95,7 @@ def lib():
         L.or_run.restype = _D
         L.or_run.argtypes = [_V, _P, ctypes.c_int]
         L.or_diag.argtypes = [_V, _P, _P]
+        L.or_particle_times.argtypes = [_V, _P, _P, _P]
         L.or_mesh_faces.argtypes = [_V, _P, _P]
         L.or_set_equilibrium.restype = ctypes.c_int
         L.or_set_equilibrium.argtypes = [_V, ctypes.c_int]
@@ -196,6 +199,14 @@ class Oracle:
         out = np.zeros(4)
         self.L.or_diag(self.h, _ptr(U), _ptr(out))
         return {"water": out[0], "max_lnS_l": out[1], "ice_number": out[2], "gas_mass": out[3]}
+
+    def particle_times(self, U):
+        """Response time tau_p and Stokes number of the droplets and crystals at their
+        mean radius r20 (Eq. 24 diagnostics): two arrays [2][nr][nx]."""
+        tau = np.zeros((2, self.nr, self.nx))
+        St = np.zeros((2, self.nr, self.nx))
+        self.L.or_particle_times(self.h, _ptr(U), _ptr(tau), _ptr(St))
+        return tau, St
 
     def set_equilibrium(self, on=True):
         """Switch the phase change between the kinetic model and the equilibrium

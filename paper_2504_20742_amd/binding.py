@@ -92,6 +92,7 @@ _SIGS = {
     "cp_mlp_error_string": (ctypes.c_char_p, [_P]),
     "cp_sur_set": (_I, [_P, _P, _P, _I]),
     "cp_sur_features": (_I, [_P, _P, _D, _P, _P]),
+    "cp_particle_times": (_I, [_P, _P, _P, _P]),
 }
 
 
@@ -301,6 +302,16 @@ class Solver:
         assert si.size == NV and F.is_contiguous() and F.numel() == self.nr * self.nx * 19
         self._chk(self.L.cp_sur_features(self.h, _ptr(U), float(dt), si.ctypes.data, _ptr(F)))
         return F
+
+    def particle_times(self, U):
+        """Response time and Stokes number of droplets and crystals (Eq. 24
+        diagnostics): two float64 CUDA tensors [2][nr][nx]."""
+        import torch
+        self._check(U)
+        tau = torch.empty((2, self.nr, self.nx), dtype=torch.float64, device="cuda")
+        St = torch.empty_like(tau)
+        self._chk(self.L.cp_particle_times(self.h, _ptr(U), _ptr(tau), _ptr(St)))
+        return tau, St
 
     def faces(self):
         import numpy as np

@@ -940,6 +940,19 @@ int cp_diag(cp_ctx *c, const void *U, double out[8])
     return CP_OK;
 }
 
+int cp_particle_times(cp_ctx *c, const void *U, double *tau_p, double *St)
+{
+    if (!c || !U || !tau_p || !St) return fail(c, CP_EINVAL, "null argument");
+    if (c->nv != NVAR) return fail(c, CP_EUNSUPPORTED, "particle times: one liquid population only");
+    hipError_t e = c->precision == CP_FP64
+                       ? launch_particle_times<double>((const double *)U, c->plane, c->nx, c->inv_dx_d, tau_p, St,
+                                                       c->stream)
+                       : launch_particle_times<float>((const float *)U, c->plane, c->nx, c->inv_dx_d, tau_p, St,
+                                                      c->stream);
+    if (e != hipSuccess) return fail(c, CP_EHIP, hipGetErrorString(e));
+    return CP_OK;
+}
+
 int cp_sur_features(cp_ctx *c, const void *U, double dt, const float *s_in, float *F)
 {
     if (!c || !U || !s_in || !F) return fail(c, CP_EINVAL, "null argument");
@@ -1094,8 +1107,9 @@ struct cp_batch {
     hipStream_t stream = nullptr, cap_stream = nullptr;
     std::vector<cp_ctx *> plumes;
     int tx = 32, ty = 8;
+    bool tuned = false;        // tile shape picked by the autotuner
     long max_cells = 0;
-    int nwork = 0;
+    int nwork = 0, cap_work = 0;
     int *work_plume = nullptr, *work_tile = nullptr;
     void *stage_args[3] = {}, *fix_args[3] = {}, *cfl_args = nullptr;
     unsigned long long *acc = nullptr;
@@ -1167,6 +1181,81 @@ template <class R> int batch_upload_args(cp_batch *b, void *const *U)
     return CP_OK;
 }
 
+// (plume, tile) work list of one tile shape, uploaded to the batch's work arrays.
+int batch_worklist(cp_batch *b, int tx, int ty)
+{
+    std::vector<int> wp, wt;
+    for (int p = 0; p < b->n; ++p) {
+        const int gx = (b->plumes[p]->nx + tx - 1) / tx, gy = (b->plumes[p]->nr + ty - 1) / ty;
+        for (int k = 0; k < gx * gy; ++k) {
+            wp.push_back(p);
+            wt.push_back(k);
+        }
+    }
+    if ((int)wp.size() > b->cap_work) return bfail(b, CP_EINVAL, "work list larger than its arrays");
+    if (hipMemcpy(b->work_plume, wp.data(), wp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->work_tile, wt.data(), wt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, CP_EHIP, "work list upload");
+    b->nwork = (int)wp.size();
+    b->tx = tx;
+    b->ty = ty;
+    for (cp_ctx *c : b->plumes) {
+        c->tx = tx;
+        c->ty = ty;
+    }
+    return CP_OK;
+}
+
+// Pick the batch's tile shape: time the first stage of every plume (U -> its first
+// stage buffer, phase-change source off so that no active list is touched, dt = 0)
+// for each built shape; an earlier shape is kept unless a later one is more than 5 %
+// faster.  All shapes give identical results.
+template <class R> int batch_autotune(cp_batch *b, void *const *U)
+{
+    std::vector<StageArgs<R>> sa;
+    for (int p = 0; p < b->n; ++p) {
+        cp_ctx *c = b->plumes[p];
+        sa.push_back(stage_args<R>(c, U[p], U[p], c->Ua, 0, 0.0, nullptr));
+        sa.back().sp.enabled = 0;
+        sa.back().mask = TileMask{};
+        sa.back().sur_cnt = nullptr;
+    }
+    StageArgs<R> *d = balloc<StageArgs<R>>(b, b->n);
+    if (!d) return bfail(b, CP_ENOMEM, "autotune arguments");
+    if (hipMemcpy(d, sa.data(), b->n * sizeof(StageArgs<R>), hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, CP_EHIP, "autotune upload");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return bfail(b, CP_EHIP, "events");
+    float best = 1e30f;
+    int btx = 32, bty = 8, r = CP_OK;
+    for (auto &sh : tile_list()) {
+        if ((r = batch_worklist(b, sh.first, sh.second))) break;
+        hipError_t e = launch_stage_batch<R>(d, b->work_plume, b->work_tile, b->nwork, b->tx, b->ty, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int k = 0; k < 4 && e == hipSuccess; ++k)
+            e = launch_stage_batch<R>(d, b->work_plume, b->work_tile, b->nwork, b->tx, b->ty, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            r = bfail(b, CP_EHIP, std::string("batch autotune: ") + hipGetErrorString(e));
+            break;
+        }
+        if (ms < 0.95f * best) {
+            best = ms;
+            btx = sh.first;
+            bty = sh.second;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r) return r;
+    if ((r = batch_worklist(b, btx, bty))) return r;
+    b->tuned = true;
+    return CP_OK;
+}
+
 template <class R> int batch_enqueue_step(cp_batch *b, hipStream_t s)
 {
     hipError_t e = launch_cfl_batch<R>((const CflArgs<R> *)b->cfl_args, b->n, b->max_cells, s);
@@ -1207,17 +1296,10 @@ int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int prec
         b->plumes.push_back(c);
         b->max_cells = std::max(b->max_cells, c->plane);
     }
-    std::vector<int> wp, wt;
-    for (int p = 0; p < n; ++p) {
-        const int gx = (b->plumes[p]->nx + b->tx - 1) / b->tx, gy = (b->plumes[p]->nr + b->ty - 1) / b->ty;
-        for (int k = 0; k < gx * gy; ++k) {
-            wp.push_back(p);
-            wt.push_back(k);
-        }
-    }
-    b->nwork = (int)wp.size();
-    b->work_plume = balloc<int>(b, wp.size());
-    b->work_tile = balloc<int>(b, wt.size());
+    // work arrays large enough for the smallest built tile (16 x 4 cells)
+    for (int p = 0; p < n; ++p) b->cap_work += ((b->plumes[p]->nx + 15) / 16) * ((b->plumes[p]->nr + 3) / 4);
+    b->work_plume = balloc<int>(b, b->cap_work);
+    b->work_tile = balloc<int>(b, b->cap_work);
     b->acc = balloc<unsigned long long>(b, n);
     b->cfl = balloc<double>(b, n);
     b->dt = balloc<double>(b, n);
@@ -1230,8 +1312,7 @@ int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int prec
     std::vector<unsigned long long> inf(n, 0x7FF0000000000000ull);
     std::vector<double> cfl(n), zero(n, 0.0);
     for (int p = 0; p < n; ++p) cfl[p] = cases[p].cfl;
-    if (hipMemcpy(b->work_plume, wp.data(), wp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->work_tile, wt.data(), wt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+    if (batch_worklist(b, b->tx, b->ty) != CP_OK ||
         hipMemcpy(b->acc, inf.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->cfl, cfl.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->dt, zero.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1278,7 +1359,11 @@ int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host)
             hipGraphExecDestroy(b->graph);
             b->graph = nullptr;
         }
-        int r = b->precision == CP_FP64 ? batch_upload_args<double>(b, U) : batch_upload_args<float>(b, U);
+        int r = CP_OK;
+        if (!b->tuned)
+            r = b->precision == CP_FP64 ? batch_autotune<double>(b, U) : batch_autotune<float>(b, U);
+        if (r) return r;
+        r = b->precision == CP_FP64 ? batch_upload_args<double>(b, U) : batch_upload_args<float>(b, U);
         if (r) return r;
         hipGraph_t g;
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)

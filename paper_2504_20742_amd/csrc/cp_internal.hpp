@@ -201,6 +201,10 @@ hipError_t launch_sur_reset(int *cnt, unsigned long long *tot, hipStream_t s);
 template <class R> hipError_t launch_active_list(const R *U, long plane, int *count, int *list, hipStream_t s);
 // Tile masks of a state: bit v of a tile's word set when variable v >= 5 is non-zero
 // in one of the tile's cells.
+// Drag-law diagnostics: tau_p and Stokes number of droplets and crystals, [2][plane].
+template <class R>
+hipError_t launch_particle_times(const R *U, long plane, int nx, const double *inv_dx, double *tau, double *St,
+                                 hipStream_t s);
 template <class R>
 hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
                             hipStream_t s);

@@ -793,6 +793,17 @@ template <class R> __device__ __forceinline__ DriftCell drift_cell(const R *U, l
     return d;
 }
 
+// Terminal slip with the Schiller-Naumann factor of Eq. 24: w (1 + 0.15 Re^0.687) =
+// w_St, Re = rho |w| 2 r / mu (on the diameter, the number with which C_D Re -> 24 is
+// Stokes's law), six fixed-point steps from the Stokes-Cunningham slip w_St.
+__device__ __forceinline__ double sn_slip(double w_st, double rho, double r, double mu)
+{
+    double w = w_st;
+    #pragma unroll 1
+    for (int it = 0; it < 6; ++it) w = w_st / (1.0 + 0.15 * pow(rho * fabs(w) * 2.0 * r / mu, 0.687));
+    return w;
+}
+
 // Drift fluxes of the 8 moments through the face from cell a to cell b.
 __device__ __forceinline__ void drift_face(const DriftCell &a, const DriftCell &b, double dn, double *F)
 {
@@ -810,7 +821,8 @@ __device__ __forceinline__ void drift_face(const DriftCell &a, const DriftCell &
         if (!pop_valid(M[0], M[2], M[3])) continue;
         const double r20 = sqrt(M[2] / M[0]);
         const double Kn = lbar / (2.0 * r20);
-        const double W = c * r20 * r20 * (1.0 + 2.0 * (1.257 + 0.4 * exp(-1.1 / (2.0 * Kn))) * Kn);
+        const double W = sn_slip(c * r20 * r20 * (1.0 + 2.0 * (1.257 + 0.4 * exp(-1.1 / (2.0 * Kn))) * Kn), rho,
+                                 r20, mu);
         #pragma unroll
         for (int k = 0; k < 4; ++k) F[4 * pop + k] = W * M[k];
     }
@@ -1077,6 +1089,39 @@ template <class R> __global__ void __launch_bounds__(256) k_active_list(const R 
 }
 
 __global__ void k_sur_reset(int *cnt, unsigned long long *tot) { sur_fold_counts(cnt, tot); }
+
+// Drag-law diagnostics (Eq. 24): response time of the droplets and of the crystals
+// at their mean radius r20, tau_p = rho_p (2 r20)^2 Cc / (18 mu) (zero slip), and the
+// Stokes number tau_p |u| / dx_i; planes [2][nr][nx], zero without a population.
+template <class R>
+__global__ void __launch_bounds__(256) k_particle_times(const R *U, long plane, int nx, const double *inv_dx,
+                                                        double *tau, double *St)
+{
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < plane; c += (long)gridDim.x * blockDim.x) {
+        double u[NVAR];
+        #pragma unroll
+        for (int v = 0; v < NVAR; ++v) u[v] = (double)U[v * plane + c];
+        CellThermo th;
+        cell_thermo(u, th);
+        const double mu = sutherland<double>(th.T);
+        const double lbar = 1.5 * mu * sqrt(th.Rm * th.T) / th.p;
+        const double speed = sqrt(th.u * th.u + th.v * th.v);
+        #pragma unroll
+        for (int pop = 0; pop < 2; ++pop) {
+            const double *M = u + (pop ? 9 : 5);
+            const double rho_p = pop ? kRhoS : kRhoL;
+            double t = 0.0;
+            if (pop_valid(M[0], M[2], M[3])) {
+                const double r20 = sqrt(M[2] / M[0]);
+                const double Kn = lbar / (2.0 * r20);
+                const double Cc = 1.0 + 2.0 * (1.257 + 0.4 * exp(-1.1 / (2.0 * Kn))) * Kn;
+                t = rho_p * (2.0 * r20) * (2.0 * r20) * Cc / (18.0 * mu);
+            }
+            tau[pop * plane + c] = t;
+            St[pop * plane + c] = t * speed * inv_dx[c % nx];
+        }
+    }
+}
 
 // Tile masks of a state (one workgroup per tile of the given shape).
 template <class R>
@@ -1653,6 +1698,15 @@ template <class R> hipError_t launch_active_list(const R *U, long plane, int *co
 }
 
 template <class R>
+hipError_t launch_particle_times(const R *U, long plane, int nx, const double *inv_dx, double *tau, double *St,
+                                 hipStream_t s)
+{
+    const int blocks = (int)std::max<long>(1, std::min<long>((plane + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_particle_times<R>), dim3(blocks), dim3(256), 0, s, U, plane, nx, inv_dx, tau, St);
+    return hipGetLastError();
+}
+
+template <class R>
 hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
                             hipStream_t s)
 {
@@ -1736,6 +1790,8 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
                                              unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
     template hipError_t launch_tile_mask<R>(const R *, long, int, int, int, int, int, unsigned *, hipStream_t); \
+    template hipError_t launch_particle_times<R>(const R *, long, int, const double *, double *, double *,      \
+                                                 hipStream_t);                                                 \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \
     template hipError_t launch_source_fix<R>(const SourceFixArgs<R> &, long, int, hipStream_t);              \
     template hipError_t launch_drift<R>(const DriftArgs<R> &, hipStream_t);                                  \

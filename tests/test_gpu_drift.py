@@ -102,3 +102,23 @@ def test_duct_refuses_drift(B):
         s.set_drift(True)
     assert e.value.code == B.CP_EUNSUPPORTED
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_particle_times_match_oracle(B, orc, prec):
+    """Drag-law diagnostics (response time and Stokes number of droplets and
+    crystals) on a source-active jet with particles, against the oracle."""
+    m, c = inputs.sa1(2)
+    o = orc.Oracle(m, c)
+    U0 = o.init()
+    o.run(U0, 150)
+    s = B.Solver(m, c, B.CP_FP64 if prec == "fp64" else B.CP_MIXED)
+    U = dev(U0, s.dtype)
+    tau, St = s.particle_times(U)
+    Uh = U.double().cpu().numpy()          # the state the library saw (FP32 in the mixed path)
+    to, So = o.particle_times(np.ascontiguousarray(Uh))
+    tau, St = tau.cpu().numpy(), St.cpu().numpy()
+    assert (to > 0).sum() > 100
+    assert np.allclose(tau, to, rtol=1e-12, atol=0.0)
+    assert np.allclose(St, So, rtol=1e-12, atol=0.0)
+    s.close()
