@@ -238,6 +238,8 @@ def run_source_active(binding, inputs, steps, warmup, trained, which=ACTIVE_PATH
     out = {k: {kk: v for kk, v in d.items() if kk not in ("esz", "cells", "wall_s")} for k, d in res.items()}
     if "mixed" in res and "mixed_surrogate" in res:
         out["gain"] = res["mixed"]["ms_per_step"] / res["mixed_surrogate"]["ms_per_step"]
+    if "mixed" in which:
+        out["exact_source_cost"] = exact_source_cost(binding, m, c, warmup)
     if "mixed" in res and "mixed_equilibrium" in res and res["mixed"].get("condensed_water_per_rad"):
         out["equilibrium_over_kinetic_condensed_water"] = (res["mixed_equilibrium"].get("condensed_water_per_rad", 0.0)
                                                            / res["mixed"]["condensed_water_per_rad"])
@@ -247,6 +249,38 @@ def run_source_active(binding, inputs, steps, warmup, trained, which=ACTIVE_PATH
                                      "val_loss": rep["final_val_loss"]}
     out["steps"] = steps
     out["warmup"] = warmup
+    return out
+
+
+def exact_source_cost(binding, m, c, warmup, reps=10):
+    """Cost of the exact sub-cycled source on the source-active state (mixed path):
+    one cp_source call over the mesh, timed with HIP events; per active cell and per
+    sub-step of those cells.  The call is latency-bound (its time is set by the
+    stiffest cells' sequential sub-steps), so the per-cell figure is an average."""
+    import torch
+    s = binding.Solver(m, c, binding.CP_MIXED)
+    U = s.init()
+    s.step_n(U, max(warmup, 1))
+    dt = s.cfl_dt(U)
+    Q = s.source(U, dt)
+    d = s.diag(U)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        s.source(U, dt, Q)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    subs = s.diag(U)["nsub_total"]     # counted from the last cp_source call on
+    s.close()
+    del U, Q
+    torch.cuda.empty_cache()
+    active = max(d["active_cells"], 1.0)
+    out = {"ms_per_call": ms, "active_cells": d["active_cells"], "ns_per_active_cell": ms * 1e6 / active}
+    if subs:
+        out["substeps_per_call"] = subs
+        out["ns_per_cell_substep"] = ms * 1e6 / subs
     return out
 
 
@@ -269,7 +303,8 @@ def run_mlp_inference(binding, net, rows, reps=5):
     flop = rows * 2.0 * (17 * 256 + 256 * 256 + 256 * 15)
     del X
     torch.cuda.empty_cache()
-    return {"rows": rows, "ms": ms, "tflops": flop / ms / 1e9, "frac_of_bf16_dense_peak": flop / ms / 1e9 / 2500.0}
+    return {"rows": rows, "ms": ms, "ns_per_row": ms * 1e6 / rows, "tflops": flop / ms / 1e9,
+            "frac_of_bf16_dense_peak": flop / ms / 1e9 / 2500.0}
 
 
 def copy_bandwidth(gib=1.0, reps=10):
@@ -368,7 +403,7 @@ def main():
     ap.add_argument("--active-warmup", type=int, default=200)
     ap.add_argument("--active-paths", default=",".join(ACTIVE_PATHS),
                     help="source-active paths to run (comma-separated subset of %s)" % ",".join(ACTIVE_PATHS))
-    ap.add_argument("--batch-steps", type=int, default=50, help="steps of the 64-plume batch (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2000, help="steps of the 64-plume batch (0: skip)")
     ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
     ap.add_argument("--tile", default="", help="stage tile of the production-jet paths, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--hbm-copy-gib", type=float, default=1.0, help="size of the achievable-bandwidth copy (0: skip)")
@@ -445,8 +480,13 @@ def main():
         "dtype": "f64" if head_name == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "production jet 2048x512 (x-stretch 1.002, r-clustered), SSP-RK3 CFL 0.5, "
-                               "path=%s" % head_name,
-                   "nx": 2048, "nr": 512, "cells": head["cells"]},
+                               "path=%s, phase-change source %s" % (
+                                   head_name, "active in %d cells" % head["active_cells"] if head["active_cells"]
+                                   else "inactive (subsaturated everywhere)"),
+                   "nx": 2048, "nr": 512, "cells": head["cells"],
+                   # the source-active twin on the same mesh is reported beside it
+                   "source_activity": {"active_cells": head["active_cells"], "max_lnS_l": head["max_lnS_l"],
+                                       "network_cell_stages": head.get("network_cell_stages", 0)}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_stage (%s, tile %dx%d)" % ("f32" if head["esz"] == 4 else "f64", *head["tile"]),
@@ -467,6 +507,12 @@ def main():
         line["source_active_2048x512"] = active
     if mlp is not None:
         line["surrogate_inference"] = mlp
+    if active is not None and mlp is not None and "exact_source_cost" in active:
+        # the exact source per active cell (one call over the source-active jet) against
+        # one network row: what the learned source would save per cell it takes over
+        ex = active["exact_source_cost"]["ns_per_active_cell"]
+        line["source_cost_per_cell"] = {"exact_ns_per_active_cell": ex, "network_ns_per_row": mlp["ns_per_row"],
+                                        "exact_over_network": ex / mlp["ns_per_row"]}
     if a.hbm_copy_gib > 0:
         log("bench: %.1f GiB device copy (achievable HBM bandwidth)" % a.hbm_copy_gib)
         line["hbm_copy"] = copy_bandwidth(a.hbm_copy_gib)
