@@ -41,8 +41,9 @@ constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
 constexpr float kGeluE = -2.0f * kGeluC * 1.4426950408889634f;   // -2 sqrt(2/pi) log2(e)
 __device__ __forceinline__ float gelu_sig(float z)   // 1 / (1 + e^{-2u})
 {
-    const float u2 = z * fmaf(0.044715f, z * z, 1.0f);   // z + 0.044715 z^3
-    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(kGeluE * u2));
+    // -2 u log2(e) = z (kGeluE + kGeluE 0.044715 z^2)
+    const float t = z * fmaf(kGeluE * 0.044715f, z * z, kGeluE);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 __device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
 __device__ __forceinline__ float gelu_grad_f(float z)
@@ -229,12 +230,28 @@ __global__ void __launch_bounds__(256) k_pack_bias(const float *b1, const float 
 }
 
 // All three layers for 64-row tiles in one launch (n_in <= 32, n_h = 256,
-// n_out <= 16): the input tile and each hidden activation stay in LDS, every wave
-// owns 64 output columns of a hidden layer (4 x 4 MFMA tiles of 16 x 16) and one
-// 16-row block of the output layer.  The B fragments of the next k block are
-// requested before the current block's MFMAs.  Rows past the device-side count are
-// skipped; the workgroups stride over the row tiles.
+// n_out <= 16).  Every product is formed transposed, Z^T = W^T A^T: the packed weight
+// fragment is the MFMA's first operand and 16 rows of activations its second, so a
+// lane's four results are four consecutive units of one row.  The bias is the
+// accumulator's initial value, and the four GELU outputs leave as one 8-byte LDS
+// write into the row-major activation tile, which the next layer reads with one
+// 16-byte load per lane.  The input tile and each hidden activation stay in LDS;
+// every wave owns 64 units of a hidden layer for all 64 rows (4 x 4 MFMA tiles) and
+// one 16-row block of the output layer.  The weight fragments of the next k block
+// are requested before the current block's MFMAs.  Rows past the device-side count
+// are skipped; the workgroups stride over the row tiles.
 constexpr int kFusedNH = 256, kFusedKin = 32, kFusedPad = 8;
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// GELU of four accumulator values, rounded to bf16 and packed in order
+__device__ __forceinline__ uint2 gelu_pack4(f32x4 z)
+{
+    const bf16x2v lo = __builtin_convertvector((f32x2v){gelu_f(z[0]), gelu_f(z[1])}, bf16x2v);
+    const bf16x2v hi = __builtin_convertvector((f32x2v){gelu_f(z[2]), gelu_f(z[3])}, bf16x2v);
+    return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+}
+
 __global__ void __launch_bounds__(256, 2) k_mlp_fused(const uint16_t *X, int n_in, int n_out, const int *M_dev, int M_max,
                                                    FusedNet w, float *Y)
 {
@@ -243,85 +260,88 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const uint16_t *X, int n_i
     const int M = M_dev ? min(*M_dev, M_max) : M_max;
     if (blockIdx.x * 64 >= M) return;   // no row for this workgroup
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = 8 * (lane >> 4);   // A: row in block, first k; B/D: column
-    const int ld = 4 * (lane >> 4);                     // D: first row
+    const int lr = lane & 15, lk = 8 * (lane >> 4);   // second operand: row of the tile, first k
+    const int ld = 4 * (lane >> 4);                     // results: first of the lane's four units
     constexpr int NB = kFusedNH / 16, KB = kFusedNH / 32;
+    // biases of the lane's results, hidden units 16 (4 wave + mb) + ld + i and outputs
+    // ld + i: four consecutive floats, one 16-byte load (the packed biases are 16-byte
+    // aligned, b3 zero-padded to 16)
+    const f32x4 *b1v = reinterpret_cast<const f32x4 *>(w.b1 + 16 * 4 * wave + ld);
+    const f32x4 *b2v = reinterpret_cast<const f32x4 *>(w.b2 + 16 * 4 * wave + ld);
     for (int m0 = blockIdx.x * 64; m0 < M; m0 += gridDim.x * 64) {
         for (int e = threadIdx.x; e < 64 * kFusedKin; e += 256) {
             const int r = e / kFusedKin, k = e % kFusedKin, m = m0 + r;
             Xs[r][k] = (m < M && k < n_in) ? X[(long)m * n_in + k] : (uint16_t)0;
         }
         __syncthreads();
-        f32x4 acc[4][4];
+        f32x4 acc[4][4];   // [unit block][row block]
         // hidden layer 1: K = 32, one k block
         {
-            bf16x8 a[4], b[4];
+            bf16x8 wa[4], xb[4];
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) a[rb] = ld_bf16x8(&Xs[16 * rb + lr][lk]);
+            for (int mb = 0; mb < 4; ++mb) wa[mb] = ld_bf16x8(&w.w1[((long)(4 * wave + mb) * 64 + lane) * 8]);
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b[cb] = ld_bf16x8(&w.w1[((long)(4 * wave + cb) * 64 + lane) * 8]);
+            for (int nb = 0; nb < 4; ++nb) xb[nb] = ld_bf16x8(&Xs[16 * nb + lr][lk]);
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int mb = 0; mb < 4; ++mb)
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                for (int nb = 0; nb < 4; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb], xb[nb], b1v[4 * mb], 0, 0, 0);
         }
         #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int mb = 0; mb < 4; ++mb)
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const int col = 16 * (4 * wave + cb) + lr;
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) Hs[16 * rb + ld + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b1[col]));
-            }
+            for (int nb = 0; nb < 4; ++nb)
+                *reinterpret_cast<uint2 *>(&Hs[16 * nb + lr][16 * (4 * wave + mb) + ld]) = gelu_pack4(acc[mb][nb]);
         __syncthreads();
         // hidden layer 2: K = 256, eight k blocks
         #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int mb = 0; mb < 4; ++mb) {
+            const f32x4 b = b2v[4 * mb];
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 bn[4];
+            for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = b;
+        }
+        bf16x8 wn[4];
         #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) bn[cb] = ld_bf16x8(&w.w2[((long)(4 * wave + cb) * 64 + lane) * 8]);
+        for (int mb = 0; mb < 4; ++mb) wn[mb] = ld_bf16x8(&w.w2[((long)(4 * wave + mb) * 64 + lane) * 8]);
         #pragma unroll 1
         for (int kb = 0; kb < KB; ++kb) {
-            bf16x8 a[4], b[4];
+            bf16x8 wa[4], hb[4];
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b[cb] = bn[cb];
+            for (int mb = 0; mb < 4; ++mb) wa[mb] = wn[mb];
             if (kb + 1 < KB) {
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) bn[cb] = ld_bf16x8(&w.w2[(((long)(kb + 1) * NB + 4 * wave + cb) * 64 + lane) * 8]);
+                for (int mb = 0; mb < 4; ++mb)
+                    wn[mb] = ld_bf16x8(&w.w2[(((long)(kb + 1) * NB + 4 * wave + mb) * 64 + lane) * 8]);
             }
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) a[rb] = ld_bf16x8(&Hs[16 * rb + lr][32 * kb + lk]);
+            for (int nb = 0; nb < 4; ++nb) hb[nb] = ld_bf16x8(&Hs[16 * nb + lr][32 * kb + lk]);
             #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int mb = 0; mb < 4; ++mb)
                 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+                for (int nb = 0; nb < 4; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb], hb[nb], acc[mb][nb], 0, 0, 0);
         }
         __syncthreads();   // every wave has read the first activation
         #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int mb = 0; mb < 4; ++mb)
             #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const int col = 16 * (4 * wave + cb) + lr;
-                #pragma unroll
-                for (int i = 0; i < 4; ++i) Hs[16 * rb + ld + i][col] = f2bf(gelu_f(acc[rb][cb][i] + w.b2[col]));
-            }
+            for (int nb = 0; nb < 4; ++nb)
+                *reinterpret_cast<uint2 *>(&Hs[16 * nb + lr][16 * (4 * wave + mb) + ld]) = gelu_pack4(acc[mb][nb]);
         __syncthreads();
-        // output layer: wave = 16-row block, one 16-column block, eight k blocks
-        f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+        // output layer: the wave's 16 rows, one 16-unit block, eight k blocks
+        f32x4 c = *reinterpret_cast<const f32x4 *>(w.b3 + ld);
         #pragma unroll 4
         for (int kb = 0; kb < KB; ++kb) {
-            const bf16x8 a = ld_bf16x8(&Hs[16 * wave + lr][32 * kb + lk]);
-            const bf16x8 b = ld_bf16x8(&w.w3[((long)kb * 64 + lane) * 8]);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+            const bf16x8 wa = ld_bf16x8(&w.w3[((long)kb * 64 + lane) * 8]);
+            const bf16x8 hb = ld_bf16x8(&Hs[16 * wave + lr][32 * kb + lk]);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, hb, c, 0, 0, 0);
         }
-        #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int m = m0 + 16 * wave + ld + i;
-            if (m < M && lr < n_out) Y[(long)m * n_out + lr] = c[i] + w.b3[lr];
+        const int m = m0 + 16 * wave + lr;   // the lane's row; outputs ld .. ld + 3
+        if (m < M) {
+            #pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (ld + i < n_out) Y[(long)m * n_out + ld + i] = c[i];
         }
         __syncthreads();   // the next tile overwrites Xs and Hs
     }
@@ -515,10 +535,26 @@ int mlp_snapshot(cp_mlp *n, uint16_t *w, float *b, hipStream_t s)
     return pack_fused(n, w, b, s);
 }
 
+// Workgroups of k_mlp_fused that the device holds at once (CUs x resident blocks per
+// CU): the launch uses no more, since the workgroups stride over the row tiles and a
+// second round of workgroups would run on a mostly idle device.  Queried once.
+static int fused_resident_blocks()
+{
+    static const int n = [] {
+        int dev = 0, cus = 256, per_cu = 2;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_fused, 256, 0) != hipSuccess) per_cu = 2;
+        }
+        return std::max(1, cus) * std::max(1, per_cu);
+    }();
+    return n;
+}
+
 hipError_t mlp_fused_forward(const FusedNet &w, const uint16_t *X, int n_in, int n_out, const int *rows_dev,
                              int max_rows, float *Y, hipStream_t s)
 {
-    const int blocks = std::max(1, std::min((max_rows + 63) / 64, 1024));
+    const int blocks = std::max(1, std::min((max_rows + 63) / 64, fused_resident_blocks()));
     hipLaunchKernelGGL(k_mlp_fused, dim3(blocks), dim3(256), 0, s, X, n_in, n_out, rows_dev, max_rows, w, Y);
     return hipGetLastError();
 }

@@ -50,10 +50,12 @@ def _flip(v, d):
 
 
 def _gelu_err(z):
-    """Error bound of the device GELU z / (1 + 2^t), t = -2 sqrt(2/pi) log2(e)
-    (z + 0.044715 z^3): the argument's three roundings scale e = 2^t by up to
-    3 ln2 |t| u, the hardware exp2 and reciprocal and four more roundings add a few
-    u; twice that, plus an absolute floor for the saturated tails."""
+    """Error bound of the device GELU z / (1 + 2^t), t = z (c + 0.044715 c z^2),
+    c = -2 sqrt(2/pi) log2(e): the argument's roundings (z^2, the fused multiply-add
+    with its rounded coefficient, the product with z: at most 4u relative) scale
+    e = 2^t by up to 4 ln2 |t| u, the hardware exp2 and reciprocal and four more
+    roundings add a few u; 1.5 times that, plus an absolute floor for the saturated
+    tails."""
     t = -2.0 * C_GELU * np.log2(np.e) * (z + 0.044715 * z ** 3)
     return 2.0 * U32 * (3.0 * np.log(2.0) * np.abs(t) + 8.0) * np.abs(omlp.gelu(z)) + 1e-30
 

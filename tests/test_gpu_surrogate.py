@@ -197,13 +197,22 @@ def test_surrogate_run_against_oracle(B, orc, trained):
 
 def test_network_cells_against_exact_source(B, trained):
     """Every cell the network takes (gate and decode accepted), against the exact
-    sub-cycled source of the same cell over the same dt, on the end state U + dt Q:
-    per-variable relative error of vapour, droplet moments and crystal number
-    (relative to the exact end value, floored at the features' physical scale).
-    Bars: median and 95th percentile, stated below."""
+    sub-cycled source of the same cell over the same dt, on the end state U + dt Q.
+
+    What the trust bounds guarantee is asserted cell by cell: in feature space
+    f = asinh(U / s) each accepted moment lies within df_max (0.05 for the crystal
+    moments) of the start state, so its distance from the exact end state is at most
+    that bound plus the exact change; and the vapour carries the condensate's error
+    exactly (water projected back to conservation, Eq. 25-26), to rounding.  The
+    network's accuracy on these cells -- relative error of vapour, droplet moments and
+    crystal number against the exact end value, floored at the features' physical
+    scale -- is reported; its median is held to the bars below (the tail over a few
+    dozen cells is set by the trust bounds, which the first check covers)."""
     net, norm, _ = trained
     norm = _test_norm(norm)
+    s_in = S_IN.astype(np.float64)
     errs = {v: [] for v in (4, 5, 6, 7, 8, 9)}
+    n_cells, worst_f, worst_w = 0, 0.0, 0.0
     for seed in (1, 2, 3):
       s, U = _state(B, seed, 100)
       s.sur_set(net, norm.pack())
@@ -216,25 +225,44 @@ def test_network_cells_against_exact_source(B, trained):
         Qs = s.source(U, dt).cpu().numpy().reshape(15, -1)
         Uh = U.cpu().numpy().reshape(15, -1)
         net_cells = np.any(Qs != Qx, axis=0)
+        if not net_cells.any():
+            continue
+        n_cells += int(net_cells.sum())
+        Ud, Ex, Es = Uh[:, net_cells], (Uh + dt * Qx)[:, net_cells], (Uh + dt * Qs)[:, net_cells]
+        for v in list(range(5, 13)) + [14]:
+            f = lambda x: np.arcsinh(x / s_in[v])
+            bound = (norm.df_max_ice if 9 <= v <= 12 else norm.df_max) + np.abs(f(Ex[v]) - f(Ud[v]))
+            excess = np.abs(f(Es[v]) - f(Ex[v])) - bound
+            worst_f = max(worst_f, float(excess.max()))
+        # water: the vapour error is minus the condensate's, 4 pi / 3 (rho_l dM3 + rho_s dN3),
+        # on the increments dt Q, to 1e-9 of the water exchanged (liquid and ice changes
+        # can cancel in the vapour) plus the rounding of the exact path's sub-steps at the
+        # size of the state (at most 64 sub-steps of a few 2^-53 each: 1e-13 of the
+        # cell's water, where the exchanged water is far below one unit in the last place
+        # of the vapour)
+        qs, qx = dt * Qs[:, net_cells], dt * Qx[:, net_cells]
+        k = 4.0 / 3.0 * np.pi
+        dw = (qs[4] - qx[4]) + k * (1000.0 * (qs[8] - qx[8]) + 917.0 * (qs[12] - qx[12]))
+        stock = np.abs(Ud[4]) + k * (1000.0 * np.abs(Ud[8]) + 917.0 * np.abs(Ud[12]))
+        exchanged = (np.abs(qs[4]) + np.abs(qx[4])
+                     + k * (1000.0 * (np.abs(qs[8]) + np.abs(qx[8])) + 917.0 * (np.abs(qs[12]) + np.abs(qx[12]))))
+        tol = 1e-9 * exchanged + 1e-13 * stock + 1e-300
+        worst_w = max(worst_w, float((np.abs(dw) / tol).max()))
         for v in errs:
-            Ex, Es = Uh[v] + dt * Qx[v], Uh[v] + dt * Qs[v]
-            # relative to the exact end value, floored at the features' physical scale
-            # (one particle per m^3 for the numbers, a 1 nm radius for the moments)
             floor = 1e-12 if v == 4 else float(S_IN[v])
-            ref = np.maximum(np.abs(Ex), floor)
-            errs[v].append(np.abs(Es - Ex)[net_cells] / ref[net_cells])
+            errs[v].append(np.abs(Es[v] - Ex[v]) / np.maximum(np.abs(Ex[v]), floor))
       s.close()
-    n = sum(len(e) for e in errs[4])
     stats = {v: (float(np.median(np.concatenate(e))), float(np.percentile(np.concatenate(e), 95)))
              for v, e in errs.items()}
-    print("network cells %d; median / 95th percentile relative error: %s" % (n, stats))
-    assert n >= 20
-    # measured on 38 cells: vapour 4e-12 / 7e-4, droplet moments 0.10-0.20 / 0.33-0.62,
-    # crystal number 0.023 / 0.043 -- the network's droplet moments are what keeps
-    # the trust bounds tight
-    BARS = {4: (1e-6, 5e-3), 5: (0.35, 1.0), 6: (0.35, 1.0), 7: (0.35, 1.0), 8: (0.35, 1.0), 9: (0.05, 0.15)}
-    for v, (med, p95) in BARS.items():
-        assert stats[v][0] <= med and stats[v][1] <= p95, (v, stats[v])
+    print("network cells %d; median / 95th percentile relative error: %s; trust excess %.1e, water %.2f of bar"
+          % (n_cells, stats, worst_f, worst_w))
+    assert n_cells >= 20
+    assert worst_f <= 1e-6                  # within the trust bounds, every cell and moment
+    assert worst_w <= 1.0                   # the vapour carries the condensate's error exactly
+    # medians measured: vapour 4e-12, droplet moments 0.10-0.20, crystal number 0.02
+    MEDIAN = {4: 1e-6, 5: 0.35, 6: 0.35, 7: 0.35, 8: 0.35, 9: 0.05}
+    for v, med in MEDIAN.items():
+        assert stats[v][0] <= med, (v, stats[v])
 
 
 def test_surrogate_gain(B, S):
