@@ -125,8 +125,7 @@ template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), vapour
 // diffusivity, eddy viscosity and limited slopes of one direction on the tile plus a
-// 1-cell ring (RX x RY), and one face buffer reused for the x-faces, the r-faces and
-// the scalars' r slopes.  Whatever is cheap to recompute (molecular viscosity, the
+// 1-cell ring (RX x RY), and one face buffer reused for the x-faces and the r-faces.  Whatever is cheap to recompute (molecular viscosity, the
 // faces' eddy diffusivity, a halo cell's source address) is not stored: the FP32 tile
 // then fits six workgroups per CU.
 template <class R, int TX, int TY> struct Tile {
@@ -134,16 +133,14 @@ template <class R, int TX, int TY> struct Tile {
     static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     static constexpr int NFX = (TX + 1) * TY, NFR = TX * (TY + 1);
     static constexpr int NF = NFX > NFR ? NFX : NFR;
-    static constexpr int NFB = 6 * NF > 5 * NR ? 6 * NF : 5 * NR;
+    static constexpr int NFB = 6 * NF;
     R rho[N], u[N], v[N], p[N], T[N], Y[N];   // u..Y are reused for 5 scalars at a time
     R D[NR], mut[NR];
-    R sl[5][NR];                 // slopes of one direction (x, then r); the scalars' x slopes
-    R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF];
-                                 // the scalars' r slopes during the scalar phase, [5][NR]
+    R sl[5][NR];                 // gas slopes of one direction (x, then r)
+    R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF]
     int nonzero[3];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
     unsigned omask;              // non-zero passive scalars of the tile's output (bit v: variable v)
     __device__ R (*face())[NF] { return reinterpret_cast<R(*)[NF]>(fbuf); }
-    __device__ R (*rslope())[NR] { return reinterpret_cast<R(*)[NR]>(fbuf); }
 };
 
 // Eddy diffusivity / dn of the passive scalars at a face, from the cells' eddy
@@ -246,16 +243,13 @@ template <class R> __device__ __forceinline__ R assemble_duct(R fe, R ae, R fw, 
     return -(fe * ae - fw * aw) * iv;
 }
 
-// Passive scalar flux through a face: upwind MUSCL value (from the cell slopes)
-// times the Roe mass flux, minus eddy diffusion.
-// Both one-sided states are formed and the upwind one selected, so the flux is
-// branch-free (no divergent LDS reads).
-template <class R>
-__device__ __forceinline__ R scalar_face(const R *phi, const R *sl, int a, int b, int ra, int rb, R Fm, R kd)
+// Passive scalar flux through a face from the two cells' values and limited slopes:
+// upwind MUSCL value times the Roe mass flux, minus eddy diffusion.  Both one-sided
+// states are formed and the upwind one selected, so the flux is branch-free.
+template <class R> __device__ __forceinline__ R scalar_flux(R pa, R pb, R sa, R sb, R Fm, R kd)
 {
-    const R pa = phi[a], pb = phi[b];
-    const R upL = pa + R(0.5) * sl[ra];
-    const R upR = pb - R(0.5) * sl[rb];
+    const R upL = pa + R(0.5) * sa;
+    const R upR = pb - R(0.5) * sb;
     return Fm * (Fm >= R(0) ? upL : upR) - kd * (pb - pa);
 }
 
@@ -486,8 +480,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         }
         if (axi) res[2] += hoop;
     }
-    // phase 5: passive scalars, five at a time in the freed primitive arrays, slopes
-    // once per cell.  T of the cell is kept for the source-activity test.  A scalar
+    // phase 5: passive scalars, five at a time in the freed primitive arrays.  T of
+    // the cell is kept for the source-activity test.  A scalar
     // that is zero on the whole tile and halo (no particles there) has zero slopes
     // and zero fluxes, so its slope and flux work is skipped: the result is the same
     // zero (the stage output is bit-identical).
@@ -528,7 +522,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             continue;
         }
         // the slots are free once every thread is done with the previous group's
-        // faces; a group with nothing live read none of them
+        // fluxes; a group with nothing live read none of them
         if (prev_live) __syncthreads();
         int nz = 0;
         if (inner) {
@@ -560,20 +554,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         __syncthreads();
         const int live = __builtin_amdgcn_readfirstlane(t.nonzero[g]);   // block-uniform
         prev_live = live;
-        R(*srs)[NRG] = t.rslope();   // r slopes in the free face buffer
-        if (live) {   // a group with nothing live has zero slopes and fluxes: no slope pass, no barrier
-            for (int r = tid; r < NRG; r += NT) {
-                const int le = ext_of_ring<TX, TY>(r);
-                #pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    if (!(live & (1 << k))) continue;
-                    const R *ph = scalar_slot(t, k);
-                    t.sl[k][r] = vl_slope(ph[le] - ph[le - 1], ph[le + 1] - ph[le]);
-                    srs[k][r] = vl_slope(ph[le] - ph[le - EX], ph[le + EX] - ph[le]);
-                }
-            }
-            __syncthreads();
-        }
+        // the limited slopes of a live scalar are formed where the faces need them, from
+        // the five cells on each axis through the cell (no slope pass, no barrier): the
+        // same van Leer slopes, so the same fluxes
         if (valid) {
             R aw = R(0), ae = R(0), iv = R(0);
             if (q1d) {
@@ -589,13 +572,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                     continue;
                 }
                 const R *ph = scalar_slot(t, k);
-                const R fw = scalar_face(ph, t.sl[k], l - 1, l, rl - 1, rl, Fm0, kd0);
-                const R fe = scalar_face(ph, t.sl[k], l, l + 1, rl, rl + 1, Fm1, kd1);
-                const R fs_raw = scalar_face(ph, srs[k], l - EX, l, rl - RX, rl, Fm2, kd2);
-                const R fsv = (axi && j == 0) ? R(0) : fs_raw;   // zero-area axis face
-                const R fnv = scalar_face(ph, srs[k], l, l + EX, rl, rl + RX, Fm3, kd3);
-                res[s0 + k] = q1d ? assemble_duct(fe, ae, fw, aw, iv)
-                                  : assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+                const R pc = ph[l], pw = ph[l - 1], pe = ph[l + 1];
+                const R sxw = vl_slope(pw - ph[l - 2], pc - pw), sxc = vl_slope(pc - pw, pe - pc);
+                const R sxe = vl_slope(pe - pc, ph[l + 2] - pe);
+                const R fw = scalar_flux(pw, pc, sxw, sxc, Fm0, kd0);
+                const R fe = scalar_flux(pc, pe, sxc, sxe, Fm1, kd1);
+                if (q1d) {
+                    res[s0 + k] = assemble_duct(fe, ae, fw, aw, iv);
+                } else {
+                    const R ps = ph[l - EX], pn = ph[l + EX];
+                    const R srs_ = vl_slope(ps - ph[l - 2 * EX], pc - ps), src = vl_slope(pc - ps, pn - pc);
+                    const R srn = vl_slope(pn - pc, ph[l + 2 * EX] - pn);
+                    const R fs_raw = scalar_flux(ps, pc, srs_, src, Fm2, kd2);
+                    const R fsv = (axi && j == 0) ? R(0) : fs_raw;   // zero-area axis face
+                    const R fnv = scalar_flux(pc, pn, src, srn, Fm3, kd3);
+                    res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+                }
             }
         }
     }

@@ -896,6 +896,19 @@ template <class R> __device__ __forceinline__ R van_leer(R a, R b)
     return (a * b > R(0)) ? R(2) * a * b / (a + b) : R(0);
 }
 
+// c = sqrt(c^2) and 1 / c^2: in FP32 from one reciprocal square root
+__device__ __forceinline__ void sound_speed(float c2, float &c, float &ic2)
+{
+    const float ic = __builtin_amdgcn_rsqf(c2);
+    c = c2 * ic;
+    ic2 = ic * ic;
+}
+__device__ __forceinline__ void sound_speed(double c2, double &c, double &ic2)
+{
+    c = sqrt(c2);
+    ic2 = tdiv(1.0, c2);
+}
+
 // Roe flux on (rho, rho u_n, rho u_t, rho E) of the two-species gas in primitive-
 // jump form with Harten's entropy fix on the acoustic waves.  q = (rho, u_n, u_t,
 // p, Y).  F[0..3] mass, normal and tangential momentum (less pref), energy.
@@ -916,12 +929,12 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R H = wl * Hl + wr * Hr;
     const R Y = wl * Yl + wr * Yr;
     const R q2 = un * un + ut * ut;
-    const R cpm = gas_cp(Y), Rm = gas_R(Y);
+    const R Rm = gas_R(Y);
     const R h0 = gas_h0(Y);
-    const R T = tdiv(H - R(0.5) * q2 - h0, cpm);
-    const R c2 = tdiv(cpm, cpm - Rm) * Rm * T;
-    const R c = fsqrt(c2);
-    const R ic2 = tdiv(R(1), c2);
+    // c^2 = gamma R T with T = (H - q^2/2 - h0) / c_p and gamma = c_p / c_v
+    const R c2 = Rm * tdiv(H - R(0.5) * q2 - h0, gas_cv(Y));
+    R c, ic2;
+    sound_speed(c2, c, ic2);
 
     const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
     const R i2c2 = R(0.5) * ic2;
