@@ -1147,10 +1147,9 @@ template <class R> int batch_upload_args(cp_batch *b, void *const *U)
         const void *in[3] = {U[p], c->Ua, c->Ub};
         void *out[3] = {c->Ua, c->Ub, U[p]};
         for (int s = 0; s < 3; ++s) {
+            // each plume keeps its own tile masks of U, Ua, Ub (seeded by cp_batch_step_n)
             sa[s].push_back(stage_args<R>(c, in[s], U[p], out[s], s, 0.0, b->dt + p));
             fa[s].push_back(fix_args<R>(c, in[s], out[s], s, 0.0, b->dt + p));
-            sa[s].back().mask = TileMask{};   // the batch runs without tile masks
-            fa[s].back().mask = TileMask{};
         }
         CflArgs<R> &a = ca[p];
         a.U = (const R *)U[p];
@@ -1381,6 +1380,12 @@ int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host)
         b->graph_U.assign(U, U + b->n);
     }
     if (hipMemsetAsync(b->t, 0, b->n * sizeof(double), b->stream) != hipSuccess) return bfail(b, CP_EHIP, "memset");
+    // the plumes' states may have changed since the last call: their tile masks first
+    // (the replays keep them current)
+    for (int p = 0; p < b->n && nsteps > 0; ++p) {
+        int r = mask_seed(b->plumes[p], U[p], b->stream);
+        if (r) return bfail(b, r, "plume " + std::to_string(p) + ": " + b->plumes[p]->err);
+    }
     for (int k = 0; k < nsteps; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return bfail(b, CP_EHIP, "graph launch");
     std::vector<double> t(b->n);
