@@ -1109,6 +1109,7 @@ struct cp_batch {
     int tx = 32, ty = 8;
     bool tuned = false;        // tile shape picked by the autotuner
     long max_cells = 0;
+    int max_cfl_tiles = 0;     // CFL tiles of the largest plume
     int nwork = 0, cap_work = 0;
     int *work_plume = nullptr, *work_tile = nullptr;
     void *stage_args[3] = {}, *fix_args[3] = {}, *cfl_args = nullptr;
@@ -1257,7 +1258,7 @@ template <class R> int batch_autotune(cp_batch *b, void *const *U)
 
 template <class R> int batch_enqueue_step(cp_batch *b, hipStream_t s)
 {
-    hipError_t e = launch_cfl_batch<R>((const CflArgs<R> *)b->cfl_args, b->n, b->max_cells, s);
+    hipError_t e = launch_cfl_batch<R>((const CflArgs<R> *)b->cfl_args, b->n, b->max_cfl_tiles, s);
     if (e == hipSuccess) e = launch_cfl_finalize_batch(b->acc, b->cfl, b->dt, b->t, b->n, s);
     for (int st = 0; st < 3 && e == hipSuccess; ++st) {
         e = launch_stage_batch<R>((const StageArgs<R> *)b->stage_args[st], b->work_plume, b->work_tile, b->nwork,
@@ -1294,6 +1295,7 @@ int cp_batch_create(int n, const cp_mesh *meshes, const cp_case *cases, int prec
         c->ty = b->ty;
         b->plumes.push_back(c);
         b->max_cells = std::max(b->max_cells, c->plane);
+        b->max_cfl_tiles = std::max(b->max_cfl_tiles, cfl_batch_tiles(c->nx, c->nr));
     }
     // work arrays large enough for the smallest built tile (16 x 4 cells)
     for (int p = 0; p < n; ++p) b->cap_work += ((b->plumes[p]->nx + 15) / 16) * ((b->plumes[p]->nr + 3) / 4);

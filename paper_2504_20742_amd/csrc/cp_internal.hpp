@@ -154,7 +154,8 @@ hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int
                               hipStream_t s);
 template <class R>
 hipError_t launch_source_fix_batch(const SourceFixArgs<R> *args, int nplumes, long max_cells, hipStream_t s);
-template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, long max_cells, hipStream_t s);
+template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, int max_tiles, hipStream_t s);
+int cfl_batch_tiles(int nx, int nr);   // CFL tiles of one plume's mesh
 hipError_t launch_cfl_finalize_batch(unsigned long long *acc, const double *cfl, double *dt, double *t, int n,
                                      hipStream_t s);
 hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s);

@@ -859,9 +859,16 @@ template <class R> __global__ void __launch_bounds__(256) k_drift(DriftArgs<R> a
 }
 
 // batched: blockIdx.y selects the plume
-template <class R> __global__ void __launch_bounds__(256) k_source_fix_batch(const SourceFixArgs<R> *args)
+// batched: blockIdx.y selects the plume; one wavefront per workgroup, and a
+// workgroup past the plume's listed cells leaves at once (as in k_source_fix)
+template <class R> __global__ void __launch_bounds__(64) k_source_fix_batch(const SourceFixArgs<R> *args)
 {
-    source_fix_body(args[blockIdx.y], blockIdx.x, gridDim.x);
+    const SourceFixArgs<R> &a = args[blockIdx.y];
+    if ((long)blockIdx.x * blockDim.x >= min((long)*a.count, a.plane)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && a.next_count) *a.next_count = 0;
+        return;
+    }
+    source_fix_body(a, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ surrogate
@@ -1285,12 +1292,13 @@ __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, i
 // BX x BY threads over a BX x (BY * RPT) tile (RPT rows per thread).  A tile whose
 // 1-cell ring lies inside the mesh loads its cells directly, all five variables at
 // once; boundary tiles go through the ghost-cell mapping.
-template <int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile_f32(CflArgs<float> a)
+template <int BX, int BY, int RPT> __device__ __forceinline__ void cfl_tile_f32_body(const CflArgs<float> &a, int bxi,
+                                                                                     int byi)
 {
     constexpr int TY = BY * RPT, EXC = BX + 2, NEC = EXC * (TY + 2);
     __shared__ float pr[5][NEC];
     const BcInfo &bc = a.bc;
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * TY;
+    const int i0 = bxi * BX, j0 = byi * TY;
     const bool inner = i0 >= 1 && j0 >= 1 && i0 + BX + 1 <= bc.nx && j0 + TY + 1 <= bc.nr;
     if (inner) {
         // every load of the thread's ring cells in flight before the first use
@@ -1346,40 +1354,22 @@ template <int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_c
     cfl_block_min(best, a.acc, a.block_min);
 }
 
-template <class R> __device__ __forceinline__ void cfl_body(const CflArgs<R> &a, int bx, int nbx)
+template <int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile_f32(CflArgs<float> a)
 {
-    const BcInfo &bc = a.bc;
-    const int n = bc.nx * bc.nr;
-    double best = __builtin_huge_val();
-    for (int c = bx * blockDim.x + threadIdx.x; c < n; c += nbx * blockDim.x) {
-        const int i = c % bc.nx, j = c / bc.nx;
-        double d;
-        if constexpr (sizeof(R) == 4) {   // same arithmetic as k_cfl_tile_f32
-            const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
-            const float uN = cfl_prim_f32(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim_f32(a.U, a.plane, bc, i, j - 1).u;
-            const float vE = cfl_prim_f32(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim_f32(a.U, a.plane, bc, i - 1, j).v;
-            d = (double)cfl_limit_f32(a, i, j, w, uN, uS, vE, vW);
-        } else {
-            const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
-            const double uN = cfl_prim(a.U, a.plane, bc, i, j + 1).u, uS = cfl_prim(a.U, a.plane, bc, i, j - 1).u;
-            const double vE = cfl_prim(a.U, a.plane, bc, i + 1, j).v, vW = cfl_prim(a.U, a.plane, bc, i - 1, j).v;
-            d = cfl_limit(a, i, j, w, uN, uS, vE, vW);
-        }
-        if (d < best) best = d;
-    }
-    cfl_block_min(best, a.acc, nullptr);
+    cfl_tile_f32_body<BX, BY, RPT>(a, blockIdx.x, blockIdx.y);
 }
 
 // Tiled form: the primitives of a BX x (BY * RPT) tile and its 1-cell ring are
-// computed once into LDS and shared by the neighbouring cells' limits (same
-// arithmetic as cfl_body, so the minimum is bit-identical); interior tiles load
-// their cells directly.
-template <class R, int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile(CflArgs<R> a)
+// computed once into LDS and shared by the neighbouring cells' limits (the same
+// arithmetic for interior and boundary tiles, so the minimum does not depend on how
+// the mesh is cut into tiles); interior tiles load their cells directly.
+template <class R, int BX, int BY, int RPT>
+__device__ __forceinline__ void cfl_tile_body(const CflArgs<R> &a, int bxi, int byi)
 {
     constexpr int TY = BY * RPT, EXC = BX + 2, NEC = EXC * (TY + 2);
     __shared__ double pr[5][NEC];
     const BcInfo &bc = a.bc;
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * TY;
+    const int i0 = bxi * BX, j0 = byi * TY;
     const bool inner = i0 >= 1 && j0 >= 1 && i0 + BX + 1 <= bc.nx && j0 + TY + 1 <= bc.nr;
     if (inner) {
         // every load of the thread's ring cells in flight before the first use
@@ -1435,10 +1425,24 @@ template <class R, int BX, int BY, int RPT> __global__ void __launch_bounds__(BX
     cfl_block_min(best, a.acc, a.block_min);
 }
 
-// batched: blockIdx.y selects the plume, each plume reduces into its own slot
-template <class R> __global__ void __launch_bounds__(256) k_cfl_batch(const CflArgs<R> *args)
+template <class R, int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_tile(CflArgs<R> a)
 {
-    cfl_body(args[blockIdx.y], blockIdx.x, gridDim.x);
+    cfl_tile_body<R, BX, BY, RPT>(a, blockIdx.x, blockIdx.y);
+}
+
+// batched: blockIdx.y selects the plume, blockIdx.x one of its tiles (row by row);
+// each plume reduces into its own slot
+template <class R, int BX, int BY, int RPT> __global__ void __launch_bounds__(BX *BY) k_cfl_batch(const CflArgs<R> *args)
+{
+    const CflArgs<R> &a = args[blockIdx.y];
+    constexpr int TY = BY * RPT;
+    const int gx = (a.bc.nx + BX - 1) / BX, gy = (a.bc.nr + TY - 1) / TY;
+    const int t = blockIdx.x;
+    if (t >= gx * gy) return;   // past this plume's tiles (the whole workgroup)
+    if constexpr (sizeof(R) == 4)
+        cfl_tile_f32_body<BX, BY, RPT>(a, t % gx, t / gx);
+    else
+        cfl_tile_body<R, BX, BY, RPT>(a, t % gx, t / gx);
 }
 
 __global__ void k_cfl_finalize_batch(unsigned long long *acc, const double *cfl, double *dt, double *t, int n)
@@ -1618,15 +1622,21 @@ hipError_t launch_stage_batch(const StageArgs<R> *args, const int *wp, const int
 template <class R>
 hipError_t launch_source_fix_batch(const SourceFixArgs<R> *args, int nplumes, long max_cells, hipStream_t s)
 {
-    int bx = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 256));
-    hipLaunchKernelGGL((k_source_fix_batch<R>), dim3(bx, nplumes), dim3(256), 0, s, args);
+    // up to 64 one-wavefront workgroups per plume, striding over its list
+    int bx = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, 64));
+    hipLaunchKernelGGL((k_source_fix_batch<R>), dim3(bx, nplumes), dim3(64), 0, s, args);
     return hipGetLastError();
 }
 
-template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, long max_cells, hipStream_t s)
+int cfl_batch_tiles(int nx, int nr)
 {
-    int bx = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
-    hipLaunchKernelGGL((k_cfl_batch<R>), dim3(bx, nplumes), dim3(256), 0, s, args);
+    return ((nx + kCflBX - 1) / kCflBX) * ((nr + kCflBY * kCflRows - 1) / (kCflBY * kCflRows));
+}
+
+template <class R> hipError_t launch_cfl_batch(const CflArgs<R> *args, int nplumes, int max_tiles, hipStream_t s)
+{
+    constexpr int BX = kCflBX, BY = kCflBY, RPT = kCflRows;
+    hipLaunchKernelGGL((k_cfl_batch<R, BX, BY, RPT>), dim3(std::max(1, max_tiles), nplumes), dim3(BX * BY), 0, s, args);
     return hipGetLastError();
 }
 
@@ -1790,7 +1800,7 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_stage_batch<R>(const StageArgs<R> *, const int *, const int *, int, int, int,   \
                                               hipStream_t);                                                   \
     template hipError_t launch_source_fix_batch<R>(const SourceFixArgs<R> *, int, long, hipStream_t);        \
-    template hipError_t launch_cfl_batch<R>(const CflArgs<R> *, int, long, hipStream_t);                     \
+    template hipError_t launch_cfl_batch<R>(const CflArgs<R> *, int, int, hipStream_t);                      \
     template hipError_t launch_source<R>(const R *, R *, long, long, double, const SourceParams &,           \
                                          unsigned long long *, int, hipStream_t);                             \
     template hipError_t launch_init<R>(R *, const double *, int, int, int, hipStream_t);                      \
