@@ -1207,29 +1207,34 @@ int batch_worklist(cp_batch *b, int tx, int ty)
 }
 
 // Pick the batch's tile shape: time the first stage of every plume (U -> its first
-// stage buffer, phase-change source off so that no active list is touched, dt = 0)
-// for each built shape; an earlier shape is kept unless a later one is more than 5 %
-// faster.  All shapes give identical results.
+// stage buffer, phase-change source off so that no active list is touched, dt = 0,
+// with the plumes' tile masks of that shape) for each built shape; an earlier shape
+// is kept unless a later one is more than 5 % faster.  All shapes give identical
+// results.
 template <class R> int batch_autotune(cp_batch *b, void *const *U)
 {
-    std::vector<StageArgs<R>> sa;
-    for (int p = 0; p < b->n; ++p) {
-        cp_ctx *c = b->plumes[p];
-        sa.push_back(stage_args<R>(c, U[p], U[p], c->Ua, 0, 0.0, nullptr));
-        sa.back().sp.enabled = 0;
-        sa.back().mask = TileMask{};
-        sa.back().sur_cnt = nullptr;
-    }
     StageArgs<R> *d = balloc<StageArgs<R>>(b, b->n);
     if (!d) return bfail(b, CP_ENOMEM, "autotune arguments");
-    if (hipMemcpy(d, sa.data(), b->n * sizeof(StageArgs<R>), hipMemcpyHostToDevice) != hipSuccess)
-        return bfail(b, CP_EHIP, "autotune upload");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return bfail(b, CP_EHIP, "events");
     float best = 1e30f;
     int btx = 32, bty = 8, r = CP_OK;
     for (auto &sh : tile_list()) {
         if ((r = batch_worklist(b, sh.first, sh.second))) break;
+        std::vector<StageArgs<R>> sa;
+        for (int p = 0; p < b->n && !r; ++p) {
+            cp_ctx *c = b->plumes[p];
+            if ((r = mask_seed(c, U[p], b->stream))) r = bfail(b, r, c->err);
+            sa.push_back(stage_args<R>(c, U[p], U[p], c->Ua, 0, 0.0, nullptr));
+            sa.back().sp.enabled = 0;
+            sa.back().sur_cnt = nullptr;
+        }
+        if (r) break;
+        if (hipMemcpyAsync(d, sa.data(), b->n * sizeof(StageArgs<R>), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess) {
+            r = bfail(b, CP_EHIP, "autotune upload");
+            break;
+        }
         hipError_t e = launch_stage_batch<R>(d, b->work_plume, b->work_tile, b->nwork, b->tx, b->ty, b->stream);
         if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
         for (int k = 0; k < 4 && e == hipSuccess; ++k)
