@@ -180,6 +180,27 @@ def test_koop_rate_range_and_monotone(orc):
     assert L.or_koop_delta_aw(150.0) == hi
 
 
+def test_koop_homogeneous_freezing_temperature(orc):
+    """Eq. 12 against observation, not against its own polynomial: with the oracle's
+    Delta a_w (Sonntag's ice and liquid vapour pressures) and Koop rate, a pure-water
+    droplet of 10 um freezes with probability one half within one second
+    (J V t = ln 2) at a temperature inside the observed homogeneous-freezing range
+    of cloud droplets (golden).  A wrong unit of J (cm^-3 vs m^-3) moves that
+    temperature by about 4 K, a swapped vapour-pressure ratio or a sign slip in the
+    polynomial far more."""
+    L = orc.lib()
+    g = GOLD["homogeneous_freezing_T_K"]
+    V = 4.0 / 3.0 * math.pi * g["radius_m"] ** 3
+    lo, hi = 200.0, 272.0
+    for _ in range(80):     # J rises monotonically as T falls
+        mid = 0.5 * (lo + hi)
+        if L.or_koop_rate(L.or_koop_delta_aw(mid)) * V * g["time_s"] > math.log(2.0):
+            lo = mid
+        else:
+            hi = mid
+    assert g["range"][0] < lo < g["range"][1], lo
+
+
 # ---------------------------------------------------------------- Eq. 16
 def test_young_growth_limits(orc):
     """P14 (Eq. 16): G vanishes at r_crit; sign(G) = sign(dT) for r >> r_crit;
