@@ -407,6 +407,9 @@ def main():
     ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
     ap.add_argument("--tile", default="", help="stage tile of the production-jet paths, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--hbm-copy-gib", type=float, default=1.0, help="size of the achievable-bandwidth copy (0: skip)")
+    ap.add_argument("--big-mesh-steps", type=int, default=20,
+                    help="timed steps of the mixed path on the 2048x2048 jet, whose states exceed the "
+                         "256 MB Infinity Cache (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -447,7 +450,7 @@ def main():
         log("bench: production jet, path %s, %d warmup + %d timed steps" % (p, a.warmup, a.steps))
         attach = (trained[0], trained[1].pack()) if p == "mixed_surrogate" else None
         tile = tuple(int(x) for x in a.tile.split("x")) if a.tile else None
-        res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach, tile=tile)
+        res[p] = run_path(binding, m, c, prec, a.steps, a.warmup, a.stage_reps, sur=attach, tile=tile, keep=True)
     if a.mlp_rows > 0:
         from paper_2504_20742_amd import surrogate
         if trained is None:
@@ -466,6 +469,15 @@ def main():
             part["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)
         print(json.dumps(part), flush=True)
         return
+    # accuracy of each path against the FP64 path after the same steps (same dt sequence
+    # up to the FP32 CFL limit of the mixed paths), then the states are released
+    if "fp64" in res:
+        for k in res:
+            if k != "fp64":
+                res[k]["error_vs_fp64"] = rel_errors(res[k]["U"], res["fp64"]["U"])
+    for d in res.values():
+        d.pop("U", None)
+    torch.cuda.empty_cache()
     head_name = "mixed_surrogate" if "mixed_surrogate" in res else ("mixed" if "mixed" in res else "fp64")
     head = res[head_name]
     achieved = head["stage_bytes"] / (head["stage_ms"] / 1e3) / 1e9
@@ -495,8 +507,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_stage (%s, tile %dx%d)" % ("f32" if head["esz"] == 4 else "f64", *head["tile"]),
                      "bytes_per_launch": head["stage_bytes"], "ms_per_launch": head["stage_ms"]},
-        "paths": {k: {kk: v[kk] for kk in ("cell_updates_per_s", "ms_per_step", "stage_ms", "tile",
-                                            "max_lnS_l", "active_cells") if kk in v} for k, v in res.items()},
+        "paths": {k: dict({kk: v[kk] for kk in ("cell_updates_per_s", "ms_per_step", "stage_ms", "tile",
+                                                 "max_lnS_l", "active_cells", "error_vs_fp64") if kk in v},
+                          # end to end: algorithmic bytes of a cell-update (8 array passes of the
+                          # three stages: 960 B in FP64, 480 B with FP32 storage) at the step rate
+                          end_to_end_frac=v["cell_updates_per_s"] * (960.0 if v["esz"] == 8 else 480.0)
+                          / (HBM_PEAK_GBS * 1e9))
+                  for k, v in res.items()},
     }
     valu = measured_valu(head["tile"]) if head["esz"] == 4 else None
     if valu is not None:
@@ -520,6 +537,16 @@ def main():
     if a.hbm_copy_gib > 0:
         log("bench: %.1f GiB device copy (achievable HBM bandwidth)" % a.hbm_copy_gib)
         line["hbm_copy"] = copy_bandwidth(a.hbm_copy_gib)
+    if a.big_mesh_steps > 0:
+        # the three FP32 states of 2048 x 512 (189 MB) fit in the 256 MB Infinity Cache;
+        # at 2048 x 2048 (755 MB) they do not, so its stage time is a true-HBM figure
+        log("bench: mixed path on the 2048x2048 jet, %d steps" % a.big_mesh_steps)
+        mb, cb = inputs.config2(0, 2048, 2048)
+        big = run_path(binding, mb, cb, binding.CP_MIXED, a.big_mesh_steps, 5, a.stage_reps)
+        gbs = big["stage_bytes"] / (big["stage_ms"] / 1e3) / 1e9
+        line["stage_2048x2048"] = {"cells": big["cells"], "ms_per_step": big["ms_per_step"],
+                                   "cell_updates_per_s": big["cell_updates_per_s"], "stage_ms": big["stage_ms"],
+                                   "tile": big["tile"], "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
     if a.batch_steps > 0:
         log("bench: 64-plume batch, %d steps" % a.batch_steps)
         line["batch_64_plumes"] = run_batch(binding, inputs, a.batch_steps)
