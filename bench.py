@@ -11,11 +11,15 @@ stages with the phase-change source).  Workloads, all synthetic and seeded:
   mesh, where the phase-change source is live: the same three paths, the gain of
   the surrogate (mixed exact step time / mixed surrogate step time), the share of
   active cells it takes, and the error of each path against the FP64 path;
-* 64 plumes of uneven size advanced in one captured graph (mixed precision).
+* 64 plumes of uneven size advanced in one captured graph (mixed precision, 2000 steps);
+* one GPU's share of the production jet split into 2, 4 and 8 x-slabs (mixed and FP64),
+  and the stage kernel on the 2048 x 2048 jet, whose states exceed the Infinity Cache.
 
 Timed regions: K steps of the captured step graph with inputs resident in HBM,
 bracketed by synchronisation.  The roofline entry is the fused stage kernel of the
-headline path, timed with HIP events on the stream it is launched on.
+headline path, timed with HIP events on the stream it is launched on; `traffic` and
+`valu_issue` come from the committed rocprofv3 summaries in profiles/ while they were
+taken on the kernel sources as they are.
 
 Prints ONE JSON line.
 """
@@ -407,6 +411,9 @@ def main():
     ap.add_argument("--mlp-rows", type=int, default=1 << 20, help="rows of the timed network inference (0: skip)")
     ap.add_argument("--tile", default="", help="stage tile of the production-jet paths, e.g. 32x8 (default: autotuned)")
     ap.add_argument("--hbm-copy-gib", type=float, default=1.0, help="size of the achievable-bandwidth copy (0: skip)")
+    ap.add_argument("--slab-steps", type=int, default=100,
+                    help="timed steps of the mixed and FP64 paths on one GPU's share of the production "
+                         "jet split into 2, 4 and 8 x-slabs (1024, 512, 256 x 512 cells; 0: skip)")
     ap.add_argument("--big-mesh-steps", type=int, default=20,
                     help="timed steps of the mixed path on the 2048x2048 jet, whose states exceed the "
                          "256 MB Infinity Cache (0: skip)")
@@ -537,6 +544,17 @@ def main():
     if a.hbm_copy_gib > 0:
         log("bench: %.1f GiB device copy (achievable HBM bandwidth)" % a.hbm_copy_gib)
         line["hbm_copy"] = copy_bandwidth(a.hbm_copy_gib)
+    if a.slab_steps > 0:
+        # a shard of the production jet at its real shape: n_x / k columns, all 512 rows
+        # (the same 2 m x 0.5 m jet on a mesh of that size: same cell count and shape)
+        line["slabs"] = {}
+        for nxs in (1024, 512, 256):
+            log("bench: %dx512 slab, %d steps" % (nxs, a.slab_steps))
+            ms_, cs_ = inputs.config2(0, nxs, 512)
+            line["slabs"]["%dx512" % nxs] = {
+                p: {kk: v for kk, v in run_path(binding, ms_, cs_, prec, a.slab_steps, 10).items()
+                    if kk in ("ms_per_step", "cell_updates_per_s", "tile")}
+                for p, prec in (("mixed", binding.CP_MIXED), ("fp64", binding.CP_FP64))}
     if a.big_mesh_steps > 0:
         # the three FP32 states of 2048 x 512 (189 MB) fit in the 256 MB Infinity Cache;
         # at 2048 x 2048 (755 MB) they do not, so its stage time is a true-HBM figure
