@@ -201,15 +201,16 @@ __device__ __forceinline__ double prop_tsat(const SourceParams &sp, bool ice, do
 // Young's parameter nu (Eq. 16) with gamma, c_p of the vapour and q_c.
 __device__ __forceinline__ double young_nu(double Tsat, double h)
 {
-    return kRv * Tsat / h * (kYoungA - 0.5 - (2.0 - kQc) / (2.0 * kQc) * (kGv + 1.0) / (2.0 * kGv) * kCpv * Tsat / h);
+    const double q = Tsat / h;
+    return kRv * q * (kYoungA - 0.5 - (2.0 - kQc) / (2.0 * kQc) * (kGv + 1.0) / (2.0 * kGv) * kCpv * q);
 }
 
 // Young's growth law, beta = 0 (Eq. 16): Kn = lbar / 2r.
 __device__ __forceinline__ double young_G(double lam, double drive, double r, double rho_p, double h,
                                           double nu, double lbar)
 {
-    double Kn = lbar / (2.0 * r);
-    return lam * drive / (rho_p * h * r * (1.0 + 3.78 * (1.0 - nu) * Kn / kPrV));
+    // r (1 + 3.78 (1 - nu) Kn / Pr_v) with Kn = lbar / (2 r): one division
+    return lam * drive / (rho_p * h * (r + (1.89 / kPrV) * (1.0 - nu) * lbar));
 }
 
 // A particle population (mu0 > N_MIN) is valid while r20 and r30 are at least a
@@ -226,10 +227,11 @@ struct CellThermo {      // quantities of one state that the rates need
 __device__ __forceinline__ void cell_thermo(const double *U, CellThermo &c)
 {
     c.rho = U[0];
-    c.u = U[1] / U[0];
-    c.v = U[2] / U[0];
-    double Y = U[4] / U[0];
-    double e = U[3] / U[0] - 0.5 * (c.u * c.u + c.v * c.v);
+    const double ir = 1.0 / U[0];
+    c.u = U[1] * ir;
+    c.v = U[2] * ir;
+    double Y = U[4] * ir;
+    double e = U[3] * ir - 0.5 * (c.u * c.u + c.v * c.v);
     c.T = gas_T<double>(e, Y);
     c.Rm = gas_R<double>(Y);
     c.cpm = gas_cp<double>(Y);
@@ -260,17 +262,21 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
     const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
     const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
     const double mu = sutherland<double>(T);
-    const double lam = th.cpm * mu / kPr;
+    const double lam = th.cpm * mu * (1.0 / kPr);
     const double lbar = 1.5 * mu * sqrt(th.Rm * T) / th.p;
+    // Kelvin radius 2 sigma / (rho_l R_v T ln S_l) (Eq. 3): the critical radius where
+    // S_l > 1, the curvature term of the droplets' growth drive either way
+    const double kel = fabs(lnSl) < 1e-12 ? 0.0 : 2.0 * sig / (kRhoL * kRv * T * lnSl);
 
     double Jl = 0.0, rc = 0.0;
     r.act = 0.0;
     if (lnSl > 0.0 && rv > 0.0) {
-        rc = 2.0 * sig / (kRhoL * kRv * T * lnSl);                      // Eq. 3
-        const double x = kFourThirdsPi * sig * rc * rc / (kKb * T);     // dG*/kT
+        rc = kel;                                                       // Eq. 3
+        const double iT = 1.0 / T, hT = hfg * iT;
+        const double x = (kFourThirdsPi / kKb) * sig * rc * rc * iT;    // dG*/kT
         const double K = sp.cnt_const * sqrt(sig) * rv * rv;            // Eq. 4
         const double phi = 2.0 * kQc * kGv / ((kGv + 1.0) * kCpv)
-                           * (hfg * hfg / (kRv * T * T) - hfg / T);     // Eq. 5
+                           * hT * (hT * (1.0 / kRv) - 1.0);             // Eq. 5
         const double inv1p = 1.0 / (1.0 + phi);
         Jl = K * exp(-x) * inv1p;
         if (Ns > Na) {                                                  // Eq. 10 on free soot
@@ -290,8 +296,7 @@ __device__ inline void phase_rates(const double *U, double h, const SourceParams
         double r20 = sqrt(M2 / M0);
         double Ts = prop_tsat(sp, false, lnpv, T);
         double dT = Ts - T;
-        double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
-                                          : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+        double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20) : dT * (1.0 - kel / r20);
         r.Gl = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
     }
     if (ice) {
@@ -390,19 +395,23 @@ __device__ inline void phase_rates_n(const double *U, double h, const SourcePara
     const double hfg = kLv0 + (kCpv - kCl) * (T - kTref);
     const double hsg = kLs0 + (kCpv - kCi) * (T - kTref);
     const double mu = sutherland<double>(T);
-    const double lam = th.cpm * mu / kPr;
+    const double lam = th.cpm * mu * (1.0 / kPr);
     const double lbar = 1.5 * mu * sqrt(th.Rm * T) / th.p;
+    // Kelvin radius 2 sigma / (rho_l R_v T ln S_l) (Eq. 3): the critical radius where
+    // S_l > 1, the curvature term of the droplets' growth drive either way
+    const double kel = fabs(lnSl) < 1e-12 ? 0.0 : 2.0 * sig / (kRhoL * kRv * T * lnSl);
 
     double J[NP], rc = 0.0;
     #pragma unroll
     for (int pop = 0; pop < NP; ++pop) J[pop] = 0.0;
     r.act = 0.0;
     if (lnSl > 0.0 && rv > 0.0) {
-        rc = 2.0 * sig / (kRhoL * kRv * T * lnSl);                      // Eq. 3
-        const double x = kFourThirdsPi * sig * rc * rc / (kKb * T);     // dG*/kT
+        rc = kel;                                                       // Eq. 3
+        const double iT = 1.0 / T, hT = hfg * iT;
+        const double x = (kFourThirdsPi / kKb) * sig * rc * rc * iT;    // dG*/kT
         const double K = sp.cnt_const * sqrt(sig) * rv * rv;            // Eq. 4
         const double phi = 2.0 * kQc * kGv / ((kGv + 1.0) * kCpv)
-                           * (hfg * hfg / (kRv * T * T) - hfg / T);     // Eq. 5
+                           * hT * (hT * (1.0 / kRv) - 1.0);             // Eq. 5
         const double inv1p = 1.0 / (1.0 + phi);
         const double Jhom = K * exp(-x) * inv1p;
         if (Ns > Na) {                                                  // Eq. 10 on free soot
@@ -430,8 +439,7 @@ __device__ inline void phase_rates_n(const double *U, double h, const SourcePara
             double r20 = sqrt(M[2] / M[0]);
             double Ts = prop_tsat(sp, false, lnpv, T);
             double dT = Ts - T;
-            double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20)
-                                              : dT * (1.0 - 2.0 * sig / (kRhoL * kRv * T * lnSl) / r20);
+            double drive = fabs(lnSl) < 1e-12 ? dT - 2.0 * sig * Ts / (kRhoL * hfg * r20) : dT * (1.0 - kel / r20);
             r.Gl[pop] = young_G(lam, drive, r20, kRhoL, hfg, young_nu(Ts, hfg), lbar);
         }
     }
@@ -760,8 +768,9 @@ __device__ inline int source_integrate(const double *U0, double dt, const Source
             }
         }
     }
+    const double idt = 1.0 / dt;
     #pragma unroll
-    for (int v = 0; v < NVAR; ++v) Q[v] = (U[v] - U0[v]) / dt;
+    for (int v = 0; v < NVAR; ++v) Q[v] = (U[v] - U0[v]) * idt;
     return nsub;
 }
 
@@ -875,8 +884,9 @@ __device__ inline int source_integrate_n(const double *U0, double dt, const Sour
             }
         }
     }
+    const double idt = 1.0 / dt;
     #pragma unroll
-    for (int v = 0; v < NV; ++v) Q[v] = (U[v] - U0[v]) / dt;
+    for (int v = 0; v < NV; ++v) Q[v] = (U[v] - U0[v]) * idt;
     return nsub;
 }
 
