@@ -240,6 +240,14 @@ int cp_nvar(const cp_ctx *ctx);
  * built-in autotuner on the next step.  CP_EUNSUPPORTED for shapes not built (with
  * two liquid populations only 32 x 8 is built).                                  */
 int cp_set_tile(cp_ctx *ctx, int tx, int ty);
+
+/* Per-tile masks of the non-zero passive scalars (on by default): the stage kernel
+ * loads and transports only the scalars that can be non-zero on a tile's stencil
+ * and skips the RK loads of planes that are zero on the whole tile; the results are
+ * the same bit for bit with and without them (a scalar outside a tile's mask is
+ * zero on its whole stencil).  on = 0 turns them off, for comparison.  The drift
+ * pass (cp_set_drift) runs without them.  CP_EINVAL for a null context.           */
+int cp_set_tile_masks(cp_ctx *ctx, int on);
 int cp_get_tile(const cp_ctx *ctx, int *tx, int *ty);
 
 /* Measurement entry point: launch the three SSP-RK3 stages of the fused stage kernel

@@ -69,6 +69,7 @@ _SIGS = {
     "cp_set_tile": (_I, [_P, _I, _I]),
     "cp_set_property_table": (_I, [_P, _D]),
     "cp_set_drift": (_I, [_P, _I]),
+    "cp_set_tile_masks": (_I, [_P, _I]),
     "cp_set_bimodal": (_I, [_P, _I]),
     "cp_nvar": (_I, [_P]),
     "cp_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -264,6 +265,11 @@ class Solver:
 
     def set_tile(self, tx, ty):
         self._chk(self.L.cp_set_tile(self.h, int(tx), int(ty)))
+
+    def set_tile_masks(self, on=True):
+        """Per-tile masks of the non-zero passive scalars (an optimisation with
+        identical results); off for comparison."""
+        self._chk(self.L.cp_set_tile_masks(self.h, 1 if on else 0))
 
     def set_drift(self, on=True):
         self._chk(self.L.cp_set_drift(self.h, 1 if on else 0))

@@ -47,6 +47,7 @@ struct cp_ctx {
     int *act_count = nullptr, *act_list = nullptr;  // source-active cells per stage
     unsigned *tmask[3] = {};                        // tile masks of U, Ua, Ub (non-zero scalars)
     unsigned ghost_bits = 0;                        // non-zero scalars of the inflow / far-field states
+    bool masks_off = false;                         // cp_set_tile_masks(ctx, 0)
     bool sur_ready = false;                         // a network snapshot is attached
     SurNorm nm{};
     int *sur_cnt = nullptr, *sur_cells = nullptr, *fb_list = nullptr;
@@ -319,7 +320,7 @@ BcInfo bcinfo(const cp_ctx *c)
 // Tile masks of the passive scalars: one per state buffer (the caller's U, and the
 // two stage buffers), for the current tile shape.  Off with the drift, whose pass
 // moves particles after the stage kernel without widening the masks.
-bool masks_on(const cp_ctx *c) { return !c->drift && c->tx > 0 && c->tmask[0]; }
+bool masks_on(const cp_ctx *c) { return !c->drift && !c->masks_off && c->tx > 0 && c->tmask[0]; }
 unsigned *mask_of(const cp_ctx *c, const void *p)
 {
     return p == c->Ua ? c->tmask[1] : (p == c->Ub ? c->tmask[2] : c->tmask[0]);
@@ -980,6 +981,14 @@ int cp_set_tile(cp_ctx *c, int tx, int ty)
         c->tx = tx;
         c->ty = ty;
     }
+    drop_graphs(c);
+    return CP_OK;
+}
+
+int cp_set_tile_masks(cp_ctx *c, int on)
+{
+    if (!c) return CP_EINVAL;
+    c->masks_off = on == 0;
     drop_graphs(c);
     return CP_OK;
 }
