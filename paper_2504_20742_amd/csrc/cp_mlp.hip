@@ -3,8 +3,9 @@
 //
 // Network: n_in -> n_h -> n_h -> n_out, GELU (tanh form) after both hidden layers,
 // mean-squared-error loss.  Weights and activations are bfloat16, products are
-// accumulated in FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16), master
-// weights and Adam moments are FP32.  Parameters are flat in the order
+// accumulated in FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16 in the training
+// GEMM, v_mfma_f32_16x16x32_bf16 in the fused inference), master weights and Adam
+// moments are FP32.  Parameters are flat in the order
 // W1 [n_in][n_h], b1, W2 [n_h][n_h], b2, W3 [n_h][n_out], b3.
 //
 // One strided GEMM kernel serves every product of the forward and backward pass:
