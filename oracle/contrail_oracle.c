@@ -625,9 +625,9 @@ void or_source_rates_cell(const or_ctx *cx, const double *Uin, double h, double 
     }
 }
 
-/* A cell with no particles that is not supersaturated over liquid has no source:
- * no nucleation, growth or freezing can start there (the rates below are all zero).
- * Decided on the closed-form saturation pressure in either property mode.        */
+/* The equilibrium comparison model's rule for a cell without condensate: it
+ * changes only once it is supersaturated over liquid (no ice from vapour alone),
+ * judged on the closed-form saturation pressure in either property mode.          */
 static int source_idle(const double *U)
 {
     if (U[5] > N_MIN || U[9] > N_MIN || U[15] > N_MIN) return 0;
@@ -650,16 +650,20 @@ static int source_integrate(const or_ctx *cx, const double *U0, double dt, doubl
 {
     double U[NV];
     memcpy(U, U0, sizeof(U));
-    if (!cx->c.phase_change || source_idle(U)) {
-        for (int v = 0; v < NV; ++v) Q[v] = 0.0;
-        return 0;
-    }
+    for (int v = 0; v < NV; ++v) Q[v] = 0.0;
+    if (!cx->c.phase_change) return 0;
     const int npop = cx->bimodal ? 2 : 1;
     const double fpi = 4.0 / 3.0 * PI;
     rates_t r;
     double S[NV];
     phase_change_rates(cx, U, dt, &r);
     exchange_terms(U, (const double(*)[4])r.dM, r.dN, npop, r.act, r.mdot_f, S);
+    /* rates that vanish in every component, with no population left without mass,
+     * leave the state as it is, so every later evaluation vanishes too: no source
+     * (e.g. a cell without particles that is not supersaturated over liquid) */
+    int live = r.stale_l[0] || r.stale_l[1] || r.stale_s;
+    for (int v = 0; v < NV && !live; ++v) live = S[v] != 0.0;
+    if (!live) return 0;
     /* depletion time scales and positivity scaling protect the components that are
      * not negative already (transport of sharp fields can leave a moment slightly
      * negative; no scaling of the step restores it) */
