@@ -265,9 +265,11 @@ const char *cp_error_string(const cp_ctx *ctx);
 /* ---------------------------------------------------------------------- batch
  * Many operating points (plumes), each with its own mesh and case, advanced
  * together: every RK stage is one launch over a work list of (plume, tile) pairs
- * (the tile shape picked by timing every built shape before the first step),
- * each plume keeps its own CFL time step on the device, and the whole step is a
- * captured HIP graph.  Per-plume results are identical to running that plume alone.
+ * (the tile shape picked by timing every built shape before the first step), each
+ * plume with its own tile masks of non-zero passive scalars (seeded at every
+ * cp_batch_step_n call), the CFL limit over (plume, tile) pairs with one time step
+ * per plume kept on the device, and the whole step is a captured HIP graph.
+ * Per-plume results are identical to running that plume alone.
  * Arrays: U[p] is plume p's U[15][nr_p][nx_p] (caller-owned device memory).         */
 typedef struct cp_batch cp_batch;
 
