@@ -23,6 +23,12 @@
  * Readings where the paper is silent are documented beside the code that takes
  * them (and in the design notes of the repository).
  *
+ * Parity unpinned (nothing but the paper's own statement to check them against):
+ * the immersion-freezing time scale k_imm (Eq. 14-15 carry no time unit) and the
+ * Kantrowitz bracket of Eq. 5 beyond its classical form.  Every other part is pinned
+ * in the tests against closed forms, exact solutions, quadrature, invariants or
+ * published values.
+ *
  * Build:  gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC  (no fast-math).
  * Every per-cell result is independent of the thread count.
  */
