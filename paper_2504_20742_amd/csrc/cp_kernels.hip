@@ -262,7 +262,14 @@ template <class TileT> __device__ __forceinline__ auto *scalar_slot(TileT &t, in
 
 // phi = U / rho with one transport reciprocal per cell and group.
 template <class R> __device__ __forceinline__ R inv_rho(R rho) { return trcp(rho); }
-template <class R> __device__ __forceinline__ R per_mass(R U, R, R ir) { return U * ir; }
+// The product is rounded on its own (never fused into a later operation), whether
+// it goes through the tile's slots or straight into a flux: both paths then see the
+// same per-mass values.
+template <class R> __device__ __forceinline__ R per_mass(R U, R, R ir)
+{
+#pragma clang fp contract(off)
+    return U * ir;
+}
 
 // Fold the surrogate's per-stage counters into its running totals and clear them.
 __device__ __forceinline__ void sur_fold_counts(int *cnt, unsigned long long *tot)
@@ -520,6 +527,37 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                     if (k < ng) res[s0 + k] = R(0);
             }
             continue;
+        }
+        if (!q1d && inner && __builtin_popcount(cg) == 1) {
+            // one candidate scalar on an interior tile: each cell reads its stencil of
+            // that scalar straight from memory (the same per-mass values, slopes and
+            // fluxes as through the tile's slots, without the load pass and its
+            // barrier; a scalar zero on the cell's whole stencil gives the same zero)
+            const int k = __builtin_ctz(cg);
+            #pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (q < ng && q != k) res[s0 + q] = R(0);
+            const unsigned c0 = (unsigned)(j * nx + i);
+            auto phi = [&](int off, int le) {
+                const R u = ld_plane(a.Uin, a.plane, s0 + k, c0 + (unsigned)off);
+                const R rho = t.rho[le];
+                return per_mass(u, rho, inv_rho(rho));
+            };
+            const R pc = phi(0, l), pw = phi(-1, l - 1), pe = phi(1, l + 1);
+            const R pww = phi(-2, l - 2), pee = phi(2, l + 2);
+            const R ps = phi(-nx, l - EX), pn = phi(nx, l + EX);
+            const R pss = phi(-2 * nx, l - 2 * EX), pnn = phi(2 * nx, l + 2 * EX);
+            const R sxw = vl_slope(pw - pww, pc - pw), sxc = vl_slope(pc - pw, pe - pc);
+            const R sxe = vl_slope(pe - pc, pee - pe);
+            const R fw = scalar_flux(pw, pc, sxw, sxc, Fm0, kd0);
+            const R fe = scalar_flux(pc, pe, sxc, sxe, Fm1, kd1);
+            const R srs_ = vl_slope(ps - pss, pc - ps), src = vl_slope(pc - ps, pn - pc);
+            const R srn = vl_slope(pn - pc, pnn - pn);
+            const R fs_raw = scalar_flux(ps, pc, srs_, src, Fm2, kd2);
+            const R fsv = (axi && j == 0) ? R(0) : fs_raw;   // zero-area axis face
+            const R fnv = scalar_flux(pc, pn, src, srn, Fm3, kd3);
+            res[s0 + k] = assemble_r(assemble_x(fe, fw, idx), fnv, m.rfa[j + 1], fsv, m.rfa[j], m.invV_r[j]);
+            continue;   // the slots were not written: prev_live stands
         }
         // the slots are free once every thread is done with the previous group's
         // fluxes; a group with nothing live read none of them
