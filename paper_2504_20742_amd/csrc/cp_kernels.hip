@@ -124,20 +124,25 @@ template <class R> __device__ __forceinline__ R vl_slope(R a, R b)
 }
 
 // LDS tile: primitives of TX x TY cells plus a 2-cell halo (ext, EX x EY), vapour
-// diffusivity, eddy viscosity and limited slopes of one direction on the tile plus a
-// 1-cell ring (RX x RY), and one face buffer reused for the x-faces and the r-faces.  Whatever is cheap to recompute (molecular viscosity, the
-// faces' eddy diffusivity, a halo cell's source address) is not stored: the FP32 tile
-// then fits six workgroups per CU.
+// diffusivity, molecular and eddy viscosity and limited slopes of one direction on the
+// tile plus a 1-cell ring (RX x RY), and one face buffer reused for the x-faces and the
+// r-faces (the mass flux is its first component, which is also the Roe mass flux the
+// scalars are upwinded with).  Whatever is cheap to recompute (the faces' eddy
+// diffusivity, a halo cell's source address) is not stored: the FP32 tile then fits six
+// workgroups per CU.
 template <class R, int TX, int TY> struct Tile {
     static constexpr int EX = TX + 4, EY = TY + 4, N = EX * EY;
     static constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     static constexpr int NFX = (TX + 1) * TY, NFR = TX * (TY + 1);
     static constexpr int NF = NFX > NFR ? NFX : NFR;
-    static constexpr int NFB = 6 * NF;
+    // slopes: x slopes on the ring's rows 1..TY (RX x TY), then r slopes on its columns
+    // 1..TX (TX x (TY + 2)), each with its own compact index
+    static constexpr int NSX = RX * TY, NSR = TX * (TY + 2), NS = NSX > NSR ? NSX : NSR;
+    static constexpr int NFB = 5 * NF;
     R rho[N], u[N], v[N], p[N], T[N], Y[N];   // u..Y are reused for 5 scalars at a time
-    R D[NR], mut[NR];
-    R sl[5][NR];                 // gas slopes of one direction (x, then r)
-    R fbuf[NFB];                 // faces: F (5 components) and Roe mass flux, [6][NF]
+    R D[NR], mu[NR], mut[NR];
+    R sl[5][NS];                 // gas slopes of one direction (x, then r)
+    R fbuf[NFB];                 // faces: F (5 components, [5][NF]); F[0] is the Roe mass flux
     int nonzero[3];              // per scalar group: bit k set when scalar k is non-zero somewhere in the tile
     unsigned omask;              // non-zero passive scalars of the tile's output (bit v: variable v)
     __device__ R (*face())[NF] { return reinterpret_cast<R(*)[NF]>(fbuf); }
@@ -162,34 +167,34 @@ template <int TX, int TY> __device__ __forceinline__ int ring_of_ext(int e)
 }
 
 // Gas flux through the face between ext cells a and b = a + s (normal stride s,
-// tangential stride ts; ra, rb their ring indices): MUSCL states from the cell
+// tangential stride ts; ra, rb their ring indices, sa, sb their slope indices): MUSCL states from the cell
 // slopes, Roe convective flux, central viscous + eddy flux.  Writes F^c - F^v on
-// (rho, rho u, rho v, rho E, rho Y) in global components and the Roe mass flux.
+// (rho, rho u, rho v, rho E, rho Y) in global components; F[0] is the Roe mass flux.
 template <class R, class TileT>
-__device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, int s, int ts, bool xdir, R inv_dn,
-                                         R inv_d2t, R inv_r, R pref, R *F, R &Fm)
+__device__ __forceinline__ void gas_face(const TileT &t, int a, int ra, int rb, int sa, int sb, int s, int ts, bool xdir, R inv_dn,
+                                         R inv_d2t, R inv_r, R pref, R *F)
 {
     const int b = a + s;
-    const R(*sl)[TileT::NR] = t.sl;   // slopes of the face-normal direction
+    const R(*sl)[TileT::NS] = t.sl;   // slopes of the face-normal direction
     const R *un_ = xdir ? t.u : t.v;
     const R *ut_ = xdir ? t.v : t.u;
     R qL[5], qR[5];
-    qL[0] = t.rho[a] + R(0.5) * sl[0][ra];
-    qR[0] = t.rho[b] - R(0.5) * sl[0][rb];
-    qL[1] = un_[a] + R(0.5) * sl[xdir ? 1 : 2][ra];
-    qR[1] = un_[b] - R(0.5) * sl[xdir ? 1 : 2][rb];
-    qL[2] = ut_[a] + R(0.5) * sl[xdir ? 2 : 1][ra];
-    qR[2] = ut_[b] - R(0.5) * sl[xdir ? 2 : 1][rb];
-    qL[3] = t.p[a] + R(0.5) * sl[3][ra];
-    qR[3] = t.p[b] - R(0.5) * sl[3][rb];
-    qL[4] = t.Y[a] + R(0.5) * sl[4][ra];
-    qR[4] = t.Y[b] - R(0.5) * sl[4][rb];
+    qL[0] = t.rho[a] + R(0.5) * sl[0][sa];
+    qR[0] = t.rho[b] - R(0.5) * sl[0][sb];
+    qL[1] = un_[a] + R(0.5) * sl[xdir ? 1 : 2][sa];
+    qR[1] = un_[b] - R(0.5) * sl[xdir ? 1 : 2][sb];
+    qL[2] = ut_[a] + R(0.5) * sl[xdir ? 2 : 1][sa];
+    qR[2] = ut_[b] - R(0.5) * sl[xdir ? 2 : 1][sb];
+    qL[3] = t.p[a] + R(0.5) * sl[3][sa];
+    qR[3] = t.p[b] - R(0.5) * sl[3][sb];
+    qL[4] = t.Y[a] + R(0.5) * sl[4][sa];
+    qR[4] = t.Y[b] - R(0.5) * sl[4][sb];
     R Fc[4];
     roe_flux(qL, qR, pref, Fc);
-    Fm = Fc[0];
+    const R Fm = Fc[0];
     const R FY = Fm * (Fm >= R(0) ? qL[4] : qR[4]);
 
-    const R mu = R(0.5) * (sutherland_t(t.T[a]) + sutherland_t(t.T[b]));
+    const R mu = R(0.5) * (t.mu[ra] + t.mu[rb]);
     const R mut = R(0.5) * (t.mut[ra] + t.mut[rb]);
     const R rho = R(0.5) * (t.rho[a] + t.rho[b]);
     const R cpf = R(0.5) * (gas_cp(t.Y[a]) + gas_cp(t.Y[b]));
@@ -379,19 +384,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         t.p[e] = U0 * gas_R(Y) * T;
     }
     __syncthreads();
-    // phase 2 (tile + ring): viscosity, vapour diffusivity, eddy viscosity
-    // mu_t = rho l^2 |du/dr + dv/dx|, and van Leer slopes of the gas primitives
+    // phase 2 (tile + ring): molecular viscosity, vapour diffusivity, eddy viscosity
+    // mu_t = rho l^2 |du/dr + dv/dx|, and van Leer x slopes of the gas primitives (the
+    // x-faces need them on the tile's rows only, not on the ring's first and last)
     for (int r = tid; r < NRG; r += NT) {
         const int l = ext_of_ring<TX, TY>(r);
         const int i = min(i0 + r % RX - 1, nx), j = min(j0 + r / RX - 1, nr);
         const R T = t.T[l];
+        t.mu[r] = sutherland_t(T);
         t.D[r] = R(kD0) * fpow_pos(T * R(1.0 / kTref), R(kDexp)) * tdiv(R(kP0), t.p[l]);
         const R dudr = (t.u[l + EX] - t.u[l - EX]) * m.inv_d2r[j + 1];
         const R dvdx = (t.v[l + 1] - t.v[l - 1]) * m.inv_d2x[i + 1];
         t.mut[r] = t.rho[l] * m.lm2[i + 1] * fabs(dudr + dvdx);
-        const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
-        #pragma unroll
-        for (int k = 0; k < 5; ++k) t.sl[k][r] = vl_slope(w[k][l] - w[k][l - 1], w[k][l + 1] - w[k][l]);
+        if (r >= RX && r < RX * (TY + 1)) {
+            const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
+            #pragma unroll
+            for (int k = 0; k < 5; ++k) t.sl[k][r - RX] = vl_slope(w[k][l] - w[k][l - 1], w[k][l + 1] - w[k][l]);
+        }
     }
     __syncthreads();
 
@@ -407,11 +416,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
         const int la = (fj + 2) * EX + fi + 1;
         const int ra = (fj + 1) * RX + fi;
-        R F[5], fm;
-        gas_face<R>(t, la, ra, ra + 1, 1, EX, true, m.inv_dxf[ig], m.inv_d2r[jg + 1], m.inv_rc[jg + 1], pref, F, fm);
+        R F[5];
+        gas_face<R>(t, la, ra, ra + 1, ra - RX, ra - RX + 1, 1, EX, true, m.inv_dxf[ig], m.inv_d2r[jg + 1],
+                    m.inv_rc[jg + 1], pref, F);
         #pragma unroll
         for (int k = 0; k < 5; ++k) face[k][f] = F[k];
-        face[5][f] = fm;
     }
     __syncthreads();
     R res[NV];
@@ -428,7 +437,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             const R dudx = (t.u[l + 1] - t.u[l - 1]) * m.inv_d2x[i + 1];
             const R dvdr = (t.v[l + EX] - t.v[l - EX]) * m.inv_d2r[j + 1];
             const R vr = t.v[l] * ir;
-            const R mue = sutherland_t(t.T[l]) + t.mut[rl];
+            const R mue = t.mu[rl] + t.mut[rl];
             const R ttt = mue * (R(2) * vr - R(2.0 / 3.0) * (dudx + dvdr + vr));
             hoop = ((t.p[l] - pref) - ttt) * ir;
         }
@@ -446,32 +455,34 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             #pragma unroll
             for (int k = 0; k < 5; ++k) res[k] = assemble_x(face[k][fw + 1], face[k][fw], idx);
         }
-        Fm0 = face[5][fw];
-        Fm1 = face[5][fw + 1];
+        Fm0 = face[0][fw];
+        Fm1 = face[0][fw + 1];
         kd0 = face_kd(t.mut[rl - 1], t.mut[rl], m.inv_dxf[i]);
         kd1 = face_kd(t.mut[rl], t.mut[rl + 1], m.inv_dxf[i + 1]);
     }
-    // r-direction gas slopes, over the x slopes the x-faces no longer need
-    for (int r = tid; r < NRG; r += NT) {
+    // r-direction gas slopes, over the x slopes the x-faces no longer need: the r-faces
+    // need them on the tile's columns only, not on the ring's first and last
+    for (int q = tid; q < TX * (TY + 2); q += NT) {
+        const int r = (q / TX) * RX + q % TX + 1;
         const int le = ext_of_ring<TX, TY>(r);
         const R *w[5] = {t.rho, t.u, t.v, t.p, t.Y};
         #pragma unroll
-        for (int k = 0; k < 5; ++k) t.sl[k][r] = vl_slope(w[k][le] - w[k][le - EX], w[k][le + EX] - w[k][le]);
+        for (int k = 0; k < 5; ++k) t.sl[k][q] = vl_slope(w[k][le] - w[k][le - EX], w[k][le + EX] - w[k][le]);
     }
     __syncthreads();
     // phase 4: r-faces, each once (the axis face has zero area)
     for (int f = tid; f < TileT::NFR; f += NT) {
         const int fi = f % TX, fj = f / TX;
         const int ig = min(i0 + fi, nx), jg = min(j0 + fj, nr);
-        R F[5] = {R(0), R(0), R(0), R(0), R(0)}, fm = R(0);
+        R F[5] = {R(0), R(0), R(0), R(0), R(0)};
         if (!(axi && jg == 0) && !q1d) {
             const int la = (fj + 1) * EX + fi + 2;
             const int ra = fj * RX + fi + 1;
-            gas_face<R>(t, la, ra, ra + RX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1], m.inv_rf[jg], pref, F, fm);
+            gas_face<R>(t, la, ra, ra + RX, f, f + TX, EX, 1, false, m.inv_drf[jg], m.inv_d2x[ig + 1],
+                        m.inv_rf[jg], pref, F);
         }
         #pragma unroll
         for (int k = 0; k < 5; ++k) face[k][f] = F[k];
-        face[5][f] = fm;
     }
     __syncthreads();
     if (valid) {
@@ -479,8 +490,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         const R ivr = m.invV_r[j], as = m.rfa[j], an = m.rfa[j + 1];
         #pragma unroll
         for (int k = 0; k < 5; ++k) res[k] = assemble_r(res[k], face[k][fn], an, face[k][fs], as, ivr);
-        Fm2 = face[5][fs];
-        Fm3 = face[5][fn];
+        Fm2 = face[0][fs];
+        Fm3 = face[0][fn];
         if (!q1d) {   // the axis face's scalar flux is zeroed where it is used
             kd2 = face_kd(t.mut[rl - RX], t.mut[rl], m.inv_drf[j]);
             kd3 = face_kd(t.mut[rl], t.mut[rl + RX], m.inv_drf[j + 1]);

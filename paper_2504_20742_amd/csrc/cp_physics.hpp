@@ -906,17 +906,18 @@ template <class R> __device__ __forceinline__ R van_leer(R a, R b)
     return (a * b > R(0)) ? R(2) * a * b / (a + b) : R(0);
 }
 
-// c = sqrt(c^2) and 1 / c^2: in FP32 from one reciprocal square root
-__device__ __forceinline__ void sound_speed(float c2, float &c, float &ic2)
+// c = sqrt(c^2), 1 / c and 1 / c^2: in FP32 from one reciprocal square root
+__device__ __forceinline__ void sound_speed(float c2, float &c, float &ic, float &ic2)
 {
-    const float ic = __builtin_amdgcn_rsqf(c2);
+    ic = __builtin_amdgcn_rsqf(c2);
     c = c2 * ic;
     ic2 = ic * ic;
 }
-__device__ __forceinline__ void sound_speed(double c2, double &c, double &ic2)
+__device__ __forceinline__ void sound_speed(double c2, double &c, double &ic, double &ic2)
 {
     c = sqrt(c2);
     ic2 = tdiv(1.0, c2);
+    ic = c * ic2;
 }
 
 // Roe flux on (rho, rho u_n, rho u_t, rho E) of the two-species gas in primitive-
@@ -943,8 +944,8 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R h0 = gas_h0(Y);
     // c^2 = gamma R T with T = (H - q^2/2 - h0) / c_p and gamma = c_p / c_v
     const R c2 = Rm * tdiv(H - R(0.5) * q2 - h0, gas_cv(Y));
-    R c, ic2;
-    sound_speed(c2, c, ic2);
+    R c, ic, ic2;
+    sound_speed(c2, c, ic, ic2);
 
     const R dr = rr - rl, dun = unr - unl, dut = utr - utl, dp = pr - pl;
     const R i2c2 = R(0.5) * ic2;
@@ -954,9 +955,10 @@ template <class R> __device__ __forceinline__ void roe_flux(const R *qL, const R
     const R a4 = (dp + rho * c * dun) * i2c2;
     R l1 = fabs(un - c), l4 = fabs(un + c);
     const R l2 = fabs(un);
-    const R del = R(0.1) * c;
-    if (l1 < del) l1 = tdiv(l1 * l1 + del * del, R(2) * del);
-    if (l4 < del) l4 = tdiv(l4 * l4 + del * del, R(2) * del);
+    // Harten's fix within del = c / 10: l -> (l^2 + del^2) / (2 del), with 1 / (2 del) = 5 / c
+    const R del = R(0.1) * c, i2del = R(5) * ic;
+    if (l1 < del) l1 = (l1 * l1 + del * del) * i2del;
+    if (l4 < del) l4 = (l4 * l4 + del * del) * i2del;
     const R w1 = l1 * a1, w2 = l2 * a2, w3 = l2 * a3, w4 = l4 * a4;
     // eigenvectors: (1, un-c, ut, H-un c), (1, un, ut, q2/2 + h0), (0, 0, 1, ut), (1, un+c, ut, H+un c)
     F[0] = R(0.5) * (ml + mr) - R(0.5) * (w1 + w2 + w4);
