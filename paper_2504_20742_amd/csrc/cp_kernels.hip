@@ -349,29 +349,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         t.omask = 0;
     }
     // phase 1: gas primitives of tile + halo
-    for (int e = tid; e < NE; e += NT) {
-        const int ex = e % EX, ey = e / EX;
-        const int i = min(i0 + ex - 2, nx + 1), j = min(j0 + ey - 2, nr + 1);
-        int code;
-        R U0, U1, U2, U3, U4;
-        if (inner) {
-            code = j * nx + i;
-            U0 = ld_plane(a.Uin, a.plane, 0, code);
-            U1 = ld_plane(a.Uin, a.plane, 1, code);
-            U2 = ld_plane(a.Uin, a.plane, 2, code);
-            U3 = ld_plane(a.Uin, a.plane, 3, code);
-            U4 = ld_plane(a.Uin, a.plane, 4, code);
-        } else {
-            const CellSrc cs = map_cell(i, j, bc);
-            code = cs.code;
-            U0 = fetch(a.Uin, a.plane, bc, code, 0);
-            U1 = fetch(a.Uin, a.plane, bc, code, 1);
-            U2 = fetch(a.Uin, a.plane, bc, code, 2);
-            U3 = fetch(a.Uin, a.plane, bc, code, 3);
-            U4 = fetch(a.Uin, a.plane, bc, code, 4);
-            if (cs.fu) U1 = -U1;
-            if (cs.fv) U2 = -U2;
-        }
+    auto put_prims = [&](int e, R U0, R U1, R U2, R U3, R U4) {
         const R ir = trcp(U0);
         const R u = U1 * ir, v = U2 * ir, Y = U4 * ir;
         const R eint = U3 * ir - R(0.5) * (u * u + v * v);
@@ -382,6 +360,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         t.Y[e] = Y;
         t.T[e] = T;
         t.p[e] = U0 * gas_R(Y) * T;
+    };
+    if (inner) {
+        // every load of the thread's cells is issued before the first is used: one
+        // round trip to memory per tile rather than one per pass of the loop
+        constexpr int NP = (NE + NT - 1) / NT;
+        R Ub[NP][5];
+        #pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int e = min(tid + q * NT, NE - 1);   // a spare lane reloads the last cell
+            const unsigned code = (unsigned)((j0 + e / EX - 2) * nx + i0 + e % EX - 2);
+            #pragma unroll
+            for (int v = 0; v < 5; ++v) Ub[q][v] = ld_plane(a.Uin, a.plane, v, code);
+        }
+        #pragma unroll
+        for (int q = 0; q < NP; ++q)
+            if (tid + q * NT < NE) put_prims(tid + q * NT, Ub[q][0], Ub[q][1], Ub[q][2], Ub[q][3], Ub[q][4]);
+    } else {
+        for (int e = tid; e < NE; e += NT) {
+            const int i = min(i0 + e % EX - 2, nx + 1), j = min(j0 + e / EX - 2, nr + 1);
+            const CellSrc cs = map_cell(i, j, bc);
+            R U1 = fetch(a.Uin, a.plane, bc, cs.code, 1), U2 = fetch(a.Uin, a.plane, bc, cs.code, 2);
+            if (cs.fu) U1 = -U1;
+            if (cs.fv) U2 = -U2;
+            put_prims(e, fetch(a.Uin, a.plane, bc, cs.code, 0), U1, U2, fetch(a.Uin, a.plane, bc, cs.code, 3),
+                      fetch(a.Uin, a.plane, bc, cs.code, 4));
+        }
     }
     __syncthreads();
     // phase 2 (tile + ring): molecular viscosity, vapour diffusivity, eddy viscosity
