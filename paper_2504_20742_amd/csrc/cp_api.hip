@@ -521,22 +521,37 @@ int stage_any(cp_ctx *c, const void *Uin, const void *Un, void *Uout, int stage,
     return CP_OK;
 }
 
+// Arguments of the CFL reduction over U for context c (the running minimum and
+// the per-workgroup array are the caller's).
+template <class R> CflArgs<R> cfl_args(const cp_ctx *c, const void *U)
+{
+    CflArgs<R> a;
+    a.U = (const R *)U;
+    a.plane = c->plane;
+    a.bc = bcinfo(c);
+    a.xc = c->xc_d;
+    a.rc = c->rc_d;
+    a.inv_dx = c->inv_dx_d;
+    a.inv_dr = c->inv_dr_d;
+    const bool f32 = sizeof(R) == 4;
+    a.f_d2x = f32 ? (const float *)c->met[M_INV_D2X] : nullptr;
+    a.f_d2r = f32 ? (const float *)c->met[M_INV_D2R] : nullptr;
+    a.f_lm2 = f32 ? (const float *)c->met[M_LM2] : nullptr;
+    a.f_idx = f32 ? (const float *)c->met[M_INV_DX] : nullptr;
+    a.kappa_m = c->cs.kappa_m;
+    a.delta0 = c->cs.delta0_frac * c->cs.R_core;
+    a.s_delta = c->cs.s_delta;
+    a.acc = nullptr;
+    a.block_min = nullptr;
+    return a;
+}
+
 int cfl_any(cp_ctx *c, const void *U, hipStream_t s)
 {
     hipError_t e;
     auto fill = [&](auto *tag) {
         using R = std::remove_pointer_t<decltype(tag)>;
-        CflArgs<R> a;
-        a.U = (const R *)U;
-        a.plane = c->plane;
-        a.bc = bcinfo(c);
-        a.xc = c->xc_d;
-        a.rc = c->rc_d;
-        a.inv_dx = c->inv_dx_d;
-        a.inv_dr = c->inv_dr_d;
-        a.kappa_m = c->cs.kappa_m;
-        a.delta0 = c->cs.delta0_frac * c->cs.R_core;
-        a.s_delta = c->cs.s_delta;
+        CflArgs<R> a = cfl_args<R>(c, U);
         a.acc = c->acc_d;
         a.block_min = c->cfl_bm;
         return launch_cfl<R>(a, s);
@@ -1162,16 +1177,7 @@ template <class R> int batch_upload_args(cp_batch *b, void *const *U)
             fa[s].push_back(fix_args<R>(c, in[s], out[s], s, 0.0, b->dt + p));
         }
         CflArgs<R> &a = ca[p];
-        a.U = (const R *)U[p];
-        a.plane = c->plane;
-        a.bc = bcinfo(c);
-        a.xc = c->xc_d;
-        a.rc = c->rc_d;
-        a.inv_dx = c->inv_dx_d;
-        a.inv_dr = c->inv_dr_d;
-        a.kappa_m = c->cs.kappa_m;
-        a.delta0 = c->cs.delta0_frac * c->cs.R_core;
-        a.s_delta = c->cs.s_delta;
+        a = cfl_args<R>(c, U[p]);
         a.acc = b->acc + p;
         a.block_min = nullptr;   // the batch merges into per-plume running minima
     }

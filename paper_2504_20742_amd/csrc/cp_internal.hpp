@@ -112,11 +112,15 @@ template <class R> struct CflArgs {
     BcInfo bc;
     const double *xc, *rc;     // double centres (offset 2)
     const double *inv_dx, *inv_dr;
+    // FP32 contexts: the mesh factors of the limit in the storage precision, indexed as
+    // in Metrics (1/(x_{i+1} - x_{i-1}) and l_m^2 at i + 1, 1/(r_{j+1} - r_{j-1}) at
+    // j + 1, 1/dx at i); null for FP64 contexts, whose limit uses the centres above
+    const float *f_d2x, *f_d2r, *f_lm2, *f_idx;
     double kappa_m, delta0, s_delta;
     unsigned long long *acc;   // running min of the per-cell limit (bits of a positive double)
     double *block_min;         // tiled kernels: one minimum per workgroup (or null: use acc)
 };
-constexpr int kCflBX = 64, kCflBY = 4, kCflRows = 4;   // CFL kernels: 64 x 4 threads, 4 rows each
+constexpr int kCflBX = 64, kCflBY = 4, kCflRows = 2;   // CFL kernels: 64 x 4 threads, 2 rows each
 
 struct Ctx;   // host context (cp_api.hip)
 }  // namespace cp

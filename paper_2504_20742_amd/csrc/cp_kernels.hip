@@ -1324,10 +1324,9 @@ __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, i
                                                float uS, float vE, float vW)
 {
 #pragma clang fp contract(off)
-    const float dudr = (uN - uS) * __builtin_amdgcn_rcpf((float)(a.rc[j + 3] - a.rc[j + 1]));
-    const float dvdx = (vE - vW) * __builtin_amdgcn_rcpf((float)(a.xc[i + 3] - a.xc[i + 1]));
-    const float lm = (float)(a.kappa_m * (a.delta0 + a.s_delta * a.xc[i + 2]));
-    const float mut = w.rho * lm * lm * fabsf(dudr + dvdx);
+    const float dudr = (uN - uS) * a.f_d2r[j + 1];
+    const float dvdx = (vE - vW) * a.f_d2x[i + 1];
+    const float mut = w.rho * a.f_lm2[i + 1] * fabsf(dudr + dvdx);
     const float Rm = (1.0f - w.Y) * float(kRa) + w.Y * float(kRv);
     const float cpm = (1.0f - w.Y) * float(kCpa) + w.Y * float(kCpv);
     const float cvm = (1.0f - w.Y) * float(kCva) + w.Y * float(kCvv);
@@ -1337,7 +1336,7 @@ __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, i
     const float mu = float(kMu0) * t * __builtin_amdgcn_sqrtf(t) * float(kTref + kSuth) * __builtin_amdgcn_rcpf(w.T + float(kSuth));
     const float fac = fmaxf(gam * float(1.0 / kPr), 4.0f / 3.0f);
     const float nu = (mu + mut) * __builtin_amdgcn_rcpf(w.rho) * fac;
-    const float idx = (float)a.inv_dx[i], idr = (float)a.inv_dr[j];
+    const float idx = a.f_idx[i], idr = (float)a.inv_dr[j];
     const float rate = (fabsf(w.u) + snd) * idx + (fabsf(w.v) + snd) * idr + 2.0f * nu * (idx * idx + idr * idr);
     return __builtin_amdgcn_rcpf(rate);
 }
