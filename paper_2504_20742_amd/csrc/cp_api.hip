@@ -53,8 +53,7 @@ struct cp_ctx {
     int *sur_cnt = nullptr, *sur_cells = nullptr, *fb_list = nullptr;
     unsigned long long *sur_tot = nullptr;   // running totals of network / fallback cells
     int *src_cnt = nullptr, *src_list = nullptr;   // active cells of a cp_source call
-    uint16_t *sur_X = nullptr;   // gated feature rows (bf16) and network outputs
-    float *sur_Y = nullptr;
+    float *sur_Y = nullptr;      // network outputs of the gated rows
     uint16_t *sur_w = nullptr;   // packed snapshot of the attached network's weights
     float *sur_b = nullptr;
     SourceParams sp{};
@@ -417,7 +416,6 @@ SurArgs<R> sur_args(const cp_ctx *c, const void *Uin, void *Uout, int stage, dou
     a.cnt = c->sur_cnt;
     a.mlp_cells = c->sur_cells;
     a.fb_list = c->fb_list;
-    a.X = c->sur_X;
     a.Y = c->sur_Y;
     a.nm = c->nm;
     a.flag = c->flag_d;
@@ -432,17 +430,16 @@ FusedNet sur_net(const cp_ctx *c)
                     c->sur_b + 512};
 }
 
-// Learned source for the active cells of a stage: split them (network / exact),
-// run the network on its rows, decode + project + apply, exact source for the rest.
+// Learned source for the active cells of a stage: split them (network / exact) and run
+// the network on its rows in one launch, then decode + project + apply, exact source
+// for the rest.
 template <class R>
 int surrogate_stage(cp_ctx *c, const void *Uin, void *Uout, int stage, double dt, const double *dt_dev, hipStream_t s)
 {
     // the stage kernel has already folded and cleared the counters
     SurArgs<R> a = sur_args<R>(c, Uin, Uout, stage, dt, dt_dev);
-    hipError_t e = launch_sur_gate<R>(a, c->plane, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
-    e = mlp_fused_forward(sur_net(c), c->sur_X, 17, 15, c->sur_cnt, (int)c->plane, c->sur_Y, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
+    hipError_t e = launch_sur_gate_net<R>(a, sur_net(c), c->sur_Y, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate and network: ") + hipGetErrorString(e));
     const SourceFixArgs<R> f = fix_args<R>(c, Uin, Uout, stage, dt, dt_dev);
     e = launch_sur_finish<R>(a, f.sp, f.next_count, c->nsub_d, c->plane, s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate finish: ") + hipGetErrorString(e));
@@ -462,10 +459,8 @@ template <class R> int surrogate_source(cp_ctx *c, const void *U, double dt, voi
     a.q_only = 1;
     a.mask = TileMask{};
     if (e == hipSuccess) e = launch_sur_reset(c->sur_cnt, c->sur_tot, s);
-    if (e == hipSuccess) e = launch_sur_gate<R>(a, c->plane, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate: ") + hipGetErrorString(e));
-    e = mlp_fused_forward(sur_net(c), c->sur_X, 17, 15, c->sur_cnt, (int)c->plane, c->sur_Y, s);
-    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
+    if (e == hipSuccess) e = launch_sur_gate_net<R>(a, sur_net(c), c->sur_Y, c->plane, s);
+    if (e != hipSuccess) return fail(c, CP_EHIP, std::string("surrogate gate and network: ") + hipGetErrorString(e));
     SourceParams sp = c->sp;
     sp.enabled = 1;
     e = launch_sur_finish<R>(a, sp, nullptr, nullptr, c->plane, s);
@@ -895,7 +890,6 @@ int cp_sur_set(cp_ctx *c, cp_mlp *mlp, const float *norm, int n_norm)
     if (!c->fb_list && !(c->fb_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
     if (!c->src_list && !(c->src_list = dalloc<int>(c, c->plane))) return fail(c, CP_ENOMEM, "surrogate lists");
     if (!mlp_fusable(mlp)) return fail(c, CP_EUNSUPPORTED, "in-step inference needs 256 hidden units");
-    if (!c->sur_X && !(c->sur_X = dalloc<uint16_t>(c, (size_t)c->plane * 17))) return fail(c, CP_ENOMEM, "feature rows");
     if (!c->sur_Y && !(c->sur_Y = dalloc<float>(c, (size_t)c->plane * 15))) return fail(c, CP_ENOMEM, "output rows");
     if (!c->sur_w && !(c->sur_w = dalloc<uint16_t>(c, kFusedW1 + kFusedW2 + kFusedW3)))
         return fail(c, CP_ENOMEM, "packed weights");

@@ -150,7 +150,6 @@ template <class R> hipError_t launch_stage(const StageArgs<R> &a, int tx, int ty
 template <class R> hipError_t launch_cfl(const CflArgs<R> &a, hipStream_t s);
 template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long max_cells, int nv, hipStream_t s);
 template <class R> hipError_t launch_drift(const DriftArgs<R> &a, hipStream_t s);
-hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s);
 // dt = cfl * min(block_min[0..n)), t += dt (t nullable)
 hipError_t launch_cfl_finalize_blocks(const double *block_min, int n, double cfl, double *dt, double *t, hipStream_t s);
 template <class R>
@@ -191,14 +190,14 @@ template <class R> struct SurArgs {
     int *cnt;                  // [0] cells gated to the network, [1] gate fallback cells,
                                // [2] network cells rejected at decode (exact source)
     int *mlp_cells, *fb_list;
-    uint16_t *X;               // bf16 features [rows][17]
-    const float *Y;            // network output [rows][15]
+    const float *Y;            // network output [rows][15] (written by the gate's launch)
     SurNorm nm;
     int *flag;
     int q_only;                // write Q itself to Uout (cp_source) instead of adding b dt Q
     TileMask mask;             // mask.out: tile mask of Uout, widened by the cells changed here
 };
-template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s);
+template <class R>
+hipError_t launch_sur_gate_net(const SurArgs<R> &a, const FusedNet &w, float *Y, long max_cells, hipStream_t s);
 template <class R>
 hipError_t launch_sur_finish(const SurArgs<R> &a, const SourceParams &sp, int *next_count, unsigned long long *nsub,
                              long max_cells, hipStream_t s);

@@ -12,6 +12,7 @@
 // stream.  Cells where the phase-change source (Sec. 2.2) can act are appended to
 // a compacted list; k_source_fix integrates the stiff source for those cells
 // only, which keeps the register footprint of the stencil kernel small.
+#include "cp_fused_net.hpp"
 #include "cp_internal.hpp"
 
 namespace cp {
@@ -968,39 +969,86 @@ __global__ void __launch_bounds__(256) k_sur_features(const R *U, long plane, do
     }
 }
 
-// Split the active cells: the network takes a cell whose standardised features lie
-// inside the training envelope, whose vapour is not near saturation
-// (|ln S_l| >= lnS_gate) and whose droplets cannot freeze (no droplets, or the gas
-// at or above the melting point); every other cell keeps the exact source.  Freezing
-// (Eq. 12-15) changes the crystal number by orders of magnitude per kelvin: that
-// regime stays with the exact source.
-template <class R> __global__ void __launch_bounds__(256) k_sur_gate(SurArgs<R> a)
+// The gate: the network takes a cell whose standardised features lie inside the
+// training envelope, whose vapour is not near saturation (|ln S_l| >= lnS_gate) and
+// whose droplets cannot freeze (no droplets, or the gas at or above the melting
+// point); every other cell keeps the exact source.  Freezing (Eq. 12-15) changes the
+// crystal number by orders of magnitude per kelvin: that regime stays with the exact
+// source.  f receives the standardised features.
+template <class R> __device__ __forceinline__ bool sur_gate_cell(const SurArgs<R> &a, long c, double dt, float *f)
 {
+    double T, M0;
+    const double lnSl = sur_raw_features(a.Uin, a.plane, c, dt, a.nm.s_in, f, &T, &M0);
+    const bool freezing = T < kTmelt && M0 > kNmin;
+    bool inside = !freezing && fabs(lnSl) >= (double)a.nm.lnS_gate && lnSl >= (double)a.nm.lnS_lo &&
+                  lnSl <= (double)a.nm.lnS_hi;
+    #pragma unroll
+    for (int q = 0; q < 17; ++q) {
+        f[q] = (f[q] - a.nm.mu_in[q]) / a.nm.sd_in[q];
+        inside = inside && f[q] >= a.nm.lo[q] && f[q] <= a.nm.hi[q];
+    }
+    return inside;
+}
+
+// Gate and network in one launch.  Each workgroup takes the active cells 64 at a time:
+// its first wavefront gates one cell per lane, appends the rejected cells to the
+// fallback list and packs the accepted ones into the rows of the network's input tile
+// (one counter update per wavefront for each list), and the whole workgroup then
+// evaluates the network on those rows (fused_net_tile), whose outputs land in Y at the
+// rows the cells were given in mlp_cells.  The workgroups stride over the list.
+template <class R>
+__global__ void __launch_bounds__(256, 2) k_sur_gate_net(SurArgs<R> a, FusedNet w, float *Y)
+{
+    __shared__ FusedXTile Xs;
+    __shared__ FusedHTile Hs;
+    __shared__ int tile_rows, tile_base;
     const int n = (int)min((long)*a.count, a.plane);
-    if ((long)blockIdx.x * blockDim.x >= n) return;   // no listed cell for this workgroup
+    if ((long)blockIdx.x * 64 >= n) return;   // no listed cell for this workgroup
     const double dt = a.dt_dev ? *a.dt_dev : a.dt;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const long c = a.list[k];
-        float f[17];
-        double T, M0;
-        const double lnSl = sur_raw_features(a.Uin, a.plane, c, dt, a.nm.s_in, f, &T, &M0);
-        const bool freezing = T < kTmelt && M0 > kNmin;
-        bool inside = !freezing && fabs(lnSl) >= (double)a.nm.lnS_gate && lnSl >= (double)a.nm.lnS_lo &&
-                      lnSl <= (double)a.nm.lnS_hi;
-        #pragma unroll
-        for (int q = 0; q < 17; ++q) {
-            f[q] = (f[q] - a.nm.mu_in[q]) / a.nm.sd_in[q];
-            inside = inside && f[q] >= a.nm.lo[q] && f[q] <= a.nm.hi[q];
+    const int lane = threadIdx.x & 63;
+    for (int m0 = blockIdx.x * 64; m0 < n; m0 += gridDim.x * 64) {
+        if (threadIdx.x < 64) {
+            const int k = m0 + lane;
+            const bool listed = k < n;
+            bool inside = false;
+            long c = 0;
+            float f[17];
+            if (listed) {
+                c = a.list[k];
+                inside = sur_gate_cell(a, c, dt, f);
+            }
+            const unsigned long long in_mask = __ballot(inside), fb_mask = __ballot(listed && !inside);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            int base = 0, fbase = 0;
+            if (lane == 0) {
+                if (in_mask) base = atomicAdd(a.cnt, __popcll(in_mask));
+                if (fb_mask) fbase = atomicAdd(a.cnt + 1, __popcll(fb_mask));
+            }
+            base = __shfl(base, 0, 64);
+            fbase = __shfl(fbase, 0, 64);
+            const int rows = __popcll(in_mask);
+            if (listed && !inside) a.fb_list[fbase + __popcll(fb_mask & below)] = (int)c;
+            if (inside) {
+                const int r = __popcll(in_mask & below);
+                a.mlp_cells[base + r] = (int)c;
+                #pragma unroll
+                for (int q = 0; q < kFusedKin; ++q) Xs[r][q] = q < 17 ? to_bf16(f[q]) : (uint16_t)0;
+            }
+            if (lane >= rows) {   // the tile's unused rows are zero
+                #pragma unroll
+                for (int q = 0; q < kFusedKin; ++q) Xs[lane][q] = 0;
+            }
+            if (lane == 0) {
+                tile_rows = rows;
+                tile_base = base;
+            }
         }
-        if (inside) {
-            const int slot = atomicAdd(a.cnt, 1);
-            a.mlp_cells[slot] = (int)c;
-            #pragma unroll
-            for (int q = 0; q < 17; ++q) a.X[(long)slot * 17 + q] = to_bf16(f[q]);
-        } else {
-            const int slot = atomicAdd(a.cnt + 1, 1);
-            a.fb_list[slot] = (int)c;
-        }
+        __syncthreads();
+        const int rows = tile_rows, base = tile_base;   // block-uniform
+        if (rows > 0)
+            fused_net_tile(w, Xs, Hs, rows, 15, Y + (long)base * 15);   // ends with a barrier
+        else
+            __syncthreads();   // every wave has read tile_rows before it is rewritten
     }
 }
 
@@ -1508,16 +1556,6 @@ __global__ void k_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
     acc[p] = 0x7FF0000000000000ull;
 }
 
-__global__ void k_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t)
-{
-#pragma clang fp contract(off)
-    const double m = __longlong_as_double((long long)*acc);
-    const double d = cfl * m;
-    *dt = d;
-    if (t) *t = *t + d;
-    *acc = 0x7FF0000000000000ull;   // +inf for the next reduction
-}
-
 // dt = cfl * (minimum of the per-workgroup minima), one workgroup.
 __global__ void __launch_bounds__(256) k_cfl_finalize_blocks(const double *bm, int n, double cfl, double *dt, double *t)
 {
@@ -1720,10 +1758,21 @@ template <class R> hipError_t launch_source_fix(const SourceFixArgs<R> &a, long 
     return hipGetLastError();
 }
 
-template <class R> hipError_t launch_sur_gate(const SurArgs<R> &a, long max_cells, hipStream_t s)
+template <class R>
+hipError_t launch_sur_gate_net(const SurArgs<R> &a, const FusedNet &w, float *Y, long max_cells, hipStream_t s)
 {
-    int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 255) / 256, 1024));
-    hipLaunchKernelGGL((k_sur_gate<R>), dim3(blocks), dim3(256), 0, s, a);
+    // the workgroups the device holds at once, striding over the list
+    static const int resident = [] {
+        int dev = 0, cus = 256, per_cu = 2;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sur_gate_net<R>, 256, 0) != hipSuccess)
+                per_cu = 2;
+        }
+        return std::max(1, cus) * std::max(1, per_cu);
+    }();
+    const int blocks = (int)std::max<long>(1, std::min<long>((max_cells + 63) / 64, resident));
+    hipLaunchKernelGGL((k_sur_gate_net<R>), dim3(blocks), dim3(256), 0, s, a, w, Y);
     return hipGetLastError();
 }
 
@@ -1792,12 +1841,6 @@ hipError_t launch_cfl_finalize_blocks(const double *block_min, int n, double cfl
     return hipGetLastError();
 }
 
-hipError_t launch_cfl_finalize(unsigned long long *acc, double cfl, double *dt, double *t, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cfl_finalize, dim3(1), dim3(1), 0, s, acc, cfl, dt, t);
-    return hipGetLastError();
-}
-
 hipError_t launch_acc_reset(unsigned long long *acc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_acc_reset, dim3(1), dim3(1), 0, s, acc);
@@ -1839,7 +1882,7 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
 #define CP_INSTANTIATE(R)                                                                                   \
     template hipError_t launch_stage<R>(const StageArgs<R> &, int, int, int, hipStream_t);                   \
     template hipError_t launch_cfl<R>(const CflArgs<R> &, hipStream_t);                                      \
-    template hipError_t launch_sur_gate<R>(const SurArgs<R> &, long, hipStream_t);                           \
+    template hipError_t launch_sur_gate_net<R>(const SurArgs<R> &, const FusedNet &, float *, long, hipStream_t); \
     template hipError_t launch_sur_finish<R>(const SurArgs<R> &, const SourceParams &, int *,                 \
                                              unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
