@@ -150,6 +150,49 @@ def test_surrogate_source_closure(B, trained):
     s.close()
 
 
+def test_gate_and_network_over_many_workgroup_chunks(B, trained):
+    """The gate-and-network launch strides its workgroups over 64-cell chunks of the
+    active list; with more active cells than the resident workgroups take in one round,
+    each workgroup gates and evaluates several chunks.  The source is a function of the
+    cell alone, so a mesh made of k copies of a source-active state gives, cell for cell
+    and bit for bit, the source of the single copy -- the exact one and the learned one
+    (a network row depends only on its own features, wherever it sits in a tile)."""
+    net, norm, _ = trained
+    norm = _open_norm(norm)
+    s, U = _state(B, 2, 300)
+    dt = s.cfl_dt(U)
+    nr, nx = 48, 96
+    Qx = s.source(U, dt).cpu().numpy().reshape(15, nr, nx)
+    s.sur_set(net, norm.pack())
+    s.set_qmode(B.CP_Q_SURROGATE)
+    d0 = s.diag(U)
+    Qs = s.source(U, dt).cpu().numpy().reshape(15, nr, nx)
+    d1 = s.diag(U)
+    n_net = int(d1["surrogate_cells"] - d0["surrogate_cells"])
+    n_fb = int(d1["fallback_cells"] - d0["fallback_cells"])
+    active = int(np.any(Qx != 0, axis=0).sum())
+    assert n_net > 0 and active > 0
+    k = -(-40000 // (n_net + n_fb))      # > 32768 listed cells: 512 resident workgroups x 64
+    m, c = inputs.sa1(2)
+    mb = dict(m)
+    mb["nx"] = nx * k
+    big = B.Solver(mb, c, B.CP_FP64)
+    Ub = torch.from_numpy(np.ascontiguousarray(np.tile(U.cpu().numpy().reshape(15, nr, nx), (1, 1, k)))).cuda()
+    print("many chunks: %d copies, %d listed cells, %d network rows" % (k, k * (n_net + n_fb), k * n_net), flush=True)
+    Qbx = big.source(Ub, dt).cpu().numpy().reshape(15, nr, nx * k)
+    assert np.array_equal(Qbx, np.tile(Qx, (1, 1, k)))
+    big.sur_set(net, norm.pack())
+    big.set_qmode(B.CP_Q_SURROGATE)
+    e0 = big.diag(Ub)
+    Qb = big.source(Ub, dt).cpu().numpy().reshape(15, nr, nx * k)
+    e1 = big.diag(Ub)
+    assert e1["surrogate_cells"] - e0["surrogate_cells"] == k * n_net
+    assert e1["fallback_cells"] - e0["fallback_cells"] == k * n_fb
+    assert np.array_equal(Qb, np.tile(Qs, (1, 1, k)))
+    big.close()
+    s.close()
+
+
 def _test_norm(norm):
     """The trust bounds of the in-loop tests: 0.5 in feature space, 0.05 for the
     crystal moments (a sweep on this jet: 0.2 / 0.01 accept no cell; 1 / 0.2 break
