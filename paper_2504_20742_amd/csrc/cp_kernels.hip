@@ -580,15 +580,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         if (prev_live) __syncthreads();
         int nz = 0;
         if (inner) {
-            for (int e = tid; e < NE; e += NT) {
+            // as in phase 1: every load of the thread's cells is issued before the first
+            // is used
+            constexpr int NP = (NE + NT - 1) / NT;
+            R ub[NP][5];
+            #pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int e = min(tid + q * NT, NE - 1);   // a spare lane reloads the last cell
                 const unsigned code = (unsigned)((j0 + e / EX - 2) * nx + i0 + e % EX - 2);
+                #pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    if (k < ng && (cg & (1u << k))) ub[q][k] = ld_plane(a.Uin, a.plane, s0 + k, code);
+            }
+            #pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int e = tid + q * NT;
+                if (e >= NE) continue;
                 const R rho = t.rho[e], ir = inv_rho(rho);
                 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
                     if (k >= ng || !(cg & (1u << k))) continue;
-                    const R u = ld_plane(a.Uin, a.plane, s0 + k, code);
-                    nz |= (u != R(0)) << k;
-                    scalar_slot(t, k)[e] = per_mass(u, rho, ir);
+                    nz |= (ub[q][k] != R(0)) << k;
+                    scalar_slot(t, k)[e] = per_mass(ub[q][k], rho, ir);
                 }
             }
         } else {
