@@ -23,13 +23,13 @@ __device__ __forceinline__ float gelu_sig(float z)   // 1 / (1 + e^{-2u})
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 __device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
+
 // gfx950 v_mfma_f32_16x16x32_bf16 (lane layout checked on the device): A operand of
 // lane l holds row l % 16, k = 8 (l / 16) + i; B operand k = 8 (l / 16) + i, column
 // l % 16; the 4 results are rows 4 (l / 16) + i, column l % 16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ bf16x8 ld_bf16x8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
-
 
 // All three layers for a 64-row tile (n_in <= 32, n_h = 256, n_out <= 16).  Every
 // product is formed transposed, Z^T = W^T A^T: the packed weight fragment is the
