@@ -768,7 +768,10 @@ __global__ void __launch_bounds__(TX *TY) CP_STAGE_WAVES k_stage_batch(const Sta
     __shared__ Tile<R, TX, TY> t;
     const int w = xcd_band(blockIdx.x, nwork);
     const int p = work_plume[w], tb = work_tile[w];
-    const StageArgs<R> &a = args[p];
+    // the plume's arguments are read from the table once, at the start, into scalar
+    // registers as kernel arguments are (reading each field from the table where it is
+    // used made the batch's step 16 % slower)
+    const StageArgs<R> a = args[p];
     const int gx = (a.bc.nx + TX - 1) / TX;
     stage_tile<R, TX, TY>(a, (tb % gx) * TX, (tb / gx) * TY, t);
 }
@@ -925,7 +928,6 @@ template <class R> __global__ void __launch_bounds__(256) k_drift(DriftArgs<R> a
     if (bad) atomicOr(a.flag, 1);
 }
 
-// batched: blockIdx.y selects the plume
 // batched: blockIdx.y selects the plume; one wavefront per workgroup, and a
 // workgroup past the plume's listed cells leaves at once (as in k_source_fix)
 template <class R> __global__ void __launch_bounds__(64) k_source_fix_batch(const SourceFixArgs<R> *args)
