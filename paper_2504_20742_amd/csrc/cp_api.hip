@@ -59,7 +59,7 @@ struct cp_ctx {
     SourceParams sp{};
     int qmode = CP_Q_EXACT;
     int tx = 0, ty = 0;                             // 0: autotune on first use
-    hipGraphExec_t graph = nullptr, graph_k = nullptr;   // one step, kStepsPerGraph steps
+    hipGraphExec_t graph = nullptr, graph_m = nullptr, graph_k = nullptr;   // 1, kStepsMid, kStepsPerGraph steps
     void *graph_U = nullptr;
     double Y_amb = 0, u_amb = 0;
     std::string err;
@@ -67,14 +67,15 @@ struct cp_ctx {
 
 namespace {
 
-constexpr int kStepsPerGraph = 8;
+constexpr int kStepsPerGraph = 32, kStepsMid = 8;
 
 // Release the captured step graphs (after any change of what a step launches).
 void drop_graphs(cp_ctx *c)
 {
     if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->graph_m) hipGraphExecDestroy(c->graph_m);
     if (c->graph_k) hipGraphExecDestroy(c->graph_k);
-    c->graph = c->graph_k = nullptr;
+    c->graph = c->graph_m = c->graph_k = nullptr;
 }
 
 int fail(cp_ctx *c, int code, const std::string &msg)
@@ -844,17 +845,19 @@ int cp_step_n(cp_ctx *c, void *U, int n, double *t_host)
     if (r) return r;
     if (!c->graph || c->graph_U != U) {
         drop_graphs(c);
-        if ((r = capture_steps(c, U, 1, &c->graph))) return r;
-        if ((r = capture_steps(c, U, kStepsPerGraph, &c->graph_k))) {
+        if ((r = capture_steps(c, U, 1, &c->graph)) || (r = capture_steps(c, U, kStepsMid, &c->graph_m)) ||
+            (r = capture_steps(c, U, kStepsPerGraph, &c->graph_k))) {
             drop_graphs(c);
             return r;
         }
         c->graph_U = U;
     }
     HIPCHK(c, hipMemsetAsync(c->t_d, 0, sizeof(double), c->stream));
-    // whole groups of steps per replay (fewer graph boundaries), then single steps
+    // whole groups of steps per replay (fewer graph boundaries), then smaller groups and
+    // single steps
     for (int k = 0; k < n / kStepsPerGraph; ++k) HIPCHK(c, hipGraphLaunch(c->graph_k, c->stream));
-    for (int k = 0; k < n % kStepsPerGraph; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    for (int k = 0; k < n % kStepsPerGraph / kStepsMid; ++k) HIPCHK(c, hipGraphLaunch(c->graph_m, c->stream));
+    for (int k = 0; k < n % kStepsMid; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     double t = 0.0;
     HIPCHK(c, hipMemcpyAsync(&t, c->t_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if ((r = check_flag(c))) return r;
