@@ -1137,7 +1137,7 @@ struct cp_batch {
     unsigned long long *acc = nullptr;
     double *cfl = nullptr, *dt = nullptr, *t = nullptr;
     std::vector<void *> allocs;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr, graph_k = nullptr;   // one step, kStepsMid steps
     std::vector<void *> graph_U;
     std::string err;
 };
@@ -1348,6 +1348,7 @@ void cp_batch_destroy(cp_batch *b)
     if (b->stream) hipStreamSynchronize(b->stream);
     else hipDeviceSynchronize();
     if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->graph_k) hipGraphExecDestroy(b->graph_k);
     for (cp_ctx *c : b->plumes) cp_destroy(c);
     for (void *p : b->allocs)
         if (p) hipFree(p);
@@ -1370,32 +1371,37 @@ int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host)
     if (!b || !U || nsteps < 0) return CP_EINVAL;
     for (int p = 0; p < b->n; ++p)
         if (!U[p]) return bfail(b, CP_EINVAL, "null plume array");
-    const bool same = b->graph && b->graph_U.size() == (size_t)b->n &&
+    const bool same = b->graph && b->graph_k && b->graph_U.size() == (size_t)b->n &&
                       std::equal(b->graph_U.begin(), b->graph_U.end(), U);
     if (!same) {
-        if (b->graph) {
-            hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
-        }
+        if (b->graph) hipGraphExecDestroy(b->graph);
+        if (b->graph_k) hipGraphExecDestroy(b->graph_k);
+        b->graph = b->graph_k = nullptr;
+        b->graph_U.clear();
         int r = CP_OK;
         if (!b->tuned)
             r = b->precision == CP_FP64 ? batch_autotune<double>(b, U) : batch_autotune<float>(b, U);
         if (r) return r;
         r = b->precision == CP_FP64 ? batch_upload_args<double>(b, U) : batch_upload_args<float>(b, U);
         if (r) return r;
-        hipGraph_t g;
-        if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return bfail(b, CP_EHIP, "begin capture");
-        r = b->precision == CP_FP64 ? batch_enqueue_step<double>(b, b->cap_stream)
-                                    : batch_enqueue_step<float>(b, b->cap_stream);
-        hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
-        if (r) return r;
-        if (ec != hipSuccess) return bfail(b, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
-        if (hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(g);
-            return bfail(b, CP_EHIP, "graph instantiate");
+        // one step and kStepsMid steps per graph
+        for (int g = 0; g < 2 && !r; ++g) {
+            hipGraph_t gr;
+            if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bfail(b, CP_EHIP, "begin capture");
+            for (int k = 0; k < (g ? kStepsMid : 1) && !r; ++k)
+                r = b->precision == CP_FP64 ? batch_enqueue_step<double>(b, b->cap_stream)
+                                            : batch_enqueue_step<float>(b, b->cap_stream);
+            hipError_t ec = hipStreamEndCapture(b->cap_stream, &gr);
+            if (r) return r;
+            if (ec != hipSuccess) return bfail(b, CP_EHIP, std::string("capture: ") + hipGetErrorString(ec));
+            hipGraphExec_t *dst = g ? &b->graph_k : &b->graph;
+            if (hipGraphInstantiate(dst, gr, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphDestroy(gr);
+                return bfail(b, CP_EHIP, "graph instantiate");
+            }
+            hipGraphDestroy(gr);
         }
-        hipGraphDestroy(g);
         b->graph_U.assign(U, U + b->n);
     }
     if (hipMemsetAsync(b->t, 0, b->n * sizeof(double), b->stream) != hipSuccess) return bfail(b, CP_EHIP, "memset");
@@ -1405,7 +1411,9 @@ int cp_batch_step_n(cp_batch *b, void *const *U, int nsteps, double *t_host)
         int r = mask_seed(b->plumes[p], U[p], b->stream);
         if (r) return bfail(b, r, "plume " + std::to_string(p) + ": " + b->plumes[p]->err);
     }
-    for (int k = 0; k < nsteps; ++k)
+    for (int k = 0; k < nsteps / kStepsMid; ++k)
+        if (hipGraphLaunch(b->graph_k, b->stream) != hipSuccess) return bfail(b, CP_EHIP, "graph launch");
+    for (int k = 0; k < nsteps % kStepsMid; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return bfail(b, CP_EHIP, "graph launch");
     std::vector<double> t(b->n);
     if (hipMemcpyAsync(t.data(), b->t, b->n * sizeof(double), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
