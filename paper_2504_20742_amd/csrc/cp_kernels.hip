@@ -713,8 +713,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
                     if (slot < a.plane) a.active_list[slot] = (int)c;
                 }
             }
+            // a scalar that no input can hold on the tile's stencil (no candidate, clear in
+            // U^n's mask) has a zero output: +0, the value the arithmetic below gives, is
+            // stored without it
+            const unsigned zero_out = ~cand & (a.stage > 0 ? ~own_un : ~0u);
             #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                if (v >= 5 && ((zero_out >> v) & 1u)) {   // block-uniform
+                    st_plane(a.Uout, a.plane, v, (unsigned)c, R(0));
+                    continue;
+                }
                 const R L = res[v];
                 R out;
                 if (a.stage == 0) {
