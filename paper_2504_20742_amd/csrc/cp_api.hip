@@ -340,15 +340,18 @@ TileMask tile_mask(const cp_ctx *c, const void *Uin, const void *Uout, int stage
     m.ghost = c->ghost_bits;
     return m;
 }
-// Masks of the caller's state U (its contents may have changed since the last call).
+// Masks of the caller's state U (its contents may have changed since the last call),
+// and all-ones masks of the two stage buffers: a stage skips the store of a zero scalar
+// where its output buffer's mask says that the tile already holds zero, and the stage
+// buffers may have been written since under another tile shape or with the masks off.
 int mask_seed(cp_ctx *c, const void *U, hipStream_t s)
 {
     if (!masks_on(c)) return CP_OK;
     hipError_t e = c->precision == CP_FP64
                        ? launch_tile_mask<double>((const double *)U, c->plane, c->nx, c->nr, c->nv, c->tx, c->ty,
-                                                  c->tmask[0], s)
+                                                  c->tmask[0], c->tmask[1], c->tmask[2], s)
                        : launch_tile_mask<float>((const float *)U, c->plane, c->nx, c->nr, c->nv, c->tx, c->ty,
-                                                 c->tmask[0], s);
+                                                 c->tmask[0], c->tmask[1], c->tmask[2], s);
     if (e != hipSuccess) return fail(c, CP_EHIP, std::string("tile mask: ") + hipGetErrorString(e));
     return CP_OK;
 }

@@ -211,7 +211,7 @@ hipError_t launch_particle_times(const R *U, long plane, int nx, const double *i
                                  hipStream_t s);
 template <class R>
 hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
-                            hipStream_t s);
+                            unsigned *unknown_a, unsigned *unknown_b, hipStream_t s);
 template <class R>
 hipError_t launch_sur_features(const R *U, long plane, double dt, const SurNorm &nm, float *F, hipStream_t s);
 

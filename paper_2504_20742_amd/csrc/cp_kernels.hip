@@ -515,9 +515,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
     // ambient far field), whose scalars are in mask.ghost.  A scalar outside that set
     // is zero on the whole stencil, and is neither loaded nor transported.
     unsigned cand = ~0u, own_in = ~0u, own_un = ~0u;   // own_*: the tile's own words
+    // scalars the output buffer may hold non-zero on the tile now (its mask before this
+    // stage rewrites it at the end): a zero output of another scalar need not be stored
+    unsigned old_out = ~0u;
     if (a.mask.in) {
         const int ti = i0 / TX, tj = j0 / TY, gx = a.mask.gx, gy = a.mask.gy;
         own_in = __builtin_amdgcn_readfirstlane(a.mask.in[tj * gx + ti]);
+        if (a.mask.out) old_out = __builtin_amdgcn_readfirstlane(a.mask.out[tj * gx + ti]);
         if (a.mask.un) own_un = __builtin_amdgcn_readfirstlane(a.mask.un[tj * gx + ti]);
         cand = inner ? 0u : a.mask.ghost;
         #pragma unroll
@@ -715,12 +719,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
             }
             // a scalar that no input can hold on the tile's stencil (no candidate, clear in
             // U^n's mask) has a zero output: +0, the value the arithmetic below gives, is
-            // stored without it
+            // stored without it -- and not stored at all where the output buffer already
+            // holds zero on the whole tile
             const unsigned zero_out = ~cand & (a.stage > 0 ? ~own_un : ~0u);
             #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 if (v >= 5 && ((zero_out >> v) & 1u)) {   // block-uniform
-                    st_plane(a.Uout, a.plane, v, (unsigned)c, R(0));
+                    if ((old_out >> v) & 1u) st_plane(a.Uout, a.plane, v, (unsigned)c, R(0));
                     continue;
                 }
                 const R L = res[v];
@@ -1249,7 +1254,7 @@ __global__ void __launch_bounds__(256) k_particle_times(const R *U, long plane, 
 // Tile masks of a state (one workgroup per tile of the given shape).
 template <class R>
 __global__ void __launch_bounds__(256) k_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty,
-                                                   unsigned *mask)
+                                                   unsigned *mask, unsigned *unknown_a, unsigned *unknown_b)
 {
     __shared__ unsigned acc;
     const int gx = (nx + tx - 1) / tx;
@@ -1266,7 +1271,12 @@ __global__ void __launch_bounds__(256) k_tile_mask(const R *U, long plane, int n
     bits = wave_or(bits);
     if ((threadIdx.x & 63) == 0 && bits) atomicOr(&acc, bits);
     __syncthreads();
-    if (threadIdx.x == 0) mask[blockIdx.x] = acc;
+    if (threadIdx.x == 0) {
+        mask[blockIdx.x] = acc;
+        // the stage buffers: whatever they hold now is not known to be zero anywhere
+        if (unknown_a) unknown_a[blockIdx.x] = ~0u;
+        if (unknown_b) unknown_b[blockIdx.x] = ~0u;
+    }
 }
 
 // ------------------------------------------------------------------ CFL
@@ -1834,10 +1844,11 @@ hipError_t launch_particle_times(const R *U, long plane, int nx, const double *i
 
 template <class R>
 hipError_t launch_tile_mask(const R *U, long plane, int nx, int nr, int nv, int tx, int ty, unsigned *mask,
-                            hipStream_t s)
+                            unsigned *unknown_a, unsigned *unknown_b, hipStream_t s)
 {
     const int tiles = ((nx + tx - 1) / tx) * ((nr + ty - 1) / ty);
-    hipLaunchKernelGGL((k_tile_mask<R>), dim3(tiles), dim3(256), 0, s, U, plane, nx, nr, nv, tx, ty, mask);
+    hipLaunchKernelGGL((k_tile_mask<R>), dim3(tiles), dim3(256), 0, s, U, plane, nx, nr, nv, tx, ty, mask, unknown_a,
+                       unknown_b);
     return hipGetLastError();
 }
 
@@ -1909,7 +1920,8 @@ hipError_t launch_diag(const R *U, long plane, int nx, int nr, const double *vol
     template hipError_t launch_sur_finish<R>(const SurArgs<R> &, const SourceParams &, int *,                 \
                                              unsigned long long *, long, hipStream_t);                        \
     template hipError_t launch_active_list<R>(const R *, long, int *, int *, hipStream_t);                    \
-    template hipError_t launch_tile_mask<R>(const R *, long, int, int, int, int, int, unsigned *, hipStream_t); \
+    template hipError_t launch_tile_mask<R>(const R *, long, int, int, int, int, int, unsigned *, unsigned *,      \
+                                            unsigned *, hipStream_t);                                          \
     template hipError_t launch_particle_times<R>(const R *, long, int, const double *, double *, double *,      \
                                                  hipStream_t);                                                 \
     template hipError_t launch_sur_features<R>(const R *, long, double, const SurNorm &, float *, hipStream_t); \

@@ -100,3 +100,41 @@ def test_masks_bit_identical_two_populations(B):
     assert ta == tb
     assert torch.equal(Ua, Ub)
     assert float(Ua[15].abs().max()) > 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_masks_stage_buffers_written_without_masks(B, prec):
+    """A stage does not store a zero scalar where its output buffer's tile mask says the
+    tile already holds zero.  The two stage buffers outlive a call: here they are filled
+    with particles by a run with the masks off (their masks untouched) and under another
+    tile shape, then a clean state is stepped with the masks on.  No stale value may
+    reach the result."""
+    p = B.CP_FP64 if prec == "fp64" else B.CP_MIXED
+    m, c = inputs.config2(0)
+    UA = _seeded(B, m, c, p, False, seed=81)
+    s = B.Solver(m, c, p)
+    clean = s.init()
+    ref, tref, _ = _run(B, m, c, p, clean, 4, False)
+    print("masks: stage buffers reused across mask toggles and tile shapes, %s" % prec, flush=True)
+    s.set_tile(32, 8)
+    U = clean.clone()
+    s.step_n(U, 2)                 # masks on: the stage buffers' masks say zero scalars
+    s.set_tile_masks(False)
+    W = UA.clone()
+    s.step_n(W, 2)                 # particles in both stage buffers, their masks untouched
+    s.set_tile_masks(True)
+    U = clean.clone()
+    t = s.step_n(U, 4)
+    assert t == tref
+    assert torch.equal(U, ref)
+    # the same after a run under another tile shape
+    s.set_tile(16, 16)
+    W = UA.clone()
+    s.step_n(W, 2)
+    s.set_tile(32, 8)
+    U = clean.clone()
+    t = s.step_n(U, 4)
+    s.close()
+    assert t == tref
+    assert torch.equal(U, ref)
+    assert float(ref[5:13].abs().max()) == 0.0
