@@ -378,15 +378,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, int i0, int j0
         for (int q = 0; q < NP; ++q)
             if (tid + q * NT < NE) put_prims(tid + q * NT, Ub[q][0], Ub[q][1], Ub[q][2], Ub[q][3], Ub[q][4]);
     } else {
-        for (int e = tid; e < NE; e += NT) {
-            const int i = min(i0 + e % EX - 2, nx + 1), j = min(j0 + e / EX - 2, nr + 1);
-            const CellSrc cs = map_cell(i, j, bc);
-            R U1 = fetch(a.Uin, a.plane, bc, cs.code, 1), U2 = fetch(a.Uin, a.plane, bc, cs.code, 2);
-            if (cs.fu) U1 = -U1;
-            if (cs.fv) U2 = -U2;
-            put_prims(e, fetch(a.Uin, a.plane, bc, cs.code, 0), U1, U2, fetch(a.Uin, a.plane, bc, cs.code, 3),
-                      fetch(a.Uin, a.plane, bc, cs.code, 4));
+        // boundary tile: the sources of all the thread's cells (ghost cells mapped to
+        // their mirror, copy or boundary state), then all their loads, then the primitives
+        constexpr int NP = (NE + NT - 1) / NT;
+        CellSrc cs[NP];
+        R Ub[NP][5];
+        #pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int e = tid + q * NT;
+            cs[q] = CellSrc{0, false, false};
+            if (e < NE) cs[q] = map_cell(min(i0 + e % EX - 2, nx + 1), min(j0 + e / EX - 2, nr + 1), bc);
         }
+        #pragma unroll
+        for (int q = 0; q < NP; ++q)
+            if (tid + q * NT < NE) {
+                #pragma unroll
+                for (int v = 0; v < 5; ++v) Ub[q][v] = fetch(a.Uin, a.plane, bc, cs[q].code, v);
+            }
+        #pragma unroll
+        for (int q = 0; q < NP; ++q)
+            if (tid + q * NT < NE)
+                put_prims(tid + q * NT, Ub[q][0], cs[q].fu ? -Ub[q][1] : Ub[q][1], cs[q].fv ? -Ub[q][2] : Ub[q][2],
+                          Ub[q][3], Ub[q][4]);
     }
     __syncthreads();
     // phase 2 (tile + ring): molecular viscosity, vapour diffusivity, eddy viscosity
@@ -1302,20 +1315,6 @@ __device__ __forceinline__ PrimD cfl_prim_of(double U0, double U1, double U2, do
     return w;
 }
 
-template <class R>
-__device__ __forceinline__ PrimD cfl_prim(const R *U, long plane, const BcInfo &bc, int i, int j)
-{
-    const CellSrc cs = map_cell(i, j, bc);
-    const double U0 = (double)fetch(U, plane, bc, cs.code, 0);
-    double U1 = (double)fetch(U, plane, bc, cs.code, 1);
-    double U2 = (double)fetch(U, plane, bc, cs.code, 2);
-    const double U3 = (double)fetch(U, plane, bc, cs.code, 3);
-    const double U4 = (double)fetch(U, plane, bc, cs.code, 4);
-    if (cs.fu) U1 = -U1;
-    if (cs.fv) U2 = -U2;
-    return cfl_prim_of(U0, U1, U2, U3, U4);
-}
-
 // Time-step limit of cell (i, j) from its primitives and the neighbour velocities
 // that enter the eddy viscosity.
 template <class R>
@@ -1388,19 +1387,6 @@ __device__ __forceinline__ PrimF cfl_prim_f32_of(float U0, float U1, float U2, f
     return w;
 }
 
-__device__ __forceinline__ PrimF cfl_prim_f32(const float *U, long plane, const BcInfo &bc, int i, int j)
-{
-    const CellSrc cs = map_cell(i, j, bc);
-    const float U0 = fetch(U, plane, bc, cs.code, 0);
-    float U1 = fetch(U, plane, bc, cs.code, 1);
-    float U2 = fetch(U, plane, bc, cs.code, 2);
-    const float U3 = fetch(U, plane, bc, cs.code, 3);
-    const float U4 = fetch(U, plane, bc, cs.code, 4);
-    if (cs.fu) U1 = -U1;
-    if (cs.fv) U2 = -U2;
-    return cfl_prim_f32_of(U0, U1, U2, U3, U4);
-}
-
 __device__ __forceinline__ float cfl_limit_f32(const CflArgs<float> &a, int i, int j, const PrimF &w, float uN,
                                                float uS, float vE, float vW)
 {
@@ -1459,14 +1445,37 @@ template <int BX, int BY, int RPT> __device__ __forceinline__ void cfl_tile_f32_
             }
         }
     } else {
-        for (int e = threadIdx.x; e < NEC; e += BX * BY) {
-            const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
-            const PrimF w = cfl_prim_f32(a.U, a.plane, bc, i, j);
-            pr[0][e] = w.rho;
-            pr[1][e] = w.u;
-            pr[2][e] = w.v;
-            pr[3][e] = w.T;
-            pr[4][e] = w.Y;
+        // boundary tile: the sources of all the thread's ring cells first, then all their
+        // loads, so that one round trip to memory serves them all
+        constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
+        CellSrc cs[IT];
+        float q[IT][5];
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            cs[it] = CellSrc{0, false, false};
+            if (e < NEC) cs[it] = map_cell(min(i0 + e % EXC - 1, bc.nx), min(j0 + e / EXC - 1, bc.nr), bc);
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) q[it][k] = fetch(a.U, a.plane, bc, cs[it].code, k);
+            }
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                const PrimF w = cfl_prim_f32_of(q[it][0], cs[it].fu ? -q[it][1] : q[it][1],
+                                                cs[it].fv ? -q[it][2] : q[it][2], q[it][3], q[it][4]);
+                pr[0][e] = w.rho;
+                pr[1][e] = w.u;
+                pr[2][e] = w.v;
+                pr[3][e] = w.T;
+                pr[4][e] = w.Y;
+            }
         }
     }
     __syncthreads();
@@ -1531,14 +1540,39 @@ __device__ __forceinline__ void cfl_tile_body(const CflArgs<R> &a, int bxi, int 
             }
         }
     } else {
-        for (int e = threadIdx.x; e < NEC; e += BX * BY) {
-            const int i = min(i0 + e % EXC - 1, bc.nx), j = min(j0 + e / EXC - 1, bc.nr);
-            const PrimD w = cfl_prim(a.U, a.plane, bc, i, j);
-            pr[0][e] = w.rho;
-            pr[1][e] = w.u;
-            pr[2][e] = w.v;
-            pr[3][e] = w.T;
-            pr[4][e] = w.Y;
+        // boundary tile: the sources of all the thread's ring cells first, then all their
+        // loads, so that one round trip to memory serves them all
+        constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
+        CellSrc cs[IT];
+        R q[IT][5];
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            cs[it] = CellSrc{0, false, false};
+            if (e < NEC) cs[it] = map_cell(min(i0 + e % EXC - 1, bc.nx), min(j0 + e / EXC - 1, bc.nr), bc);
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                #pragma unroll
+                for (int k = 0; k < 5; ++k) q[it][k] = fetch(a.U, a.plane, bc, cs[it].code, k);
+            }
+        }
+        #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e < NEC) {
+                double U1 = (double)q[it][1], U2 = (double)q[it][2];
+                if (cs[it].fu) U1 = -U1;
+                if (cs[it].fv) U2 = -U2;
+                const PrimD w = cfl_prim_of((double)q[it][0], U1, U2, (double)q[it][3], (double)q[it][4]);
+                pr[0][e] = w.rho;
+                pr[1][e] = w.u;
+                pr[2][e] = w.v;
+                pr[3][e] = w.T;
+                pr[4][e] = w.Y;
+            }
         }
     }
     __syncthreads();
