@@ -242,11 +242,13 @@ int cp_nvar(const cp_ctx *ctx);
 int cp_set_tile(cp_ctx *ctx, int tx, int ty);
 
 /* Per-tile masks of the non-zero passive scalars (on by default): the stage kernel
- * loads and transports only the scalars that can be non-zero on a tile's stencil
- * and skips the RK loads of planes that are zero on the whole tile; the results are
- * the same bit for bit with and without them (a scalar outside a tile's mask is
- * zero on its whole stencil).  on = 0 turns them off, for comparison.  The drift
- * pass (cp_set_drift) runs without them.  CP_EINVAL for a null context.           */
+ * loads and transports only the scalars that can be non-zero on a tile's stencil,
+ * skips the RK loads of planes that are zero on the whole tile, and does not store
+ * a zero scalar where the output buffer already holds zero on the tile.  The
+ * results are the same with and without them, bit for bit up to the sign of a zero
+ * (a scalar outside a tile's mask is zero on its whole stencil).  on = 0 turns them
+ * off, for comparison.  The drift pass (cp_set_drift) runs without them.
+ * CP_EINVAL for a null context.                                                    */
 int cp_set_tile_masks(cp_ctx *ctx, int on);
 int cp_get_tile(const cp_ctx *ctx, int *tx, int *ty);
 
