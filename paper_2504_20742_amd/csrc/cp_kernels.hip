@@ -1627,8 +1627,18 @@ __global__ void k_cfl_finalize_batch(unsigned long long *acc, const double *cfl,
 __global__ void __launch_bounds__(256) k_cfl_finalize_blocks(const double *bm, int n, double cfl, double *dt, double *t)
 {
 #pragma clang fp contract(off)
+    // eight loads per thread in flight at once (the minimum does not depend on the order)
     double m = __builtin_huge_val();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmin(m, bm[k]);
+    for (int k0 = threadIdx.x; k0 < n; k0 += 8 * blockDim.x) {
+        double v[8];
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * (int)blockDim.x;
+            v[u] = k < n ? bm[k] : __builtin_huge_val();
+        }
+        #pragma unroll
+        for (int u = 0; u < 8; ++u) m = fmin(m, v[u]);
+    }
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
     __shared__ double part[4];
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
