@@ -1445,8 +1445,8 @@ template <int BX, int BY, int RPT> __device__ __forceinline__ void cfl_tile_f32_
             }
         }
     } else {
-        // boundary tile: the sources of all the thread's ring cells first, then all their
-        // loads, so that one round trip to memory serves them all
+        // boundary tile: the sources of all the thread's cells (tile and ring, ghost cells
+        // mapped) first, then all their loads, so that one round trip serves them all
         constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
         CellSrc cs[IT];
         float q[IT][5];
@@ -1540,8 +1540,8 @@ __device__ __forceinline__ void cfl_tile_body(const CflArgs<R> &a, int bxi, int 
             }
         }
     } else {
-        // boundary tile: the sources of all the thread's ring cells first, then all their
-        // loads, so that one round trip to memory serves them all
+        // boundary tile: the sources of all the thread's cells (tile and ring, ghost cells
+        // mapped) first, then all their loads, so that one round trip serves them all
         constexpr int NT = BX * BY, IT = (NEC + NT - 1) / NT;
         CellSrc cs[IT];
         R q[IT][5];
