@@ -68,3 +68,26 @@ def test_batch_config4_full_runs(B):
     t = bt.step_n(Us, 5)
     assert all(x > 0 for x in t)
     assert all(bool(torch.isfinite(u).all()) for u in Us)
+
+
+def test_batch_reused_on_a_new_state(B):
+    """The batch's stage buffers keep the previous call's passive scalars; a stage skips
+    the store of a zero scalar only where a buffer's tile mask shows zero, so the initial
+    state stepped again must come out as from a fresh batch."""
+    cases = _small_batch(4)
+    ms, cs = [m for m, _ in cases], [c for _, c in cases]
+    bt = B.Batch(ms, cs, B.CP_MIXED)
+    Ua = bt.init()
+    U0 = [U.clone() for U in Ua]
+    bt.step_n(Ua, 60)                       # the scalars move (and the source may act)
+    assert any(not torch.equal(U[5:15], V[5:15]) for U, V in zip(Ua, U0))
+    Ub = bt.init()
+    tb = bt.step_n(Ub, 9)                   # one eight-step replay and one single step
+    bt.close()
+    fresh = B.Batch(ms, cs, B.CP_MIXED)
+    Uf = fresh.init()
+    tf = fresh.step_n(Uf, 9)
+    fresh.close()
+    for p in range(len(cases)):
+        assert tb[p] == tf[p]
+        assert torch.equal(Ub[p], Uf[p]), p
