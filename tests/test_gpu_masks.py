@@ -106,35 +106,39 @@ def test_masks_bit_identical_two_populations(B):
 def test_masks_stage_buffers_written_without_masks(B, prec):
     """A stage does not store a zero scalar where its output buffer's tile mask says the
     tile already holds zero.  The two stage buffers outlive a call: here they are filled
-    with particles by a run with the masks off (their masks untouched) and under another
-    tile shape, then a clean state is stepped with the masks on.  No stale value may
-    reach the result."""
+    with particles everywhere by a run with the masks off (their masks untouched) and by
+    a run under another tile shape; then a state whose particles fill only the left half
+    of the mesh is stepped with the masks on.  Tiles right of that edge become
+    candidates as the particles move, and read their own cells and halos: a value left
+    over in a stage buffer would show in the result."""
     p = B.CP_FP64 if prec == "fp64" else B.CP_MIXED
     m, c = inputs.config2(0)
     UA = _seeded(B, m, c, p, False, seed=81)
-    s = B.Solver(m, c, p)
-    clean = s.init()
-    ref, tref, _ = _run(B, m, c, p, clean, 4, False)
+    UB = _seeded(B, m, c, p, False, seed=82)
+    UB[5:13, :, m["nx"] // 2:] = 0
+    ref, tref, _ = _run(B, m, c, p, UB, 6, False)
     print("masks: stage buffers reused across mask toggles and tile shapes, %s" % prec, flush=True)
+    s = B.Solver(m, c, p)
     s.set_tile(32, 8)
-    U = clean.clone()
-    s.step_n(U, 2)                 # masks on: the stage buffers' masks say zero scalars
+    U = UB.clone()
+    s.step_n(U, 2)                 # masks on: the stage buffers' masks cover the left half
     s.set_tile_masks(False)
     W = UA.clone()
-    s.step_n(W, 2)                 # particles in both stage buffers, their masks untouched
+    s.step_n(W, 2)                 # particles everywhere in both stage buffers, masks untouched
     s.set_tile_masks(True)
-    U = clean.clone()
-    t = s.step_n(U, 4)
+    U = UB.clone()
+    t = s.step_n(U, 6)
     assert t == tref
     assert torch.equal(U, ref)
-    # the same after a run under another tile shape
+    # the same after a run under another tile shape (masks of 16 x 16 tiles)
     s.set_tile(16, 16)
     W = UA.clone()
     s.step_n(W, 2)
     s.set_tile(32, 8)
-    U = clean.clone()
-    t = s.step_n(U, 4)
+    U = UB.clone()
+    t = s.step_n(U, 6)
     s.close()
     assert t == tref
     assert torch.equal(U, ref)
-    assert float(ref[5:13].abs().max()) == 0.0
+    # the particles crossed into tiles whose masks were clear at the start
+    assert float(ref[5:13, :, m["nx"] // 2:].abs().max()) > 0.0
